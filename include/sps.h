@@ -1,0 +1,201 @@
+/*
+ * sps.h -- C ABI of libsps, the MI355X (gfx950) hot path of the sequential
+ * posterior simulator (SPS) for multinomial logit models of Geweke, Durham &
+ * Xu, "Bayesian Inference for Logistic Regression Models using Sequential
+ * Posterior Simulation" (2013).
+ *
+ * Conventions for every entry point
+ * ---------------------------------
+ *  - Status: 0 (SPS_OK) on success, a negative SPS_ERR_* code on failure, with
+ *    a message available from sps_last_error().  No exception or abort crosses
+ *    the ABI.  Arguments are validated before anything is launched; on an
+ *    argument error no output is touched.
+ *  - Memory: pointers documented "device" are HIP device memory owned by the
+ *    caller (contiguous, row-major, of the stated type); pointers documented
+ *    "host" are host memory.  The library keeps no pointer to caller memory
+ *    after a call returns, except the data and prior it copies.
+ *  - Asynchrony: work is enqueued on the context's stream.  A call returns
+ *    before the GPU finishes unless it has a host output; calls with host
+ *    outputs synchronise the stream before returning.
+ *  - Model layout: X is T x k covariates (FP64), y holds T outcomes in
+ *    [0, C), outcome 0 is the base outcome whose coefficients are fixed at 0
+ *    (the normalisation theta_c = 0 of Section 2.1).  A particle is the
+ *    vector of d = k (C - 1) free coefficients; entry (c - 1) k + i is the
+ *    coefficient of covariate i for outcome c.  theta is P x d FP64.
+ *  - Particles form J groups of N (Section 2.2): particle p = j N + n.
+ *  - Observation s (1-based, as the paper counts) is row s - 1 of X.  An
+ *    observation range [t0, t1) means rows t0..t1-1.
+ *  - Random numbers: every entry point that draws takes explicit variates
+ *    (z, u, u53) or, when they are NULL, draws them from Philox4x32-10 with
+ *    key = seed and counter = (element index, stream).
+ *  - One context per host thread; a context holds no global state, and two
+ *    contexts may be used concurrently on different streams.
+ */
+#ifndef SPS_H
+#define SPS_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    SPS_OK = 0,
+    SPS_ERR_ARG = -1,        /* invalid argument or unsupported shape          */
+    SPS_ERR_HIP = -2,        /* a HIP runtime call failed                       */
+    SPS_ERR_NOT_PD = -3,     /* particle sample variance not positive definite */
+    SPS_ERR_NONFINITE = -4,  /* NaN or +inf in a log-likelihood or log-weight   */
+    SPS_ERR_DEGENERATE = -5, /* every weight of a group is zero                */
+    SPS_ERR_NOMEM = -6,      /* device allocation failed                        */
+    SPS_ERR_STATE = -7       /* data or prior not set                           */
+};
+
+/* Arithmetic of the likelihood kernels. */
+enum {
+    SPS_FP64 = 0,   /* FP64 MFMA contraction, FP64 log-sum-exp and sums           */
+    SPS_FP32 = 1,   /* FP32 MFMA contraction, FP32 log-sum-exp, FP64 running sums */
+    SPS_BF16X3 = 2  /* BF16 hi/lo split of both operands, three BF16 MFMAs with
+                       FP32 accumulation; FP32 log-sum-exp; FP64 running sums  */
+};
+enum { SPS_RESIDUAL = 0, SPS_MULTINOMIAL = 1 }; /* S phase schemes            */
+enum { SPS_RW = 0, SPS_MALA = 1 };              /* M phase proposals          */
+
+typedef struct sps_ctx sps_ctx;
+
+/* ---------------------------------------------------------------- context */
+
+/* Create a context on HIP device `device` enqueuing on `hip_stream`
+ * (a hipStream_t; NULL = the null stream).  *out receives the context. */
+int sps_create(sps_ctx** out, int device, void* hip_stream);
+
+/* Release the context and every device buffer it owns.  NULL is a no-op. */
+void sps_destroy(sps_ctx* ctx);
+
+/* Message of the last failing call on ctx ("" if none).  The string is owned
+ * by ctx and valid until the next call on it. */
+const char* sps_last_error(const sps_ctx* ctx);
+
+/* Replace the stream that subsequent calls enqueue on. */
+int sps_set_stream(sps_ctx* ctx, void* hip_stream);
+
+/* Copy the data set into the context and build the kernel copies of X
+ * (FP32, BF16 hi/lo, FP64, each padded and with the binary sign folding
+ * described in the design notes).  X: device, T x k FP64; y: device, T int32
+ * in [0, C).  Requires 1 <= T < 2^31, 1 <= k <= 128, 2 <= C <= 8.
+ * Checks y on the device: SPS_ERR_ARG if any y is outside [0, C).
+ * Synchronises the stream. */
+int sps_set_data(sps_ctx* ctx, const double* X, const int32_t* y, int64_t T,
+                 int32_t k, int32_t C);
+
+/* Prior of the free parameters: independent N(mean_i, sd_i^2), i < d, the
+ * diagonal case of eq. (prior_Gauss).  mean, sd: host, d FP64 each, sd > 0.
+ * Requires sps_set_data first (d is taken from it). */
+int sps_set_prior(sps_ctx* ctx, const double* mean, const double* sd);
+
+/* ------------------------------------------------------- random numbers */
+
+/* Philox4x32-10 variates of a stream (the same definitions as used inside
+ * the phases).  out: device.  kind 0: `count` 53-bit integers (uint64),
+ * kind 1: `count` uniforms (U + 1/2) 2^-53 (FP64), kind 2: a count x d array
+ * of standard normals by Box-Muller (FP64). */
+int sps_random(sps_ctx* ctx, int kind, uint64_t seed, uint64_t stream,
+               int64_t count, int32_t d, void* out);
+
+/* Algorithm 1 step 1: theta (device, P x d) <- iid draws from the prior. */
+int sps_init_prior(sps_ctx* ctx, double* theta, int64_t P, uint64_t seed,
+                   uint64_t stream);
+
+/* -------------------------------------------------------- likelihood */
+
+/* ll[p] = sum over observations t0 <= t < t1 of log P(Y_t = y_t | x_t,
+ * theta_p), eq. (plogit) summed over the product form of the likelihood
+ * (Section 2.1).  theta: device P x d FP64; ll: device P FP64.
+ * prec: SPS_FP64, SPS_FP32 or SPS_BF16X3.  0 <= t0 <= t1 <= T.  Results are
+ * deterministic (fixed-order reductions, no float atomics). */
+int sps_loglik(sps_ctx* ctx, const double* theta, int64_t P, int64_t t0,
+               int64_t t1, int prec, double* ll);
+
+/* As sps_loglik, plus grad (device, P x d FP64): the gradient of ll[p] with
+ * respect to theta_p, sum_t x_t (1{y_t = c} - pi_{t,c}) for outcome c
+ * (the adjoint of the likelihood; an extension beyond the paper). */
+int sps_loglik_grad(sps_ctx* ctx, const double* theta, int64_t P, int64_t t0,
+                    int64_t t1, int prec, double* ll, double* grad);
+
+/* ------------------------------------------------------------ phases */
+
+/* C phase of cycle l (Algorithm 1 step 2(a), eq. (C_phase_compute)) with the
+ * adaptive stopping rule of Algorithm 2 step 1 (eq. (ESS_rule)): starting at
+ * w = 1 after observation s0, multiply in p(y_s | theta) for s = s0+1, ...
+ * and stop at the first s with ESS(s) < ess_frac J N (ESS pooled over all
+ * J N particles) or s = T.  Outputs: log_w (device, P FP64) = log w(t_end);
+ * ll (device, P FP64, in/out) += log_w; *t_end, *ess_end (host) = t_l and
+ * ESS(t_l).  0 <= s0 < T, 0 < ess_frac < 1.  Synchronises. */
+int sps_correct(sps_ctx* ctx, const double* theta, double* ll, int32_t J,
+                int32_t N, int64_t s0, double ess_frac, int prec,
+                double* log_w, int64_t* t_end, double* ess_end);
+
+/* Log marginal likelihood by-product (Section 3; estimator reading in the
+ * design notes): logml_j (device, J FP64, in/out) += log(N^-1 sum_n
+ * exp(log_w[j N + n])).  If logml or nse (host) is non-NULL the call
+ * synchronises and returns the combined estimate log(J^-1 sum_j
+ * exp(logml_j)) and its delta-method NSE.  SPS_ERR_DEGENERATE if a group has
+ * every log_w = -inf. */
+int sps_logml(sps_ctx* ctx, const double* log_w, int32_t J, int32_t N,
+              double* logml_j, double* logml, double* nse);
+
+/* S phase (Algorithm 1 step 2(b)), independently in each group, on exact
+ * integer weights W_n = floor(exp(log_w_n - max_n log_w) 2^40).
+ * scheme: SPS_RESIDUAL (copies floor(N W_n / S), then the remainder drawn
+ * multinomially on the residual weights, appended in draw order) or
+ * SPS_MULTINOMIAL.  u53: device J x N uint64 in [0, 2^53) or NULL (Philox
+ * from seed, stream).  ancestor: device P int32, global index j N + a.
+ * The gathers dst[p] = src[ancestor[p]] are done for each non-NULL pair
+ * (theta P x d, ll P, grad P x d); a destination must not alias its source.
+ * N <= 4096. */
+int sps_resample(sps_ctx* ctx, const double* log_w, int32_t J, int32_t N,
+                 int scheme, const uint64_t* u53, uint64_t seed, uint64_t stream,
+                 int32_t* ancestor, const double* theta_in, double* theta_out,
+                 const double* ll_in, double* ll_out, const double* grad_in,
+                 double* grad_out);
+
+/* The S phase on given integer weights W (device, J x N uint64, each group's
+ * total in (0, 2^52)); the bit-exactness entry point of sps_resample. */
+int sps_resample_int(sps_ctx* ctx, const uint64_t* W, int32_t J, int32_t N,
+                     int scheme, const uint64_t* u53, int32_t* ancestor);
+
+/* M phase, one Metropolis step for every particle (Algorithm 2 step 2(c)):
+ * V = sample variance of all J N particles (divisor P - 1), L = chol(V),
+ * proposal covariance h V.
+ *   kind SPS_RW  : theta' = theta + sqrt(h) L z                     (paper)
+ *   kind SPS_MALA: theta' = theta + (h/2) V grad log pi(theta) + sqrt(h) L z
+ *                  with the Hastings correction                 (extension)
+ * log pi = log-likelihood over observations [0, t) + log prior.
+ * theta (device P x d), ll (device P: log-likelihood over [0, t) of theta)
+ * and, for MALA, grad (device P x d: its gradient) are updated in place for
+ * accepted particles; accept iff log u < log alpha.  z: device P x d
+ * normals, u: device P uniforms in (0, 1), or NULL for Philox draws from
+ * (seed, stream) and (seed, stream + 1).  *accept_rate (host, may be NULL to
+ * stay asynchronous) = accepted / P.  SPS_ERR_NOT_PD if V is not positive
+ * definite (the failure of Section 4.2); then nothing is modified.
+ * The log-likelihood of the proposal uses precision prec. */
+int sps_mutate(sps_ctx* ctx, double* theta, double* ll, double* grad, int32_t J,
+               int32_t N, int64_t t, double h, int kind, int prec, const double* z,
+               const double* u, uint64_t seed, uint64_t stream, double* accept_rate);
+
+/* ------------------------------------------------ accuracy measures */
+
+/* Monitored functions of each particle: g (device, P x m FP64, m = d + C - 1)
+ * = (theta_1..theta_d, theta_c' xbar for c = 1..C-1), xbar the mean of the
+ * rows of X (the log-odds at the sample mean reported in Tables 2 and 5). */
+int sps_monitor(sps_ctx* ctx, const double* theta, int64_t P, double* g);
+
+/* Eqs. (partial_g)-(RNE_def) for each of m functions: g device P x m FP64;
+ * mean, sd, nse, rne: host, m FP64 each (any may be NULL).
+ * NSE = sqrt(v_hat / (J N)).  Synchronises. */
+int sps_moments(sps_ctx* ctx, const double* g, int32_t J, int32_t N, int32_t m,
+                double* mean, double* sd, double* nse, double* rne);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPS_H */

@@ -1,0 +1,158 @@
+// loglik.hip -- launch logic of the likelihood kernels and the sps_loglik /
+// sps_loglik_grad entry points.
+#include <algorithm>
+
+#include "loglik_kernel.h"
+
+namespace sps {
+
+__global__ void loglik_reduce_kernel(const double* __restrict__ part_ll,
+                                     const double* __restrict__ part_g, int64_t P, int32_t d,
+                                     int32_t nsplit, double* __restrict__ ll,
+                                     double* __restrict__ grad) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < P) {
+        double s = 0.0;
+        for (int q = 0; q < nsplit; ++q) s += part_ll[(int64_t)q * P + i];
+        ll[i] = s;
+    }
+    if (grad != nullptr && i < P * d) {
+        double s = 0.0;
+        for (int q = 0; q < nsplit; ++q) s += part_g[(int64_t)q * P * d + i];
+        grad[i] = s;
+    }
+}
+
+__global__ void fill_kernel(double* __restrict__ p, int64_t n, double v) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+int fill(sps_ctx* c, double* p, int64_t n, double v) {
+    if (n <= 0) return SPS_OK;
+    fill_kernel<<<(unsigned)((n + 255) / 256), 256, 0, c->stream>>>(p, n, v);
+    return launched(c, "fill_kernel");
+}
+
+static LoglikEntry lookup(int prec, int nc, int ks, int mode) {
+    switch (prec) {
+        case SPS_FP64: return lookup_fp64(nc, ks, mode);
+        case SPS_FP32: return lookup_fp32(nc, ks, mode);
+        case SPS_BF16X3: return lookup_bf16(nc, ks, mode);
+        default: return LoglikEntry{};
+    }
+}
+
+// Common launcher.  grad != nullptr -> forward + adjoint.  perobs != nullptr ->
+// per-observation terms written to perobs[(t - t0) * P + p] (forward only).
+static int run_loglik(sps_ctx* c, const double* theta, int64_t P, int64_t t0, int64_t t1,
+                      int prec, double* ll, double* grad, double* perobs) {
+    const int mode = grad ? MODE_GRAD : MODE_FWD;
+    const int ks = (prec == SPS_BF16X3) ? c->kb / 32 : c->kp / 4;
+    LoglikEntry e = lookup(prec, c->C - 1, ks, mode);
+    if (!e.fn) return fail(c, SPS_ERR_ARG, "no likelihood kernel for C=%d k=%d prec=%d", c->C, c->k, prec);
+    if (P == 0) return SPS_OK;
+    if (t1 == t0) {
+        if (ll) SPS_CHECK(fill(c, ll, P, 0.0));
+        if (grad) SPS_CHECK(fill(c, grad, P * c->d, 0.0));
+        return SPS_OK;
+    }
+    LoglikArgs a{};
+    switch (prec) {
+        case SPS_FP64: a.X = c->Xd; a.XT = c->XTd; a.ldx = c->kp; break;
+        case SPS_FP32: a.X = c->Xf; a.XT = c->XTf; a.ldx = c->kp; break;
+        default: a.X = c->Xh; a.Xlo = c->Xl; a.XT = c->XTh; a.XTlo = c->XTl; a.ldx = c->kb; break;
+    }
+    a.y8 = c->y8;
+    a.theta = theta;
+    a.P = P;
+    a.Tp = c->Tp;
+    a.t0 = t0;
+    a.t1 = t1;
+    a.t0a = t0 & ~int64_t(kObsStep - 1);
+    a.k = c->k;
+    a.d = c->d;
+    a.binary = c->C == 2;
+    a.nsteps = (int32_t)((t1 - a.t0a + kObsStep - 1) / kObsStep);
+    const int64_t npt = (P + e.ppb - 1) / e.ppb;
+    // Observation splits: enough blocks to fill 256 CUs several times over,
+    // at least 4 steps of work per wave, bounded partial-gradient storage.
+    const int64_t target_blocks = 2048;
+    int64_t nsplit = std::max<int64_t>(1, (target_blocks + npt - 1) / npt);
+    nsplit = std::min<int64_t>(nsplit, std::max<int64_t>(1, a.nsteps / 4));
+    if (grad) {
+        const int64_t cap = std::max<int64_t>(1, (int64_t(512) << 20) / (P * c->d * 8));
+        nsplit = std::min(nsplit, cap);
+    }
+    a.steps_per_split = (int32_t)((a.nsteps + nsplit - 1) / nsplit);
+    nsplit = (a.nsteps + a.steps_per_split - 1) / a.steps_per_split;
+    a.nsplit = (int32_t)nsplit;
+    if (nsplit == 1 && ll) {
+        a.out_ll = ll;
+        a.out_g = grad;
+    } else {
+        SPS_CHECK(ensure(c, c->part_ll, sizeof(double) * nsplit * P, "partial log-likelihoods"));
+        a.out_ll = (double*)c->part_ll.p;
+        if (grad) {
+            SPS_CHECK(ensure(c, c->part_g, sizeof(double) * nsplit * P * c->d, "partial gradients"));
+            a.out_g = (double*)c->part_g.p;
+        }
+    }
+    a.perobs = perobs;
+    dim3 grid((unsigned)(npt * nsplit));
+    hipError_t err = e.fn(a, grid, c->stream);
+    if (err != hipSuccess) return hip_fail(c, err, "loglik_kernel launch");
+    if (ll && a.out_ll != ll) {
+        const int64_t n = grad ? P * c->d : P;
+        loglik_reduce_kernel<<<(unsigned)((n + 255) / 256), 256, 0, c->stream>>>(
+            (const double*)c->part_ll.p, grad ? (const double*)c->part_g.p : nullptr, P, c->d,
+            a.nsplit, ll, grad);
+        SPS_CHECK(launched(c, "loglik_reduce_kernel"));
+    }
+    return SPS_OK;
+}
+
+static int check_loglik_args(sps_ctx* c, const char* who, const double* theta, int64_t P,
+                             int64_t t0, int64_t t1, int prec) {
+    if (!c->has_data) return fail(c, SPS_ERR_STATE, "%s: call sps_set_data first", who);
+    if (!theta && P > 0) return fail(c, SPS_ERR_ARG, "%s: null theta", who);
+    if (P < 0 || P > (int64_t(1) << 31)) return fail(c, SPS_ERR_ARG, "%s: P=%lld out of range", who, (long long)P);
+    if (t0 < 0 || t1 < t0 || t1 > c->T)
+        return fail(c, SPS_ERR_ARG, "%s: observation range [%lld, %lld) outside [0, %lld]", who,
+                    (long long)t0, (long long)t1, (long long)c->T);
+    if (prec != SPS_FP64 && prec != SPS_FP32 && prec != SPS_BF16X3)
+        return fail(c, SPS_ERR_ARG, "%s: unknown precision %d", who, prec);
+    return SPS_OK;
+}
+
+int loglik_launch(sps_ctx* c, const double* theta, int64_t P, int64_t t0, int64_t t1, int prec,
+                  double* ll, double* grad) {
+    return run_loglik(c, theta, P, t0, t1, prec, ll, grad, nullptr);
+}
+
+int loglik_perobs(sps_ctx* c, const double* theta, int64_t P, int64_t t0, int64_t t1, int prec,
+                  double* perobs) {
+    return run_loglik(c, theta, P, t0, t1, prec, nullptr, nullptr, perobs);
+}
+
+}  // namespace sps
+
+using namespace sps;
+
+extern "C" int sps_loglik(sps_ctx* c, const double* theta, int64_t P, int64_t t0, int64_t t1,
+                          int prec, double* ll) {
+    if (!c) return SPS_ERR_ARG;
+    c->err.clear();
+    SPS_CHECK(check_loglik_args(c, "sps_loglik", theta, P, t0, t1, prec));
+    if (!ll && P > 0) return fail(c, SPS_ERR_ARG, "sps_loglik: null ll");
+    return run_loglik(c, theta, P, t0, t1, prec, ll, nullptr, nullptr);
+}
+
+extern "C" int sps_loglik_grad(sps_ctx* c, const double* theta, int64_t P, int64_t t0, int64_t t1,
+                               int prec, double* ll, double* grad) {
+    if (!c) return SPS_ERR_ARG;
+    c->err.clear();
+    SPS_CHECK(check_loglik_args(c, "sps_loglik_grad", theta, P, t0, t1, prec));
+    if ((!ll || !grad) && P > 0) return fail(c, SPS_ERR_ARG, "sps_loglik_grad: null ll or grad");
+    return run_loglik(c, theta, P, t0, t1, prec, ll, grad, nullptr);
+}

@@ -1,0 +1,35 @@
+// loglik_bf16.hip -- instantiations of the likelihood kernel for SPS_BF16X3.
+#include "loglik_kernel.h"
+
+namespace sps {
+
+LoglikEntry lookup_bf16(int nc, int ks, int mode) {
+#define SPS_E(NC, KS) \
+    if (nc == NC && ks == KS) return mode == MODE_GRAD ? loglik_entry<SPS_BF16X3, NC, KS, MODE_GRAD>() \
+                                                      : loglik_entry<SPS_BF16X3, NC, KS, MODE_FWD>();
+    SPS_E(1, 1)
+    SPS_E(1, 2)
+    SPS_E(1, 4)
+    SPS_E(2, 1)
+    SPS_E(2, 2)
+    SPS_E(2, 4)
+    SPS_E(3, 1)
+    SPS_E(3, 2)
+    SPS_E(3, 4)
+    SPS_E(4, 1)
+    SPS_E(4, 2)
+    SPS_E(4, 4)
+    SPS_E(5, 1)
+    SPS_E(5, 2)
+    SPS_E(5, 4)
+    SPS_E(6, 1)
+    SPS_E(6, 2)
+    SPS_E(6, 4)
+    SPS_E(7, 1)
+    SPS_E(7, 2)
+    SPS_E(7, 4)
+#undef SPS_E
+    return LoglikEntry{};
+}
+
+}  // namespace sps

@@ -1,0 +1,484 @@
+// loglik_kernel.h -- the per-particle multinomial-logit log-likelihood and its
+// adjoint on gfx950 matrix cores.
+//
+// What is computed (eq. (plogit), normalised by theta_0 = 0, summed over the
+// product form of the likelihood): for particle p and observation t,
+//     eta_{p,t,c} = x_t' theta_{p,c}   (c = 1..C-1),  eta_{p,t,0} = 0,
+//     l_{p,t}     = eta_{p,t,y_t} - log sum_c exp(eta_{p,t,c}),
+//     LL_p        = sum_{t0 <= t < t1} l_{p,t},
+// and optionally G_{p,c} = sum_t x_t (1{y_t = c} - pi_{p,t,c}).
+//
+// Work decomposition.  A wave owns PW blocks of 16 particles and walks its
+// share of the observations in steps of 32 rows.  The contraction eta = X B
+// runs on MFMA with observations as rows and particles as columns, so the
+// C-1 predictors of one (observation, particle) land in the same lane (one
+// MFMA chain per outcome) and the log-sum-exp and the sum over observations
+// need no lane exchange until the end.  theta is read once per wave and kept
+// in registers as the B operand for the whole observation loop; X streams
+// through L2 (it is re-read once per particle tile, never per particle).
+//
+// MFMA shapes (gfx950 lane layouts, measured with an in-bounds probe):
+//   f32  16x16x4 : A lane l -> (row l%16, kslot l/16); B -> (kslot l/16, col l%16)
+//   f64  16x16x4 : same A/B layout, FP64
+//   bf16 16x16x32: A lane l -> (row l%16, kslots 8(l/16)..+7); B likewise
+//   D of f32 and bf16: lane l holds rows 4(l/16)+i, i = 0..3, of column l%16;
+//   D of f64         : lane l holds rows (l/16)+4i, i = 0..3, of column l%16.
+// The contraction index may be assigned to (step, kslot) in any order as long
+// as A and B agree; lane group g = l/16 takes a contiguous run of covariates,
+// so each lane's A fragment is one contiguous piece of an X row.
+//
+// Row order inside a 32-row step: in MFMA tile h (0, 1) the D row that lane
+// group g holds as value i covers observation o + 8g + 4h + i (the A-operand
+// rows are permuted accordingly, which differs between the f64 and the other
+// D layouts).  Lane group g then holds observations o + 8g .. o + 8g + 7 across
+// the two tiles, which is exactly the contiguous K fragment the adjoint MFMA
+// (X^T R) needs in its B operand.
+//
+// Precision modes: FP64 (parity anchor), FP32, and BF16x3 where each operand
+// is split into hi + lo BF16 parts and eta ~ Xh Bh + Xh Bl + Xl Bh with FP32
+// accumulation.  In the FP32/BF16 modes theta is pre-scaled by log2(e) so the
+// log-sum-exp runs on the hardware base-2 exp/log; partial sums per 32-row
+// step are carried into FP64 per lane.
+#pragma once
+
+#include <type_traits>
+
+#include "sps_internal.h"
+
+namespace sps {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+
+constexpr double kLog2e = 1.4426950408889634074;
+constexpr double kLn2 = 0.69314718055994530942;
+
+enum { MODE_FWD = 0, MODE_GRAD = 1 };
+
+struct LoglikArgs {
+    const void* X;      // row-major kernel copy of X (FP64 / FP32 / BF16 hi)
+    const void* Xlo;    // BF16 lo part (BF16X3 only)
+    const void* XT;     // transposed copy (kp x Tp) for the adjoint
+    const void* XTlo;   // BF16 lo part of the transposed copy
+    const int8_t* y8;   // outcomes as bytes
+    const double* theta;
+    double* out_ll;     // nsplit == 1: final ll[P]; else partials [nsplit][P]
+    double* out_g;      // nsplit == 1: final grad[P][d]; else partials [nsplit][P][d]
+    double* perobs;     // optional: per-observation terms [(t - t0) * P + p]
+    int64_t P;
+    int64_t Tp;
+    int64_t t0, t1, t0a;  // t0a = t0 rounded down to a multiple of 32
+    int32_t k, d, ldx;    // covariates, parameters, row stride of X
+    int32_t nsteps, steps_per_split, nsplit;
+    int32_t binary;       // C == 2: rows of X are sign-folded
+};
+
+__device__ __forceinline__ f32x4 mfma(float a, float b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f64x4 mfma(double a, double b, f64x4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// Round-to-nearest-even FP32 -> BF16 bits.
+__device__ __forceinline__ unsigned short to_bf16(float f) {
+    unsigned u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ float from_bf16(unsigned short h) {
+    return __uint_as_float(((unsigned)h) << 16);
+}
+
+__device__ __forceinline__ float fexp2(float x) { return __builtin_amdgcn_exp2f(x); }
+__device__ __forceinline__ float flog2(float x) { return __builtin_amdgcn_logf(x); }
+__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// Precision traits.
+template <int PREC> struct Prec;
+template <> struct Prec<SPS_FP64> {
+    using E = double;   // epilogue arithmetic
+    using Acc = f64x4;
+    static constexpr int KPS = 4;    // contraction length per MFMA
+};
+template <> struct Prec<SPS_FP32> {
+    using E = float;
+    using Acc = f32x4;
+    static constexpr int KPS = 4;
+};
+template <> struct Prec<SPS_BF16X3> {
+    using E = float;
+    using Acc = f32x4;
+    static constexpr int KPS = 32;
+};
+
+// Particle blocks per wave, chosen so the register arrays stay moderate.
+template <int PREC, int NC, int KS, int MODE>
+constexpr int pick_pw() {
+    constexpr int breg = (PREC == SPS_BF16X3) ? 8 * KS : (PREC == SPS_FP64 ? 2 * KS : KS);
+    constexpr int accr = (PREC == SPS_FP64) ? 16 : 8;  // two tiles x 4 values
+    constexpr int kbt = (PREC == SPS_BF16X3) ? 2 * KS : KS / 4;  // 16-row k blocks
+    constexpr int grad = (MODE == MODE_GRAD) ? ((PREC == SPS_FP64 ? 8 : 4) * kbt + 8) : 0;
+    constexpr int per = NC * (breg + accr + grad) + 2;
+    return per * 4 <= 160 ? 4 : (per * 2 <= 200 ? 2 : 1);
+}
+
+template <int PREC, int NC, int KS, int MODE>
+__global__ __launch_bounds__(256) void loglik_kernel(LoglikArgs a) {
+    using P_ = Prec<PREC>;
+    using E = typename P_::E;
+    using Acc = typename P_::Acc;
+    constexpr bool BF = (PREC == SPS_BF16X3);
+    constexpr int PW = pick_pw<PREC, NC, KS, MODE>();
+    constexpr int KBT = BF ? 2 * KS : KS / 4;  // adjoint k blocks of 16 (kp / 16)
+    constexpr bool GRAD = (MODE == MODE_GRAD);
+    // G accumulators of the FP32 paths are folded into a second FP32 set every
+    // kFold steps (two-level summation); FP64 accumulates directly.
+    constexpr int kFold = 16;
+
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int g = lane >> 4;
+    const int r16 = lane & 15;
+    const int split = blockIdx.x % a.nsplit;
+    const int64_t ptile = blockIdx.x / a.nsplit;
+    const int64_t pbase = (ptile * 4 + wave) * (16 * PW);
+    if (pbase >= a.P) return;  // whole wave beyond the last particle
+    const E scale = (PREC == SPS_FP64) ? E(1) : E(kLog2e);
+
+    // ---- B operand: theta of this wave's particles, kept in registers ----
+    // f32/f64: step s, lane group g covers covariate g*KS + s.
+    // bf16   : step s, lane group g covers covariates g*8*KS + 8 s + j.
+    using BReg = typename std::conditional<BF, bf16x8, E>::type;
+    BReg bh[PW][NC][KS];
+    BReg bl[BF ? PW : 1][BF ? NC : 1][BF ? KS : 1];
+#pragma unroll
+    for (int b = 0; b < PW; ++b) {
+        const int64_t p = pbase + b * 16 + r16;
+        const bool pv = p < a.P;
+        const double* th = a.theta + (pv ? p : 0) * a.d;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+#pragma unroll
+            for (int s = 0; s < KS; ++s) {
+                if constexpr (BF) {
+                    u16x8 hv, lv;
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) {
+                        const int kk = g * 8 * KS + 8 * s + j;
+                        const float v = (pv && kk < a.k) ? (float)(th[c * a.k + kk] * kLog2e) : 0.f;
+                        // split of the FP64 product: hi from the FP32 value, lo from the rest
+                        const double vd = (pv && kk < a.k) ? th[c * a.k + kk] * kLog2e : 0.0;
+                        const unsigned short h = to_bf16(v);
+                        hv[j] = h;
+                        lv[j] = to_bf16((float)(vd - (double)from_bf16(h)));
+                    }
+                    bh[b][c][s] = __builtin_bit_cast(bf16x8, hv);
+                    bl[b][c][s] = __builtin_bit_cast(bf16x8, lv);
+                } else {
+                    const int kk = g * KS + s;
+                    bh[b][c][s] = (pv && kk < a.k) ? (E)(th[c * a.k + kk] * (double)scale) : E(0);
+                }
+            }
+        }
+    }
+
+    // ---- accumulators ----
+    double acc64[PW];
+#pragma unroll
+    for (int b = 0; b < PW; ++b) acc64[b] = 0.0;
+    Acc gacc[GRAD ? PW : 1][GRAD ? NC : 1][GRAD ? KBT : 1];
+    Acc gsum[GRAD && !(PREC == SPS_FP64) ? PW : 1][GRAD && !(PREC == SPS_FP64) ? NC : 1]
+            [GRAD && !(PREC == SPS_FP64) ? KBT : 1];
+    if constexpr (GRAD) {
+#pragma unroll
+        for (int b = 0; b < PW; ++b)
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+#pragma unroll
+                for (int q = 0; q < KBT; ++q) {
+                    gacc[b][c][q] = Acc{0, 0, 0, 0};
+                    if constexpr (PREC != SPS_FP64) gsum[b][c][q] = Acc{0, 0, 0, 0};
+                }
+    }
+
+    const int st_begin = split * a.steps_per_split;
+    const int st_end = min(a.nsteps, st_begin + a.steps_per_split);
+    // A-operand row of this lane inside a 32-row step (tile h adds 4h): the
+    // D row r = 4g+i (f32/bf16) or r = g+4i (f64) must map to o + 8g + i.
+    const int arow = (PREC == SPS_FP64) ? 8 * (r16 & 3) + (r16 >> 2) : 8 * (r16 >> 2) + (r16 & 3);
+
+    for (int st = st_begin; st < st_end; ++st) {
+        const int64_t o = a.t0a + (int64_t)st * 32;
+
+        // ---- forward contraction: two 16-row tiles ----
+        Acc acc[2][PW][NC];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int64_t row = o + arow + 4 * h;
+            if constexpr (BF) {
+                const unsigned short* xh = (const unsigned short*)a.X + row * a.ldx + g * 8 * KS;
+                const unsigned short* xl = (const unsigned short*)a.Xlo + row * a.ldx + g * 8 * KS;
+                bf16x8 ah[KS], al[KS];
+#pragma unroll
+                for (int s = 0; s < KS; ++s) {
+                    ah[s] = __builtin_bit_cast(bf16x8, *(const u16x8*)(xh + 8 * s));
+                    al[s] = __builtin_bit_cast(bf16x8, *(const u16x8*)(xl + 8 * s));
+                }
+#pragma unroll
+                for (int b = 0; b < PW; ++b)
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) {
+                        Acc t = Acc{0, 0, 0, 0};
+#pragma unroll
+                        for (int s = 0; s < KS; ++s) {
+                            t = mfma(ah[s], bh[b][c][s], t);
+                            t = mfma(ah[s], bl[b][c][s], t);
+                            t = mfma(al[s], bh[b][c][s], t);
+                        }
+                        acc[h][b][c] = t;
+                    }
+            } else {
+                const E* xr = (const E*)a.X + row * a.ldx + g * KS;
+                E av[KS];
+#pragma unroll
+                for (int s = 0; s < KS; ++s) av[s] = xr[s];
+#pragma unroll
+                for (int b = 0; b < PW; ++b)
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) {
+                        Acc t = Acc{0, 0, 0, 0};
+#pragma unroll
+                        for (int s = 0; s < KS; ++s) t = mfma(av[s], bh[b][c][s], t);
+                        acc[h][b][c] = t;
+                    }
+            }
+        }
+
+        // ---- epilogue: per-observation log-probabilities ----
+        const bool full = (o >= a.t0) && (o + 32 <= a.t1);
+        unsigned ylo = 0, yhi = 0;
+        if (NC > 1) {
+            const uint2 yy = *(const uint2*)(a.y8 + o + 8 * g);
+            ylo = yy.x;
+            yhi = yy.y;
+        }
+        E rres[GRAD ? 2 : 1][GRAD ? 4 : 1][GRAD ? PW : 1][GRAD ? NC : 1];
+        E tsum[PW];
+#pragma unroll
+        for (int b = 0; b < PW; ++b) tsum[b] = E(0);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int64_t obs = o + 8 * g + 4 * h + i;
+                const bool ov = full || (obs >= a.t0 && obs < a.t1);
+                const int yt = NC > 1 ? (int)(((h ? yhi : ylo) >> (8 * i)) & 0xFFu) : 0;
+#pragma unroll
+                for (int b = 0; b < PW; ++b) {
+                    E lp;
+                    if constexpr (NC == 1) {
+                        // Binary with sign folding: l = -softplus(z), z = x~' theta.
+                        const E z = acc[h][b][0][i];
+                        E e, q, sp;
+                        if constexpr (PREC == SPS_FP64) {
+                            e = exp(-fabs(z));
+                            q = 1.0 + e;
+                            sp = fmax(z, 0.0) + log1p(e);
+                        } else {
+                            e = fexp2(-fabsf(z));
+                            q = 1.f + e;
+                            sp = fmaxf(z, 0.f) + flog2(q);
+                        }
+                        lp = -sp;
+                        if constexpr (GRAD) {
+                            // d l / d z = -sigmoid(z)
+                            E sig;
+                            if constexpr (PREC == SPS_FP64) sig = (z > 0.0 ? 1.0 : e) / q;
+                            else sig = (z > 0.f ? 1.f : e) * frcp(q);
+                            rres[h][i][b][0] = ov ? -sig : E(0);
+                        }
+                    } else {
+                        E m = E(0);
+#pragma unroll
+                        for (int c = 0; c < NC; ++c) m = acc[h][b][c][i] > m ? acc[h][b][c][i] : m;
+                        E ec[NC];
+                        E s;
+                        E ey = E(0);
+                        if constexpr (PREC == SPS_FP64) {
+                            s = exp(-m);
+#pragma unroll
+                            for (int c = 0; c < NC; ++c) {
+                                ec[c] = exp(acc[h][b][c][i] - m);
+                                s += ec[c];
+                                ey = (yt == c + 1) ? acc[h][b][c][i] : ey;
+                            }
+                            lp = ey - (m + log(s));
+                        } else {
+                            s = fexp2(-m);
+#pragma unroll
+                            for (int c = 0; c < NC; ++c) {
+                                ec[c] = fexp2(acc[h][b][c][i] - m);
+                                s += ec[c];
+                                ey = (yt == c + 1) ? acc[h][b][c][i] : ey;
+                            }
+                            lp = ey - (m + flog2(s));
+                        }
+                        if constexpr (GRAD) {
+                            E inv;
+                            if constexpr (PREC == SPS_FP64) inv = 1.0 / s;
+                            else inv = frcp(s);
+#pragma unroll
+                            for (int c = 0; c < NC; ++c)
+                                rres[h][i][b][c] = ov ? ((yt == c + 1 ? E(1) : E(0)) - ec[c] * inv) : E(0);
+                        }
+                    }
+                    tsum[b] += ov ? lp : E(0);
+                    if (a.perobs != nullptr && ov) {
+                        const int64_t p = pbase + b * 16 + r16;
+                        if (p < a.P)
+                            a.perobs[(obs - a.t0) * a.P + p] =
+                                (PREC == SPS_FP64) ? (double)lp : (double)lp * kLn2;
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < PW; ++b) acc64[b] += (double)tsum[b];
+
+        // ---- adjoint: G += X~^T R over the 32 rows of this step ----
+        if constexpr (GRAD) {
+#pragma unroll
+            for (int q = 0; q < KBT; ++q) {
+                const int64_t xrow = (int64_t)(q * 16 + r16) * a.Tp + o + 8 * g;
+                if constexpr (BF) {
+                    const bf16x8 th8 = __builtin_bit_cast(bf16x8, *(const u16x8*)((const unsigned short*)a.XT + xrow));
+                    const bf16x8 tl8 = __builtin_bit_cast(bf16x8, *(const u16x8*)((const unsigned short*)a.XTlo + xrow));
+#pragma unroll
+                    for (int b = 0; b < PW; ++b)
+#pragma unroll
+                        for (int c = 0; c < NC; ++c) {
+                            u16x8 rh, rl;
+#pragma unroll
+                            for (int j = 0; j < 8; ++j) {
+                                const float v = rres[j >> 2][j & 3][b][c];
+                                const unsigned short hb = to_bf16(v);
+                                rh[j] = hb;
+                                rl[j] = to_bf16(v - from_bf16(hb));
+                            }
+                            const bf16x8 Rh = __builtin_bit_cast(bf16x8, rh);
+                            const bf16x8 Rl = __builtin_bit_cast(bf16x8, rl);
+                            Acc t = gacc[b][c][q];
+                            t = mfma(th8, Rh, t);
+                            t = mfma(th8, Rl, t);
+                            t = mfma(tl8, Rh, t);
+                            gacc[b][c][q] = t;
+                        }
+                } else {
+                    const E* xt = (const E*)a.XT + xrow;
+                    E xv[8];
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) xv[j] = xt[j];
+#pragma unroll
+                    for (int b = 0; b < PW; ++b)
+#pragma unroll
+                        for (int c = 0; c < NC; ++c) {
+                            Acc t = gacc[b][c][q];
+#pragma unroll
+                            for (int j = 0; j < 8; ++j) t = mfma(xv[j], rres[j >> 2][j & 3][b][c], t);
+                            gacc[b][c][q] = t;
+                        }
+                }
+            }
+            if constexpr (PREC != SPS_FP64) {
+                if (((st - st_begin) % kFold) == kFold - 1) {
+#pragma unroll
+                    for (int b = 0; b < PW; ++b)
+#pragma unroll
+                        for (int c = 0; c < NC; ++c)
+#pragma unroll
+                            for (int q = 0; q < KBT; ++q) {
+                                gsum[b][c][q] += gacc[b][c][q];
+                                gacc[b][c][q] = Acc{0, 0, 0, 0};
+                            }
+                }
+            }
+        }
+    }
+
+    // ---- write out ----
+    const double lscale = (PREC == SPS_FP64) ? 1.0 : kLn2;
+    double* ll_out = a.out_ll + (int64_t)split * a.P;
+#pragma unroll
+    for (int b = 0; b < PW; ++b) {
+        double v = acc64[b];
+        v += __shfl_xor(v, 16, 64);
+        v += __shfl_xor(v, 32, 64);
+        const int64_t p = pbase + b * 16 + r16;
+        if (g == 0 && p < a.P) ll_out[p] = v * lscale;
+    }
+    if constexpr (GRAD) {
+        double* g_out = a.out_g + (int64_t)split * a.P * a.d;
+#pragma unroll
+        for (int b = 0; b < PW; ++b) {
+            const int64_t p = pbase + b * 16 + r16;
+            if (p >= a.P) continue;
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+#pragma unroll
+                for (int q = 0; q < KBT; ++q) {
+                    Acc t = gacc[b][c][q];
+                    if constexpr (PREC != SPS_FP64) t += gsum[b][c][q];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int kk = q * 16 + ((PREC == SPS_FP64) ? g + 4 * i : 4 * g + i);
+                        if (kk < a.k) g_out[p * a.d + c * a.k + kk] = (double)t[i];
+                    }
+                }
+        }
+    }
+}
+
+// Fixed-order sum of the observation-split partials.
+__global__ void loglik_reduce_kernel(const double* __restrict__ part_ll,
+                                     const double* __restrict__ part_g, int64_t P, int32_t d,
+                                     int32_t nsplit, double* __restrict__ ll,
+                                     double* __restrict__ grad);
+
+// Host-side launcher for one (PREC, NC, KS, MODE) instantiation.
+template <int PREC, int NC, int KS, int MODE>
+hipError_t launch_loglik(const LoglikArgs& a, dim3 grid, hipStream_t s) {
+    hipLaunchKernelGGL((loglik_kernel<PREC, NC, KS, MODE>), grid, dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+template <int PREC, int NC, int KS, int MODE>
+constexpr int particles_per_block() {
+    return 4 * 16 * pick_pw<PREC, NC, KS, MODE>();
+}
+
+typedef hipError_t (*LoglikLaunchFn)(const LoglikArgs&, dim3, hipStream_t);
+struct LoglikEntry {
+    LoglikLaunchFn fn = nullptr;
+    int ppb = 0;  // particles per 256-thread block
+};
+
+template <int PREC, int NC, int KS, int MODE>
+LoglikEntry loglik_entry() {
+    LoglikEntry e;
+    e.fn = &launch_loglik<PREC, NC, KS, MODE>;
+    e.ppb = particles_per_block<PREC, NC, KS, MODE>();
+    return e;
+}
+
+// One lookup per precision, each defined in its own translation unit.
+LoglikEntry lookup_fp64(int nc, int ks, int mode);
+LoglikEntry lookup_fp32(int nc, int ks, int mode);
+LoglikEntry lookup_bf16(int nc, int ks, int mode);
+
+}  // namespace sps

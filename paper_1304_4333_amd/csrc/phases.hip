@@ -1,0 +1,646 @@
+// phases.hip -- random numbers, prior draws, the C phase with the ESS rule,
+// the S phase on exact integer weights, the log marginal likelihood
+// increments and the NSE/RNE reductions of libsps.
+#include <algorithm>
+#include <cmath>
+
+#include "philox.h"
+#include "sps_internal.h"
+
+namespace sps {
+
+// ------------------------------------------------------------------ block reductions
+// 256-thread block sum / max in FP64 with a fixed tree order (deterministic).
+__device__ double block_sum256(double v, double* red) {
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    double r = red[0];
+    __syncthreads();
+    return r;
+}
+__device__ double block_max256(double v, double* red) {
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    double r = red[0];
+    __syncthreads();
+    return r;
+}
+
+// ------------------------------------------------------------------ random numbers
+__global__ void random_kernel(int kind, uint64_t seed, uint64_t stream, int64_t count, int32_t d,
+                              void* out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (kind == 2) {
+        if (i >= count * d) return;
+        ((double*)out)[i] = philox_normal(seed, stream, i / d, (int32_t)(i % d), d);
+        return;
+    }
+    if (i >= count) return;
+    uint64_t a, b;
+    philox_u53x2(seed, stream, (uint64_t)i, a, b);
+    if (kind == 0) ((uint64_t*)out)[i] = a;
+    else ((double*)out)[i] = u53_to_uniform(a);
+}
+
+int random_fill(sps_ctx* c, int kind, uint64_t seed, uint64_t stream, int64_t count, int32_t d,
+                void* out) {
+    const int64_t n = kind == 2 ? count * d : count;
+    if (n <= 0) return SPS_OK;
+    random_kernel<<<(unsigned)((n + 255) / 256), 256, 0, c->stream>>>(kind, seed, stream, count, d, out);
+    return launched(c, "random_kernel");
+}
+
+__global__ void init_prior_kernel(double* __restrict__ theta, int64_t P, int32_t d,
+                                  const double* __restrict__ mean, const double* __restrict__ isd,
+                                  uint64_t seed, uint64_t stream) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= P * d) return;
+    const int32_t i = (int32_t)(e % d);
+    theta[e] = mean[i] + philox_normal(seed, stream, e / d, i, d) / isd[i];
+}
+
+// ------------------------------------------------------------------ C phase
+// Running log-weights over a block of observations: lw[u][p] holds the
+// per-observation term on entry and log w_p(s + u + 1) on exit.
+__global__ void correct_prefix_kernel(double* __restrict__ lw, const double* __restrict__ carry,
+                                      int64_t P, int32_t nb) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    double acc = carry[p];
+    for (int32_t u = 0; u < nb; ++u) {
+        acc += lw[(int64_t)u * P + p];
+        lw[(int64_t)u * P + p] = acc;
+    }
+}
+
+// ESS(u) = (sum_p w)^2 / sum_p w^2 with w = exp(lw - max_p lw), one block per
+// observation u.  flags |= 1 if a log-weight is NaN or +inf.
+__global__ void correct_ess_kernel(const double* __restrict__ lw, int64_t P, double* __restrict__ ess,
+                                   unsigned* flags) {
+    __shared__ double red[256];
+    const double* col = lw + (int64_t)blockIdx.x * P;
+    double m = -INFINITY;
+    bool bad = false;
+    for (int64_t p = threadIdx.x; p < P; p += 256) {
+        const double v = col[p];
+        bad |= isnan(v) || v == INFINITY;
+        m = fmax(m, v);
+    }
+    if (bad) atomicOr(flags, 1u);
+    m = block_max256(m, red);
+    double s1 = 0.0, s2 = 0.0;
+    if (m > -INFINITY) {
+        for (int64_t p = threadIdx.x; p < P; p += 256) {
+            const double w = exp(col[p] - m);
+            s1 += w;
+            s2 += w * w;
+        }
+    }
+    s1 = block_sum256(s1, red);
+    s2 = block_sum256(s2, red);
+    if (threadIdx.x == 0) ess[blockIdx.x] = (m > -INFINITY) ? s1 * s1 / s2 : 0.0;
+}
+
+// First u in [0, nb) with ESS(u) < thr, or the last observation of the data.
+// out[0] = index (-1 if none), out[1] = ESS there.
+__global__ void correct_find_kernel(const double* __restrict__ ess, int32_t nb, double thr,
+                                    int64_t s, int64_t T, double* out) {
+    if (threadIdx.x != 0) return;
+    double idx = -1.0, val = 0.0;
+    for (int32_t u = 0; u < nb; ++u) {
+        if (ess[u] < thr || s + u + 1 == T) {
+            idx = (double)u;
+            val = ess[u];
+            break;
+        }
+    }
+    out[0] = idx;
+    out[1] = val;
+}
+
+__global__ void correct_final_kernel(const double* __restrict__ lwcol, double* __restrict__ log_w,
+                                     double* __restrict__ ll, int64_t P) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    const double v = lwcol[p];
+    log_w[p] = v;
+    ll[p] += v;
+}
+
+__global__ void copy_kernel(const double* __restrict__ src, double* __restrict__ dst, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[i];
+}
+
+// ------------------------------------------------------------------ logML
+// logml_j += log(N^-1 sum_n exp(log_w_jn)); flags |= 1 if a group is all -inf,
+// |= 2 if a log-weight is NaN or +inf.  One block per group.
+__global__ void logml_group_kernel(const double* __restrict__ log_w, int32_t N,
+                                   double* __restrict__ logml_j, unsigned* flags) {
+    __shared__ double red[256];
+    const double* lw = log_w + (int64_t)blockIdx.x * N;
+    double m = -INFINITY;
+    bool bad = false;
+    for (int32_t n = threadIdx.x; n < N; n += 256) {
+        bad |= isnan(lw[n]) || lw[n] == INFINITY;
+        m = fmax(m, lw[n]);
+    }
+    if (bad) atomicOr(flags, 2u);
+    m = block_max256(m, red);
+    double s = 0.0;
+    if (m > -INFINITY)
+        for (int32_t n = threadIdx.x; n < N; n += 256) s += exp(lw[n] - m);
+    s = block_sum256(s, red);
+    if (threadIdx.x == 0) {
+        if (m > -INFINITY && !bad) logml_j[blockIdx.x] += m + log(s) - log((double)N);
+        else if (!(m > -INFINITY)) atomicOr(flags, 1u);
+    }
+}
+
+// logml = log(J^-1 sum_j exp(logml_j)); nse = sd_j(exp(logml_j - logml)) / sqrt(J).
+__global__ void logml_total_kernel(const double* __restrict__ logml_j, int32_t J, double* out) {
+    __shared__ double red[256];
+    double m = -INFINITY;
+    for (int32_t j = threadIdx.x; j < J; j += 256) m = fmax(m, logml_j[j]);
+    m = block_max256(m, red);
+    double s = 0.0;
+    for (int32_t j = threadIdx.x; j < J; j += 256) s += exp(logml_j[j] - m);
+    s = block_sum256(s, red);
+    const double L = m + log(s / (double)J);
+    double v = 0.0;
+    for (int32_t j = threadIdx.x; j < J; j += 256) {
+        const double r = exp(logml_j[j] - L) - 1.0;
+        v += r * r;
+    }
+    v = block_sum256(v, red);
+    if (threadIdx.x == 0) {
+        out[0] = L;
+        out[1] = J > 1 ? sqrt(v / (double)(J - 1) / (double)J) : 0.0;
+    }
+}
+
+// ------------------------------------------------------------------ S phase
+constexpr int kResThreads = 1024;
+constexpr int kResMaxN = 4096;
+constexpr int kResPer = kResMaxN / kResThreads;  // elements per thread
+
+// Inclusive block scan of one uint64 per thread (1024 threads).
+__device__ uint64_t block_scan_u64(uint64_t v, uint64_t* tmp) {
+    const int t = threadIdx.x;
+    tmp[t] = v;
+    __syncthreads();
+    for (int off = 1; off < kResThreads; off <<= 1) {
+        const uint64_t add = t >= off ? tmp[t - off] : 0;
+        __syncthreads();
+        tmp[t] += add;
+        __syncthreads();
+    }
+    const uint64_t r = tmp[t];
+    __syncthreads();
+    return r;
+}
+
+// floor(U * S / 2^53) for U < 2^53 and S < 2^64.
+__device__ __forceinline__ uint64_t scaled_target(uint64_t U, uint64_t S) {
+    const uint64_t hi = __umul64hi(U, S);
+    const uint64_t lo = U * S;
+    return (hi << 11) | (lo >> 53);
+}
+
+// Smallest n in [0, N) with cum[n] > target (cum inclusive, nondecreasing).
+__device__ __forceinline__ int32_t search_cum(const uint64_t* cum, int32_t N, uint64_t target) {
+    int32_t lo = 0, hi = N - 1;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (cum[mid] > target) hi = mid;
+        else lo = mid + 1;
+    }
+    return lo;
+}
+
+// One block per group.  When log_w is non-null the integer weights are
+// W_n = floor(exp(log_w_n - max log_w) 2^40); otherwise they are read from W.
+// flags |= 1 degenerate group, |= 2 NaN/+inf log-weight, |= 4 bad W total.
+__global__ __launch_bounds__(kResThreads) void resample_kernel(
+    const double* __restrict__ log_w, const uint64_t* __restrict__ Win, int32_t N, int32_t scheme,
+    const uint64_t* __restrict__ u53, int32_t* __restrict__ ancestor, unsigned* flags) {
+    __shared__ uint64_t cum[kResMaxN];
+    __shared__ uint64_t tmp[kResThreads];
+    __shared__ int bad_s;
+    const int t = threadIdx.x;
+    const int64_t base = (int64_t)blockIdx.x * N;
+    int32_t* anc = ancestor + base;
+    const uint64_t* U = u53 + base;
+    if (t == 0) bad_s = 0;
+    __syncthreads();
+
+    // ---- integer weights ----
+    uint64_t w[kResPer];
+    if (log_w != nullptr) {
+        const double* lw = log_w + base;
+        double m = -INFINITY;
+        bool bad = false;
+        for (int32_t n = t; n < N; n += kResThreads) {
+            bad |= isnan(lw[n]) || lw[n] == INFINITY;
+            m = fmax(m, lw[n]);
+        }
+        if (bad) atomicOr(flags, 2u);
+        // block max over the 1024 threads, fixed tree order
+        __shared__ double dred[kResThreads];
+        dred[t] = m;
+        __syncthreads();
+        for (int ww = kResThreads / 2; ww > 0; ww >>= 1) {
+            if (t < ww) dred[t] = fmax(dred[t], dred[t + ww]);
+            __syncthreads();
+        }
+        m = dred[0];
+        __syncthreads();
+        if (!(m > -INFINITY) || bad) {
+            if (t == 0) atomicOr(flags, 1u);
+            if (t == 0) bad_s = 1;
+        }
+#pragma unroll
+        for (int q = 0; q < kResPer; ++q) {
+            const int32_t n = t * kResPer + q;
+            w[q] = (n < N && m > -INFINITY) ? (uint64_t)floor(exp(lw[n] - m) * 0x1p40) : 0;
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < kResPer; ++q) {
+            const int32_t n = t * kResPer + q;
+            w[q] = n < N ? Win[base + n] : 0;
+        }
+    }
+    __syncthreads();
+
+    // ---- cumulative weights: each thread owns elements t*4 .. t*4+3 ----
+    uint64_t local = 0;
+#pragma unroll
+    for (int q = 0; q < kResPer; ++q) local += w[q];
+    uint64_t incl = block_scan_u64(local, tmp);
+    uint64_t run = incl - local;
+#pragma unroll
+    for (int q = 0; q < kResPer; ++q) {
+        run += w[q];
+        const int32_t n = t * kResPer + q;
+        if (n < N) cum[n] = run;
+    }
+    __syncthreads();
+    const uint64_t S = cum[N - 1];
+    if (S == 0 || S >= (uint64_t(1) << 52)) {
+        if (t == 0) {
+            atomicOr(flags, 4u);
+            bad_s = 1;
+        }
+    }
+    __syncthreads();
+    if (bad_s) {
+        // leave a valid (identity) ancestry so later gathers stay in bounds
+        for (int32_t n = t; n < N; n += kResThreads) anc[n] = (int32_t)(base + n);
+        return;
+    }
+
+    if (scheme == SPS_MULTINOMIAL) {
+        for (int32_t i = t; i < N; i += kResThreads)
+            anc[i] = (int32_t)(base + search_cum(cum, N, scaled_target(U[i], S)));
+        return;
+    }
+
+    // ---- residual: deterministic copies, then multinomial on the remainders ----
+    uint64_t cpy[kResPer];
+    uint64_t ncpy = 0;
+#pragma unroll
+    for (int q = 0; q < kResPer; ++q) {
+        cpy[q] = ((uint64_t)N * w[q]) / S;
+        ncpy += cpy[q];
+    }
+    const uint64_t cincl = block_scan_u64(ncpy, tmp);
+    uint64_t pos = cincl - ncpy;
+    __shared__ uint64_t total_copies;
+    if (t == kResThreads - 1) total_copies = cincl;
+#pragma unroll
+    for (int q = 0; q < kResPer; ++q) {
+        const int32_t n = t * kResPer + q;
+        for (uint64_t r = 0; r < cpy[q]; ++r) anc[pos + r] = (int32_t)(base + n);
+        pos += cpy[q];
+    }
+    // residual weights N W_n - copies_n S, total R S < 2^64
+    uint64_t rw[kResPer];
+    uint64_t rloc = 0;
+#pragma unroll
+    for (int q = 0; q < kResPer; ++q) {
+        rw[q] = (uint64_t)N * w[q] - cpy[q] * S;
+        rloc += rw[q];
+    }
+    const uint64_t rincl = block_scan_u64(rloc, tmp);
+    uint64_t rrun = rincl - rloc;
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kResPer; ++q) {
+        rrun += rw[q];
+        const int32_t n = t * kResPer + q;
+        if (n < N) cum[n] = rrun;
+    }
+    __syncthreads();
+    const int32_t done = (int32_t)total_copies;
+    const int32_t R = N - done;
+    const uint64_t RS = cum[N - 1];
+    for (int32_t i = t; i < R; i += kResThreads)
+        anc[done + i] = (int32_t)(base + search_cum(cum, N, scaled_target(U[i], RS)));
+}
+
+__global__ void gather_kernel(const int32_t* __restrict__ anc, int64_t P, int32_t d,
+                              const double* __restrict__ th_in, double* __restrict__ th_out,
+                              const double* __restrict__ ll_in, double* __restrict__ ll_out,
+                              const double* __restrict__ g_in, double* __restrict__ g_out) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= P * d) return;
+    const int64_t p = e / d;
+    const int32_t i = (int32_t)(e % d);
+    const int64_t a = anc[p];
+    if (th_in) th_out[e] = th_in[a * d + i];
+    if (g_in) g_out[e] = g_in[a * d + i];
+    if (ll_in && i == 0) ll_out[p] = ll_in[a];
+}
+
+// ------------------------------------------------------------------ moments
+__global__ void monitor_kernel(const double* __restrict__ theta, int64_t P, int32_t k, int32_t C,
+                               const double* __restrict__ xbar, double* __restrict__ g) {
+    const int32_t d = k * (C - 1), m = d + C - 1;
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= P * m) return;
+    const int64_t p = e / m;
+    const int32_t f = (int32_t)(e % m);
+    if (f < d) {
+        g[e] = theta[p * d + f];
+    } else {
+        const int32_t c = f - d;
+        double s = 0.0;
+        for (int32_t i = 0; i < k; ++i) s += theta[p * d + c * k + i] * xbar[i];
+        g[e] = s;
+    }
+}
+
+// Group sums of (g - g_0f) and its square, shifted by the first particle's
+// value for stability: part[(j * m + f) * 2 + {0, 1}].  Block per
+// (group, 256 functions).
+__global__ void moments_group_kernel(const double* __restrict__ g, int32_t N, int32_t m,
+                                     double* __restrict__ part) {
+    const int32_t j = blockIdx.y;
+    const int32_t f = blockIdx.x * 256 + threadIdx.x;
+    if (f >= m) return;
+    const double c = g[f];
+    double s1 = 0.0, s2 = 0.0;
+    for (int32_t n = 0; n < N; ++n) {
+        const double v = g[((int64_t)j * N + n) * m + f] - c;
+        s1 += v;
+        s2 += v * v;
+    }
+    part[((int64_t)j * m + f) * 2 + 0] = s1;
+    part[((int64_t)j * m + f) * 2 + 1] = s2;
+}
+
+// out[f] = mean, out[m+f] = sd, out[2m+f] = NSE, out[3m+f] = RNE.
+__global__ void moments_final_kernel(const double* __restrict__ g, const double* __restrict__ part,
+                                     int32_t J, int32_t N, int32_t m, double* __restrict__ out) {
+    const int32_t f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= m) return;
+    const double c = g[f];
+    double gb = 0.0;
+    for (int32_t j = 0; j < J; ++j) gb += part[((int64_t)j * m + f) * 2] / (double)N;
+    gb /= (double)J;  // grand mean minus c
+    double vb = 0.0, ss = 0.0;
+    for (int32_t j = 0; j < J; ++j) {
+        const double gj = part[((int64_t)j * m + f) * 2] / (double)N;
+        vb += (gj - gb) * (gj - gb);
+        ss += part[((int64_t)j * m + f) * 2 + 1];
+    }
+    const double P = (double)J * (double)N;
+    const double vhat = J > 1 ? (double)N / (double)(J - 1) * vb : 0.0;
+    double var = ss / P - gb * gb;
+    var = var > 0.0 ? var : 0.0;
+    out[f] = c + gb;
+    out[m + f] = sqrt(var);
+    out[2 * m + f] = sqrt(vhat / P);
+    out[3 * m + f] = vhat > 0.0 ? var / vhat : INFINITY;
+}
+
+static int read_flags(sps_ctx* c, unsigned* dflags, unsigned* out) {
+    SPS_HIP(c, hipMemcpyAsync(c->hostbuf.p, dflags, sizeof(unsigned), hipMemcpyDeviceToHost, c->stream));
+    SPS_HIP(c, hipStreamSynchronize(c->stream));
+    *out = *(unsigned*)c->hostbuf.p;
+    return SPS_OK;
+}
+
+static int zero_flags(sps_ctx* c) {
+    SPS_CHECK(ensure(c, c->small, 4096, "small"));
+    SPS_CHECK(ensure_host(c, c->hostbuf, 4096));
+    SPS_CHECK(fill(c, (double*)c->small.p, 8, 0.0));
+    return SPS_OK;
+}
+
+}  // namespace sps
+
+using namespace sps;
+
+extern "C" int sps_random(sps_ctx* c, int kind, uint64_t seed, uint64_t stream, int64_t count,
+                          int32_t d, void* out) {
+    if (!c) return SPS_ERR_ARG;
+    c->err.clear();
+    if (kind < 0 || kind > 2 || count < 0 || (kind == 2 && d < 1) || (!out && count > 0))
+        return fail(c, SPS_ERR_ARG, "sps_random: bad arguments");
+    return random_fill(c, kind, seed, stream, count, d, out);
+}
+
+extern "C" int sps_init_prior(sps_ctx* c, double* theta, int64_t P, uint64_t seed, uint64_t stream) {
+    if (!c) return SPS_ERR_ARG;
+    c->err.clear();
+    if (!c->has_prior) return fail(c, SPS_ERR_STATE, "sps_init_prior: call sps_set_prior first");
+    if (P < 0 || (!theta && P > 0)) return fail(c, SPS_ERR_ARG, "sps_init_prior: bad arguments");
+    const int64_t n = P * c->d;
+    if (n == 0) return SPS_OK;
+    init_prior_kernel<<<(unsigned)((n + 255) / 256), 256, 0, c->stream>>>(
+        theta, P, c->d, c->prior_mean, c->prior_isd, seed, stream);
+    return launched(c, "init_prior_kernel");
+}
+
+extern "C" int sps_correct(sps_ctx* c, const double* theta, double* ll, int32_t J, int32_t N,
+                           int64_t s0, double ess_frac, int prec, double* log_w, int64_t* t_end,
+                           double* ess_end) {
+    if (!c) return SPS_ERR_ARG;
+    c->err.clear();
+    if (!c->has_data) return fail(c, SPS_ERR_STATE, "sps_correct: call sps_set_data first");
+    if (J < 1 || N < 1 || !theta || !ll || !log_w || !t_end)
+        return fail(c, SPS_ERR_ARG, "sps_correct: bad arguments");
+    if (s0 < 0 || s0 >= c->T) return fail(c, SPS_ERR_ARG, "sps_correct: s0=%lld outside [0, T)", (long long)s0);
+    if (!(ess_frac > 0.0 && ess_frac < 1.0)) return fail(c, SPS_ERR_ARG, "sps_correct: ess_frac outside (0, 1)");
+    if (prec != SPS_FP64 && prec != SPS_FP32 && prec != SPS_BF16X3)
+        return fail(c, SPS_ERR_ARG, "sps_correct: unknown precision %d", prec);
+    const int64_t P = (int64_t)J * N;
+    const int32_t kMaxBlock = 1024;
+    SPS_CHECK(ensure(c, c->corr_lw, sizeof(double) * P * kMaxBlock, "C-phase block"));
+    SPS_CHECK(ensure(c, c->corr_red, sizeof(double) * kMaxBlock, "C-phase ESS"));
+    SPS_CHECK(zero_flags(c));
+    double* lwblk = (double*)c->corr_lw.p;
+    double* ess = (double*)c->corr_red.p;
+    double* res = (double*)c->small.p + 2;  // [2], [3]: index, ESS
+    unsigned* flags = (unsigned*)c->small.p;
+    const unsigned pg = (unsigned)((P + 255) / 256);
+    const double thr = ess_frac * (double)P;
+
+    SPS_CHECK(fill(c, log_w, P, 0.0));  // w = 1 after observation s0
+    int64_t s = s0;
+    int32_t B = 32;
+    for (;;) {
+        const int32_t nb = (int32_t)std::min<int64_t>(B, c->T - s);
+        SPS_CHECK(loglik_perobs(c, theta, P, s, s + nb, prec, lwblk));
+        correct_prefix_kernel<<<pg, 256, 0, c->stream>>>(lwblk, log_w, P, nb);
+        SPS_CHECK(launched(c, "correct_prefix_kernel"));
+        correct_ess_kernel<<<nb, 256, 0, c->stream>>>(lwblk, P, ess, flags);
+        SPS_CHECK(launched(c, "correct_ess_kernel"));
+        correct_find_kernel<<<1, 64, 0, c->stream>>>(ess, nb, thr, s, c->T, res);
+        SPS_CHECK(launched(c, "correct_find_kernel"));
+        SPS_HIP(c, hipMemcpyAsync(c->hostbuf.p, c->small.p, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        SPS_HIP(c, hipStreamSynchronize(c->stream));
+        const double* h = (const double*)c->hostbuf.p;
+        if (*(const unsigned*)h & 1u)
+            return fail(c, SPS_ERR_NONFINITE, "sps_correct: NaN or +inf log-weight before observation %lld",
+                        (long long)(s + nb));
+        const int64_t idx = (int64_t)h[2];
+        if (idx >= 0) {
+            correct_final_kernel<<<pg, 256, 0, c->stream>>>(lwblk + idx * P, log_w, ll, P);
+            SPS_CHECK(launched(c, "correct_final_kernel"));
+            *t_end = s + idx + 1;
+            if (ess_end) *ess_end = h[3];
+            return SPS_OK;
+        }
+        copy_kernel<<<pg, 256, 0, c->stream>>>(lwblk + (int64_t)(nb - 1) * P, log_w, P);
+        SPS_CHECK(launched(c, "copy_kernel"));
+        s += nb;
+        B = std::min(2 * B, kMaxBlock);
+    }
+}
+
+extern "C" int sps_logml(sps_ctx* c, const double* log_w, int32_t J, int32_t N, double* logml_j,
+                         double* logml, double* nse) {
+    if (!c) return SPS_ERR_ARG;
+    c->err.clear();
+    if (J < 1 || N < 1 || !log_w || !logml_j) return fail(c, SPS_ERR_ARG, "sps_logml: bad arguments");
+    SPS_CHECK(zero_flags(c));
+    unsigned* flags = (unsigned*)c->small.p;
+    double* res = (double*)c->small.p + 2;
+    logml_group_kernel<<<J, 256, 0, c->stream>>>(log_w, N, logml_j, flags);
+    SPS_CHECK(launched(c, "logml_group_kernel"));
+    logml_total_kernel<<<1, 256, 0, c->stream>>>(logml_j, J, res);
+    SPS_CHECK(launched(c, "logml_total_kernel"));
+    SPS_HIP(c, hipMemcpyAsync(c->hostbuf.p, c->small.p, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    SPS_HIP(c, hipStreamSynchronize(c->stream));
+    const double* h = (const double*)c->hostbuf.p;
+    const unsigned f = *(const unsigned*)h;
+    if (f & 2u) return fail(c, SPS_ERR_NONFINITE, "sps_logml: NaN or +inf log-weight");
+    if (f & 1u) return fail(c, SPS_ERR_DEGENERATE, "sps_logml: a group has every weight zero");
+    if (logml) *logml = h[2];
+    if (nse) *nse = h[3];
+    return SPS_OK;
+}
+
+static int resample_common(sps_ctx* c, const double* log_w, const uint64_t* W, int32_t J, int32_t N,
+                           int scheme, const uint64_t* u53, int32_t* ancestor, const char* who) {
+    if (J < 1 || N < 1 || N > kResMaxN || !ancestor || !u53)
+        return fail(c, SPS_ERR_ARG, "%s: bad arguments (J>=1, 1<=N<=%d, non-null outputs)", who, kResMaxN);
+    if (scheme != SPS_RESIDUAL && scheme != SPS_MULTINOMIAL)
+        return fail(c, SPS_ERR_ARG, "%s: unknown scheme %d", who, scheme);
+    SPS_CHECK(zero_flags(c));
+    unsigned* flags = (unsigned*)c->small.p;
+    resample_kernel<<<J, kResThreads, 0, c->stream>>>(log_w, W, N, scheme, u53, ancestor, flags);
+    SPS_CHECK(launched(c, "resample_kernel"));
+    unsigned f = 0;
+    SPS_CHECK(read_flags(c, flags, &f));
+    if (f & 2u) return fail(c, SPS_ERR_NONFINITE, "%s: NaN or +inf log-weight", who);
+    if (f & 1u) return fail(c, SPS_ERR_DEGENERATE, "%s: a group has every weight zero", who);
+    if (f & 4u) return fail(c, SPS_ERR_ARG, "%s: a group's integer weight total is 0 or >= 2^52", who);
+    return SPS_OK;
+}
+
+extern "C" int sps_resample(sps_ctx* c, const double* log_w, int32_t J, int32_t N, int scheme,
+                            const uint64_t* u53, uint64_t seed, uint64_t stream, int32_t* ancestor,
+                            const double* theta_in, double* theta_out, const double* ll_in,
+                            double* ll_out, const double* grad_in, double* grad_out) {
+    if (!c) return SPS_ERR_ARG;
+    c->err.clear();
+    if (!log_w) return fail(c, SPS_ERR_ARG, "sps_resample: null log_w");
+    if ((theta_in != nullptr) != (theta_out != nullptr) || (ll_in != nullptr) != (ll_out != nullptr) ||
+        (grad_in != nullptr) != (grad_out != nullptr))
+        return fail(c, SPS_ERR_ARG, "sps_resample: gather source and destination must both be given");
+    if ((theta_in && theta_in == theta_out) || (ll_in && ll_in == ll_out) || (grad_in && grad_in == grad_out))
+        return fail(c, SPS_ERR_ARG, "sps_resample: gather destination aliases its source");
+    if ((theta_in || grad_in) && !c->has_data)
+        return fail(c, SPS_ERR_STATE, "sps_resample: gathering theta needs sps_set_data (for d)");
+    const int64_t P = (int64_t)J * N;
+    if (!u53 && P > 0) {
+        SPS_CHECK(ensure(c, c->u53, sizeof(uint64_t) * P, "resampling integers"));
+        SPS_CHECK(random_fill(c, 0, seed, stream, P, 1, c->u53.p));
+        u53 = (const uint64_t*)c->u53.p;
+    }
+    SPS_CHECK(resample_common(c, log_w, nullptr, J, N, scheme, u53, ancestor, "sps_resample"));
+    if (theta_in || ll_in || grad_in) {
+        const int32_t d = (theta_in || grad_in) ? c->d : 1;
+        const int64_t n = P * d;
+        gather_kernel<<<(unsigned)((n + 255) / 256), 256, 0, c->stream>>>(
+            ancestor, P, d, theta_in, theta_out, ll_in, ll_out, grad_in, grad_out);
+        SPS_CHECK(launched(c, "gather_kernel"));
+    }
+    return SPS_OK;
+}
+
+extern "C" int sps_resample_int(sps_ctx* c, const uint64_t* W, int32_t J, int32_t N, int scheme,
+                                const uint64_t* u53, int32_t* ancestor) {
+    if (!c) return SPS_ERR_ARG;
+    c->err.clear();
+    if (!W) return fail(c, SPS_ERR_ARG, "sps_resample_int: null W");
+    return resample_common(c, nullptr, W, J, N, scheme, u53, ancestor, "sps_resample_int");
+}
+
+extern "C" int sps_monitor(sps_ctx* c, const double* theta, int64_t P, double* g) {
+    if (!c) return SPS_ERR_ARG;
+    c->err.clear();
+    if (!c->has_data) return fail(c, SPS_ERR_STATE, "sps_monitor: call sps_set_data first");
+    if (P < 0 || ((!theta || !g) && P > 0)) return fail(c, SPS_ERR_ARG, "sps_monitor: bad arguments");
+    const int64_t n = P * (c->d + c->C - 1);
+    if (n == 0) return SPS_OK;
+    monitor_kernel<<<(unsigned)((n + 255) / 256), 256, 0, c->stream>>>(theta, P, c->k, c->C, c->xbar, g);
+    return launched(c, "monitor_kernel");
+}
+
+extern "C" int sps_moments(sps_ctx* c, const double* g, int32_t J, int32_t N, int32_t m, double* mean,
+                           double* sd, double* nse, double* rne) {
+    if (!c) return SPS_ERR_ARG;
+    c->err.clear();
+    if (J < 1 || N < 1 || m < 1 || !g) return fail(c, SPS_ERR_ARG, "sps_moments: bad arguments");
+    SPS_CHECK(ensure(c, c->gstat, sizeof(double) * ((size_t)J * m * 2 + 4 * (size_t)m), "moments"));
+    SPS_CHECK(ensure_host(c, c->hostbuf, sizeof(double) * 4 * (size_t)m + 64));
+    double* part = (double*)c->gstat.p;
+    double* out = part + (size_t)J * m * 2;
+    moments_group_kernel<<<dim3((m + 255) / 256, J), 256, 0, c->stream>>>(g, N, m, part);
+    SPS_CHECK(launched(c, "moments_group_kernel"));
+    moments_final_kernel<<<(m + 255) / 256, 256, 0, c->stream>>>(g, part, J, N, m, out);
+    SPS_CHECK(launched(c, "moments_final_kernel"));
+    SPS_HIP(c, hipMemcpyAsync(c->hostbuf.p, out, sizeof(double) * 4 * m, hipMemcpyDeviceToHost, c->stream));
+    SPS_HIP(c, hipStreamSynchronize(c->stream));
+    const double* h = (const double*)c->hostbuf.p;
+    for (int32_t f = 0; f < m; ++f) {
+        if (mean) mean[f] = h[f];
+        if (sd) sd[f] = h[m + f];
+        if (nse) nse[f] = h[2 * m + f];
+        if (rne) rne[f] = h[3 * m + f];
+    }
+    return SPS_OK;
+}

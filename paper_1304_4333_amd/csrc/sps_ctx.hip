@@ -1,0 +1,326 @@
+// sps_ctx.hip -- context lifetime, errors, scratch, and the data/prior set-up
+// of libsps: the kernel copies of X in every precision are built once here.
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+
+#include "sps_internal.h"
+
+namespace sps {
+
+int fail(sps_ctx* c, int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c) c->err = buf;
+    return code;
+}
+
+int hip_fail(sps_ctx* c, hipError_t e, const char* what) {
+    int code = (e == hipErrorOutOfMemory) ? SPS_ERR_NOMEM : SPS_ERR_HIP;
+    return fail(c, code, "%s: %s", what, hipGetErrorString(e));
+}
+
+int ensure(sps_ctx* c, Buf& b, size_t bytes, const char* what) {
+    if (bytes == 0) bytes = 8;
+    if (b.bytes >= bytes) return SPS_OK;
+    if (b.p) {
+        // The old buffer may still be read by queued work on the stream.
+        SPS_HIP(c, hipStreamSynchronize(c->stream));
+        SPS_HIP(c, hipFree(b.p));
+        b.p = nullptr;
+        b.bytes = 0;
+    }
+    size_t want = bytes + bytes / 8;  // headroom against repeated small growth
+    hipError_t e = hipMalloc(&b.p, want);
+    if (e != hipSuccess) {
+        b.p = nullptr;
+        return hip_fail(c, e, what);
+    }
+    b.bytes = want;
+    return SPS_OK;
+}
+
+int ensure_host(sps_ctx* c, Buf& b, size_t bytes) {
+    if (b.bytes >= bytes) return SPS_OK;
+    if (b.p) {
+        SPS_HIP(c, hipStreamSynchronize(c->stream));
+        SPS_HIP(c, hipHostFree(b.p));
+        b.p = nullptr;
+        b.bytes = 0;
+    }
+    hipError_t e = hipHostMalloc(&b.p, bytes, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        b.p = nullptr;
+        return hip_fail(c, e, "hipHostMalloc(staging)");
+    }
+    b.bytes = bytes;
+    return SPS_OK;
+}
+
+// Round-to-nearest-even FP32 -> BF16 bits (inputs are finite).
+__device__ __forceinline__ uint16_t bf16_bits(float f) {
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ double bf16_value(uint16_t h) {
+    return (double)__uint_as_float(((uint32_t)h) << 16);
+}
+
+// Checks y in [0, C) and X finite; flags[0] |= 1 bad y, |= 2 non-finite X.
+__global__ void check_data_kernel(const double* __restrict__ X, const int32_t* __restrict__ y,
+                                  int64_t T, int32_t k, int32_t C, unsigned* flags) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t n = T * k;
+    unsigned f = 0;
+    for (int64_t e = i; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        if (!isfinite(X[e])) f |= 2u;
+    }
+    for (int64_t t = i; t < T; t += (int64_t)gridDim.x * blockDim.x) {
+        int32_t v = y[t];
+        if (v < 0 || v >= C) f |= 1u;
+    }
+    if (f) atomicOr(flags, f);
+}
+
+// Row-major padded copies: Xd, Xf (Tp x kp), Xh, Xl (Tp x kb) and y8.
+__global__ void build_rows_kernel(const double* __restrict__ X, const int32_t* __restrict__ y,
+                                  int64_t T, int32_t k, int32_t C, int64_t Tp, int32_t kp,
+                                  int32_t kb, double* __restrict__ Xd, float* __restrict__ Xf,
+                                  uint16_t* __restrict__ Xh, uint16_t* __restrict__ Xl,
+                                  int8_t* __restrict__ y8) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t t = i / kb;
+    int32_t col = (int32_t)(i % kb);
+    if (t >= Tp) return;
+    double v = 0.0;
+    if (t < T && col < k) {
+        double sgn = (C == 2) ? (1.0 - 2.0 * (double)y[t]) : 1.0;
+        v = sgn * X[t * k + col];
+    }
+    if (col < kp) {
+        Xd[t * kp + col] = v;
+        Xf[t * kp + col] = (float)v;
+    }
+    uint16_t hi = bf16_bits((float)v);
+    uint16_t lo = bf16_bits((float)(v - bf16_value(hi)));
+    Xh[t * kb + col] = hi;
+    Xl[t * kb + col] = lo;
+    if (col == 0) y8[t] = (t < T) ? (int8_t)y[t] : (int8_t)0;
+}
+
+// Transposed copies (kp x Tp) for the adjoint contraction.
+__global__ void build_cols_kernel(const double* __restrict__ Xd, int64_t Tp, int32_t kp, int32_t kt,
+                                  double* __restrict__ XTd, float* __restrict__ XTf,
+                                  uint16_t* __restrict__ XTh, uint16_t* __restrict__ XTl) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t t = i % Tp;
+    int32_t col = (int32_t)(i / Tp);
+    if (col >= kt) return;
+    double v = col < kp ? Xd[t * kp + col] : 0.0;
+    XTd[(int64_t)col * Tp + t] = v;
+    XTf[(int64_t)col * Tp + t] = (float)v;
+    uint16_t hi = bf16_bits((float)v);
+    XTh[(int64_t)col * Tp + t] = hi;
+    XTl[(int64_t)col * Tp + t] = bf16_bits((float)(v - bf16_value(hi)));
+}
+
+// Column means of the caller's X (unsigned), one block per column, fixed order.
+__global__ void column_mean_kernel(const double* __restrict__ X, int64_t T, int32_t k,
+                                   double* __restrict__ xbar) {
+    __shared__ double red[256];
+    int32_t col = blockIdx.x;
+    double s = 0.0;
+    for (int64_t t = threadIdx.x; t < T; t += blockDim.x) s += X[t * k + col];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) xbar[col] = red[0] / (double)T;
+}
+
+static void free_data(sps_ctx* c) {
+    void* ps[] = {c->Xd, c->Xf, c->Xh, c->Xl, c->XTd, c->XTf, c->XTh, c->XTl, c->y8, c->xbar};
+    for (void* p : ps)
+        if (p) (void)hipFree(p);
+    c->Xd = nullptr; c->Xf = nullptr; c->Xh = nullptr; c->Xl = nullptr;
+    c->XTd = nullptr; c->XTf = nullptr; c->XTh = nullptr; c->XTl = nullptr;
+    c->y8 = nullptr; c->xbar = nullptr;
+    c->has_data = false;
+}
+
+static void free_prior(sps_ctx* c) {
+    if (c->prior_mean) (void)hipFree(c->prior_mean);
+    if (c->prior_isd) (void)hipFree(c->prior_isd);
+    c->prior_mean = nullptr;
+    c->prior_isd = nullptr;
+    c->has_prior = false;
+}
+
+}  // namespace sps
+
+using namespace sps;
+
+extern "C" int sps_create(sps_ctx** out, int device, void* hip_stream) {
+    if (!out) return SPS_ERR_ARG;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return SPS_ERR_HIP;
+    if (device < 0 || device >= ndev) return SPS_ERR_ARG;
+    sps_ctx* c = new (std::nothrow) sps_ctx();
+    if (!c) return SPS_ERR_NOMEM;
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    if (hipSetDevice(device) != hipSuccess) {
+        delete c;
+        return SPS_ERR_HIP;
+    }
+    *out = c;
+    return SPS_OK;
+}
+
+extern "C" void sps_destroy(sps_ctx* c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    free_data(c);
+    free_prior(c);
+    Buf* bufs[] = {&c->part_ll, &c->part_g, &c->theta2, &c->ll2, &c->grad2, &c->cov, &c->chol,
+                   &c->mean, &c->pstat, &c->z, &c->u, &c->u53, &c->corr_lw, &c->corr_red,
+                   &c->small, &c->W, &c->gstat};
+    for (Buf* b : bufs)
+        if (b->p) (void)hipFree(b->p);
+    if (c->hostbuf.p) (void)hipHostFree(c->hostbuf.p);
+    delete c;
+}
+
+extern "C" const char* sps_last_error(const sps_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+extern "C" int sps_set_stream(sps_ctx* c, void* hip_stream) {
+    if (!c) return SPS_ERR_ARG;
+    c->stream = (hipStream_t)hip_stream;
+    return SPS_OK;
+}
+
+extern "C" int sps_set_data(sps_ctx* c, const double* X, const int32_t* y, int64_t T, int32_t k,
+                            int32_t C) {
+    if (!c) return SPS_ERR_ARG;
+    c->err.clear();
+    if (!X || !y) return fail(c, SPS_ERR_ARG, "sps_set_data: null X or y");
+    if (T < 1 || T >= (int64_t(1) << 31)) return fail(c, SPS_ERR_ARG, "sps_set_data: T=%lld out of range", (long long)T);
+    if (k < 1 || k > 128) return fail(c, SPS_ERR_ARG, "sps_set_data: k=%d outside [1, 128]", k);
+    if (C < 2 || C > 8) return fail(c, SPS_ERR_ARG, "sps_set_data: C=%d outside [2, 8]", C);
+    SPS_HIP(c, hipSetDevice(c->device));
+    SPS_HIP(c, hipStreamSynchronize(c->stream));
+    free_data(c);
+    free_prior(c);
+
+    SPS_CHECK(ensure(c, c->small, 4096, "small"));
+    SPS_CHECK(ensure_host(c, c->hostbuf, 4096));
+    unsigned* flags = (unsigned*)c->small.p;
+    SPS_HIP(c, hipMemsetAsync(flags, 0, sizeof(unsigned), c->stream));
+    check_data_kernel<<<256, 256, 0, c->stream>>>(X, y, T, k, C, flags);
+    SPS_CHECK(launched(c, "check_data_kernel"));
+    SPS_HIP(c, hipMemcpyAsync(c->hostbuf.p, flags, sizeof(unsigned), hipMemcpyDeviceToHost, c->stream));
+    SPS_HIP(c, hipStreamSynchronize(c->stream));
+    unsigned f = *(unsigned*)c->hostbuf.p;
+    if (f & 1u) return fail(c, SPS_ERR_ARG, "sps_set_data: an outcome lies outside [0, %d)", C);
+    if (f & 2u) return fail(c, SPS_ERR_NONFINITE, "sps_set_data: X holds NaN or inf");
+
+    // Row strides are powers of two times the MFMA contraction length, so each
+    // likelihood kernel instantiation sees a fixed number of k-steps:
+    //   FP64/FP32 rows: kp = max(16, 4 * 2^ceil(log2(ceil(k / 4))))  (16..128)
+    //   BF16 rows     : kb = 32 * 2^ceil(log2(ceil(k / 32)))          (32..128)
+    //   transposed    : kt = max(kp, kb) rows of Tp
+    auto np2 = [](int v) { int r = 1; while (r < v) r <<= 1; return r; };
+    int64_t Tp = ((T + kObsStep - 1) / kObsStep) * kObsStep + kObsStep;
+    int32_t kp = std::max(16, 4 * np2((k + 3) / 4));
+    int32_t kb = 32 * np2((k + 31) / 32);
+    int32_t kt = std::max(kp, kb);
+    auto alloc = [&](void** p, size_t bytes, const char* what) -> int {
+        hipError_t e = hipMalloc(p, bytes);
+        if (e != hipSuccess) {
+            *p = nullptr;
+            free_data(c);
+            return hip_fail(c, e, what);
+        }
+        return SPS_OK;
+    };
+    SPS_CHECK(alloc((void**)&c->Xd, sizeof(double) * Tp * kp, "Xd"));
+    SPS_CHECK(alloc((void**)&c->Xf, sizeof(float) * Tp * kp, "Xf"));
+    SPS_CHECK(alloc((void**)&c->Xh, sizeof(uint16_t) * Tp * kb, "Xh"));
+    SPS_CHECK(alloc((void**)&c->Xl, sizeof(uint16_t) * Tp * kb, "Xl"));
+    SPS_CHECK(alloc((void**)&c->XTd, sizeof(double) * Tp * kt, "XTd"));
+    SPS_CHECK(alloc((void**)&c->XTf, sizeof(float) * Tp * kt, "XTf"));
+    SPS_CHECK(alloc((void**)&c->XTh, sizeof(uint16_t) * Tp * kt, "XTh"));
+    SPS_CHECK(alloc((void**)&c->XTl, sizeof(uint16_t) * Tp * kt, "XTl"));
+    SPS_CHECK(alloc((void**)&c->y8, (size_t)Tp, "y8"));
+    SPS_CHECK(alloc((void**)&c->xbar, sizeof(double) * k, "xbar"));
+
+    int64_t nrow = Tp * kb;
+    build_rows_kernel<<<(unsigned)((nrow + 255) / 256), 256, 0, c->stream>>>(
+        X, y, T, k, C, Tp, kp, kb, c->Xd, c->Xf, c->Xh, c->Xl, c->y8);
+    SPS_CHECK(launched(c, "build_rows_kernel"));
+    int64_t ncol = Tp * kt;
+    build_cols_kernel<<<(unsigned)((ncol + 255) / 256), 256, 0, c->stream>>>(
+        c->Xd, Tp, kp, kt, c->XTd, c->XTf, c->XTh, c->XTl);
+    SPS_CHECK(launched(c, "build_cols_kernel"));
+    column_mean_kernel<<<k, 256, 0, c->stream>>>(X, T, k, c->xbar);
+    SPS_CHECK(launched(c, "column_mean_kernel"));
+    SPS_HIP(c, hipStreamSynchronize(c->stream));
+
+    c->T = T;
+    c->k = k;
+    c->C = C;
+    c->d = k * (C - 1);
+    c->Tp = Tp;
+    c->kp = kp;
+    c->kb = kb;
+    c->kt = kt;
+    c->has_data = true;
+    return SPS_OK;
+}
+
+extern "C" int sps_set_prior(sps_ctx* c, const double* mean, const double* sd) {
+    if (!c) return SPS_ERR_ARG;
+    c->err.clear();
+    if (!c->has_data) return fail(c, SPS_ERR_STATE, "sps_set_prior: call sps_set_data first");
+    if (!mean || !sd) return fail(c, SPS_ERR_ARG, "sps_set_prior: null mean or sd");
+    int d = c->d;
+    double* isd = (double*)malloc(sizeof(double) * d);
+    if (!isd) return fail(c, SPS_ERR_NOMEM, "sps_set_prior: host allocation");
+    double cst = 0.0;
+    for (int i = 0; i < d; ++i) {
+        if (!(sd[i] > 0.0) || !std::isfinite(sd[i]) || !std::isfinite(mean[i])) {
+            free(isd);
+            return fail(c, SPS_ERR_ARG, "sps_set_prior: sd[%d] must be positive and finite", i);
+        }
+        isd[i] = 1.0 / sd[i];
+        cst -= std::log(sd[i]) + 0.5 * std::log(2.0 * M_PI);
+    }
+    SPS_HIP(c, hipSetDevice(c->device));
+    SPS_HIP(c, hipStreamSynchronize(c->stream));
+    free_prior(c);
+    hipError_t e1 = hipMalloc((void**)&c->prior_mean, sizeof(double) * d);
+    hipError_t e2 = hipMalloc((void**)&c->prior_isd, sizeof(double) * d);
+    if (e1 != hipSuccess || e2 != hipSuccess) {
+        free(isd);
+        free_prior(c);
+        return fail(c, SPS_ERR_NOMEM, "sps_set_prior: device allocation");
+    }
+    hipError_t e3 = hipMemcpy(c->prior_mean, mean, sizeof(double) * d, hipMemcpyHostToDevice);
+    hipError_t e4 = hipMemcpy(c->prior_isd, isd, sizeof(double) * d, hipMemcpyHostToDevice);
+    free(isd);
+    if (e3 != hipSuccess) return hip_fail(c, e3, "sps_set_prior: copy");
+    if (e4 != hipSuccess) return hip_fail(c, e4, "sps_set_prior: copy");
+    c->prior_const = cst;
+    c->has_prior = true;
+    return SPS_OK;
+}

@@ -1,0 +1,115 @@
+// sps_internal.h -- context and shared helpers of libsps (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "../../include/sps.h"
+
+namespace sps {
+
+// Observations are processed in steps of 32 rows (two 16-row MFMA tiles);
+// observation ranges are split across workgroups on 32-row boundaries.
+constexpr int kObsStep = 32;
+
+// A grow-only device buffer owned by the context.
+struct Buf {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+
+}  // namespace sps
+
+struct sps_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+
+    // ---- data set (sps_set_data) --------------------------------------
+    bool has_data = false;
+    bool has_prior = false;
+    int64_t T = 0;       // observations
+    int32_t k = 0;       // covariates
+    int32_t C = 0;       // outcomes
+    int32_t d = 0;       // free parameters k (C - 1)
+    int64_t Tp = 0;      // padded row count (multiple of 32, plus one spare step)
+    int32_t kp = 0;      // row stride of the FP64/FP32 copies (multiple of 16)
+    int32_t kb = 0;      // row stride of the BF16 copies (multiple of 32)
+    int32_t kt = 0;      // rows of the transposed copies, max(kp, kb)
+    // Kernel copies of X.  For C == 2 row t is multiplied by (1 - 2 y_t)
+    // ("sign folding"), so that the per-observation log-probability is
+    // -softplus(x~_t' theta) without reading y.  Padding rows/cols are 0.
+    double* Xd = nullptr;      // Tp x kp   FP64
+    float* Xf = nullptr;       // Tp x kp   FP32
+    uint16_t* Xh = nullptr;    // Tp x kb   BF16 high part
+    uint16_t* Xl = nullptr;    // Tp x kb   BF16 low part (x - hi)
+    double* XTd = nullptr;     // kt x Tp   FP64, transposed (adjoint operand)
+    float* XTf = nullptr;      // kt x Tp   FP32, transposed
+    uint16_t* XTh = nullptr;   // kt x Tp   BF16 high, transposed
+    uint16_t* XTl = nullptr;   // kt x Tp   BF16 low, transposed
+    int8_t* y8 = nullptr;      // Tp outcomes as bytes (padding 0)
+    double* xbar = nullptr;    // k column means of X
+    double* prior_mean = nullptr;  // d
+    double* prior_isd = nullptr;   // d  1 / sd
+    double prior_const = 0.0;      // -sum_i (log sd_i + log(2 pi)/2)
+
+    // ---- scratch (grow-only; allocated on first use at a given size) ----
+    sps::Buf part_ll;    // obs-split partial log-likelihoods
+    sps::Buf part_g;     // obs-split partial gradients
+    sps::Buf theta2;     // proposals
+    sps::Buf ll2, grad2; // proposal log-likelihood / gradient
+    sps::Buf cov, chol;  // d x d
+    sps::Buf mean;       // d
+    sps::Buf pstat;      // per-particle statistics of the M step
+    sps::Buf z, u;       // Philox draws when the caller passes none
+    sps::Buf u53;
+    sps::Buf corr_lw;    // C phase block of running log-weights
+    sps::Buf corr_red;   // C phase per-observation reductions
+    sps::Buf small;      // small device results (status words, sums)
+    sps::Buf hostbuf;    // pinned host staging for scalar read-back
+    sps::Buf W;          // resampling integer weights
+    sps::Buf gstat;      // moments partials
+};
+
+namespace sps {
+
+int fail(sps_ctx* c, int code, const char* fmt, ...);
+int hip_fail(sps_ctx* c, hipError_t e, const char* what);
+// Ensure b holds at least `bytes` device bytes (grow-only).
+int ensure(sps_ctx* c, Buf& b, size_t bytes, const char* what);
+int ensure_host(sps_ctx* c, Buf& b, size_t bytes);
+
+#define SPS_HIP(ctx, call)                                      \
+    do {                                                        \
+        hipError_t e_ = (call);                                 \
+        if (e_ != hipSuccess) return sps::hip_fail(ctx, e_, #call); \
+    } while (0)
+
+#define SPS_CHECK(expr)         \
+    do {                        \
+        int s_ = (expr);        \
+        if (s_ != SPS_OK) return s_; \
+    } while (0)
+
+// Launch-error check after a kernel launch.
+inline int launched(sps_ctx* c, const char* what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(c, e, what);
+    return SPS_OK;
+}
+
+// Likelihood entry used by the phases (defined in loglik.hip).
+// Writes ll (and grad when non-null) for observations [t0, t1).
+int loglik_launch(sps_ctx* c, const double* theta, int64_t P, int64_t t0, int64_t t1,
+                  int prec, double* ll, double* grad);
+// Per-observation terms l_{p,t} for t0 <= t < t1 into perobs[(t - t0) * P + p].
+int loglik_perobs(sps_ctx* c, const double* theta, int64_t P, int64_t t0, int64_t t1,
+                  int prec, double* perobs);
+// p[0..n) = v on the context stream (a kernel, safe under graph capture).
+int fill(sps_ctx* c, double* p, int64_t n, double v);
+
+}  // namespace sps
