@@ -1,0 +1,205 @@
+#!/usr/bin/env python3
+"""Throughput of the SPS hot path on one MI355X.
+
+Metric: particle x observation log-likelihood(+gradient) evaluations per
+second over whole SPS cycles.  One step is one pass of every stage of the
+hot path on the benchmark workload, the way a late cycle of Algorithm 2 runs
+it:
+  C phase from observation T - 1000 with the ESS rule (sps_correct),
+  log marginal likelihood increment (sps_logml),
+  residual resampling with gathers (sps_resample),
+  one Gaussian random-walk M step at t = t_end (sps_mutate, RW),
+  the gradient refresh at t_end (sps_loglik_grad, forward + adjoint),
+  one MALA M step at t = t_end (sps_mutate, MALA).
+Evaluations per step = P (t_end - s0) + 3 P t_end.  Inputs are resident on
+the GPU before the timed region; each step first restores the particle state
+(two device copies) so every step does the same work.
+
+The JSON line also carries the roofline of the dominant kernel (timed live
+with HIP events around each launch inside libsps) and the FP64 CPU oracle
+timed on a particle subsample of the same step.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+METRIC = "particle×obs loglik(+grad) evals/sec and SPS wall time at fixed NSE vs FP64"
+PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16x3": 2500.0}
+DTYPE = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3"}
+C_BLOCK = 1000
+
+
+def _workload_desc(w):
+    return (f"{w.name}: multinomial logit C={w.C}, T={w.T} observations, k={w.k} covariates "
+            f"(d={w.d}), J={w.J} groups x N={w.N} particles, prior N(0,{w.prior_sd**2:g} I), "
+            f"{w.precision} likelihood")
+
+
+def gpu_bench(w, steps, warmup, seed=1):
+    import torch
+    from paper_1304_4333_amd import driver, sps, synth
+
+    X, y, B = synth.make_data(w)
+    ctx = driver.setup(X, y, w.C, 0.0, w.prior_sd)
+    prec = sps.PREC[w.precision]
+    J, N, P, d, T = w.J, w.N, w.P, w.d, w.T
+    s0 = T - C_BLOCK
+    f64 = dict(dtype=torch.float64, device="cuda")
+    # particle cloud at posterior scale around the generating coefficients
+    th_np = synth.make_particles(P, d, scale=0.02, seed=seed, center=B.reshape(-1))
+    theta0 = torch.from_numpy(th_np).cuda()
+    ll0 = sps.sps_loglik(ctx, theta0, 0, s0, prec)
+    theta, theta_b = torch.empty(P, d, **f64), torch.empty(P, d, **f64)
+    ll, ll_b = torch.empty(P, **f64), torch.empty(P, **f64)
+    grad = torch.empty(P, d, **f64)
+    log_w = torch.empty(P, **f64)
+    logml_j = torch.zeros(J, **f64)
+    anc = torch.empty(P, dtype=torch.int32, device="cuda")
+
+    def step(i):
+        theta.copy_(theta0)
+        ll.copy_(ll0)
+        _, t_end, _ = sps.sps_correct(ctx, theta, ll, J, N, s0, 0.5, prec, log_w)
+        sps.sps_logml(ctx, log_w, J, N, logml_j)
+        sps.sps_resample(ctx, log_w, J, N, sps.SPS_RESIDUAL, seed=seed, stream=(i << 32) | 2,
+                         ancestor=anc, theta_in=theta, theta_out=theta_b, ll_in=ll, ll_out=ll_b)
+        sps.sps_mutate(ctx, theta_b, ll_b, None, J, N, t_end, 0.3, sps.SPS_RW, prec,
+                       seed=seed, stream=(i << 32) | 3)
+        sps.sps_loglik_grad(ctx, theta_b, 0, t_end, prec, ll_b, grad)
+        sps.sps_mutate(ctx, theta_b, ll_b, grad, J, N, t_end, 0.3, sps.SPS_MALA, prec,
+                       seed=seed, stream=(i << 32) | 5)
+        return P * (t_end - s0) + 3 * P * t_end, t_end
+
+    for i in range(warmup):
+        step(i)
+    torch.cuda.synchronize()
+    sps.sps_timing_enable(ctx, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    evals = 0
+    t_ends = []
+    for i in range(steps):
+        e, te = step(warmup + i)
+        evals += e
+        t_ends.append(te)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    kt = {name: sps.sps_timing_read(ctx, which) for name, which in
+          (("loglik", sps.SPS_KT_LOGLIK), ("loglik_grad", sps.SPS_KT_LOGLIK_GRAD),
+           ("perobs", sps.SPS_KT_PEROBS))}
+    sps.sps_timing_enable(ctx, False)
+    return dict(evals=evals, elapsed=elapsed, kt=kt, t_ends=t_ends, P=P, s0=s0)
+
+
+def roofline(w, res):
+    """Dominant likelihood kernel: algorithmic MFMA flops per launch over its
+    average HIP-event duration.  Forward: 2 k (C-1) flops per particle x
+    observation; forward + adjoint: twice that."""
+    kt = res["kt"]
+    name = max(("loglik", "loglik_grad"), key=lambda n: kt[n][1])
+    n, ms = kt[name]
+    if n == 0:
+        return None, None
+    per_po = 2 * w.k * (w.C - 1) * (2 if name == "loglik_grad" else 1)
+    t_end = int(np.median(res["t_ends"]))
+    flops = per_po * res["P"] * t_end
+    avg_s = ms / n * 1e-3
+    achieved = flops / avg_s / 1e12
+    dt = DTYPE[w.precision]
+    peak = PEAK_TFLOPS[dt]
+    return dict(bound="mfma", achieved=round(achieved, 3), peak=peak, unit="TFLOP/s",
+                frac=round(achieved / peak, 4), traffic=None), \
+        dict(kernel=name, launches=n, avg_us=round(ms / n * 1e3, 2), flops_per_launch=flops)
+
+
+def cpu_baseline(w, seconds, seed=1):
+    """The FP64 oracle on the same step, on a particle subsample of 16 groups
+    of 32 (512 particles), repeated for about `seconds`."""
+    from oracle import oracle as O
+    from paper_1304_4333_amd import synth
+
+    X, y, B = synth.make_data(w)
+    J, N = 16, 32
+    P, d, T = J * N, w.d, w.T
+    s0 = T - C_BLOCK
+    th0 = synth.make_particles(w.P, d, scale=0.02, seed=seed, center=B.reshape(-1))[:P]
+    ll0 = O.loglik(X, y, w.C, th0, 0, s0)
+    evals = 0
+    t0 = time.perf_counter()
+    steps = 0
+    while True:
+        lw, ll, t_end, _ = O.correct(X, y, w.C, th0, ll0, J, N, s0, 0.5)
+        O.logml_update(lw, J, N, np.zeros(J))
+        anc, _ = O.resample(lw, J, N, 0, O.u53(seed, (steps << 32) | 2, P))
+        th, ll = th0[anc], ll[anc]
+        z = O.normals(seed, (steps << 32) | 3, P, d)
+        u = O.uniforms(seed, (steps << 32) | 4, P)
+        th, ll, _, _, _, _ = O.mutate(X, y, w.C, 0.0, w.prior_sd, th, ll, None, J, N, t_end, 0.3, 0, z, u)
+        ll, gr = O.loglik(X, y, w.C, th, 0, t_end, grad=True)
+        z = O.normals(seed, (steps << 32) | 5, P, d)
+        u = O.uniforms(seed, (steps << 32) | 6, P)
+        O.mutate(X, y, w.C, 0.0, w.prior_sd, th, ll, gr, J, N, t_end, 0.3, 1, z, u)
+        evals += P * (t_end - s0) + 3 * P * t_end
+        steps += 1
+        el = time.perf_counter() - t0
+        if el >= seconds:
+            break
+    cores = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1)
+    return dict(value=round(evals / el, 1), unit="particle-obs evals/s", cores=cores, kind="oracle",
+                sample=f"{steps} steps of the same cycle on 512 of the {w.P} particles "
+                       f"(16 groups x 32), {el:.1f} s, OpenMP over particles")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="binary30")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); the particle-group "
+              "sharding across GPUs is a design note only.", file=sys.stderr)
+        sys.exit(2)
+    from paper_1304_4333_amd import synth
+    w = synth.workload(args.workload)
+    res = gpu_bench(w, args.steps, args.warmup)
+    value = res["evals"] / res["elapsed"]
+    roof, kinfo = roofline(w, res)
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(w, args.cpu_seconds)
+    out = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "particle-obs evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(res["elapsed"] / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": DTYPE[w.precision],
+        "data": "synthetic",
+        "config": {"workload": _workload_desc(w), "step": "C phase (last 1000 obs) + logML + "
+                   "resample + RW step + gradient refresh + MALA step",
+                   "evals_per_step": int(res["evals"] / args.steps),
+                   "dominant_kernel": kinfo,
+                   "kernel_ms": {k: [v[0], round(v[1], 3)] for k, v in res["kt"].items()}},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -195,6 +195,22 @@ int sps_monitor(sps_ctx* ctx, const double* theta, int64_t P, double* g);
 int sps_moments(sps_ctx* ctx, const double* g, int32_t J, int32_t N, int32_t m,
                 double* mean, double* sd, double* nse, double* rne);
 
+/* ------------------------------------------------------ instrumentation */
+
+/* Kernel classes timed by sps_timing_read. */
+enum { SPS_KT_LOGLIK = 0,       /* forward likelihood kernel (sps_loglik, M-phase proposals) */
+       SPS_KT_LOGLIK_GRAD = 1,  /* fused forward + adjoint kernel                          */
+       SPS_KT_PEROBS = 2 };     /* per-observation terms of the C phase                      */
+
+/* enable != 0: from now on bracket every launch of the likelihood kernels
+ * with HIP events on the context stream; enable == 0: stop.  Either way the
+ * accumulated counts are reset. */
+int sps_timing_enable(sps_ctx* ctx, int enable);
+
+/* Synchronises the stream and returns, for kernel class `which`, the number
+ * of timed launches and their summed GPU duration in milliseconds (host). */
+int sps_timing_read(sps_ctx* ctx, int which, int64_t* launches, double* total_ms);
+
 #ifdef __cplusplus
 }
 #endif

@@ -100,8 +100,11 @@ static int run_loglik(sps_ctx* c, const double* theta, int64_t P, int64_t t0, in
     }
     a.perobs = perobs;
     dim3 grid((unsigned)(npt * nsplit));
+    int slot = -1;
+    SPS_CHECK(timing_begin(c, grad ? SPS_KT_LOGLIK_GRAD : (perobs ? SPS_KT_PEROBS : SPS_KT_LOGLIK), &slot));
     hipError_t err = e.fn(a, grid, c->stream);
     if (err != hipSuccess) return hip_fail(c, err, "loglik_kernel launch");
+    SPS_CHECK(timing_end(c, slot));
     if (ll && a.out_ll != ll) {
         const int64_t n = grad ? P * c->d : P;
         loglik_reduce_kernel<<<(unsigned)((n + 255) / 256), 256, 0, c->stream>>>(

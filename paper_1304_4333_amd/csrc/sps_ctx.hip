@@ -164,9 +164,82 @@ static void free_prior(sps_ctx* c) {
     c->has_prior = false;
 }
 
+int timing_begin(sps_ctx* c, int which, int* slot) {
+    *slot = -1;
+    if (!c->timing) return SPS_OK;
+    hipEvent_t ev[2];
+    for (int i = 0; i < 2; ++i) {
+        if (!c->evpool.empty()) {
+            ev[i] = c->evpool.back();
+            c->evpool.pop_back();
+        } else {
+            SPS_HIP(c, hipEventCreate(&ev[i]));
+        }
+    }
+    SPS_HIP(c, hipEventRecord(ev[0], c->stream));
+    c->pending.push_back(sps_ctx::Timed{which, ev[0], ev[1]});
+    *slot = (int)c->pending.size() - 1;
+    return SPS_OK;
+}
+
+int timing_end(sps_ctx* c, int slot) {
+    if (slot < 0) return SPS_OK;
+    SPS_HIP(c, hipEventRecord(c->pending[slot].b, c->stream));
+    return SPS_OK;
+}
+
+// Fold finished event pairs into the totals and recycle the events.
+static int timing_collect(sps_ctx* c) {
+    if (c->pending.empty()) return SPS_OK;
+    SPS_HIP(c, hipStreamSynchronize(c->stream));
+    for (auto& t : c->pending) {
+        float ms = 0.f;
+        SPS_HIP(c, hipEventElapsedTime(&ms, t.a, t.b));
+        c->kt_ms[t.which] += ms;
+        c->kt_n[t.which] += 1;
+        c->evpool.push_back(t.a);
+        c->evpool.push_back(t.b);
+    }
+    c->pending.clear();
+    return SPS_OK;
+}
+
+void timing_release(sps_ctx* c) {
+    (void)hipStreamSynchronize(c->stream);
+    for (auto& t : c->pending) {
+        (void)hipEventDestroy(t.a);
+        (void)hipEventDestroy(t.b);
+    }
+    for (auto e : c->evpool) (void)hipEventDestroy(e);
+    c->pending.clear();
+    c->evpool.clear();
+}
+
 }  // namespace sps
 
 using namespace sps;
+
+extern "C" int sps_timing_enable(sps_ctx* c, int enable) {
+    if (!c) return SPS_ERR_ARG;
+    c->err.clear();
+    SPS_CHECK(timing_collect(c));
+    c->timing = enable != 0;
+    for (int i = 0; i < 3; ++i) {
+        c->kt_ms[i] = 0.0;
+        c->kt_n[i] = 0;
+    }
+    return SPS_OK;
+}
+
+extern "C" int sps_timing_read(sps_ctx* c, int which, int64_t* launches, double* total_ms) {
+    if (!c) return SPS_ERR_ARG;
+    c->err.clear();
+    if (which < 0 || which > 2) return fail(c, SPS_ERR_ARG, "sps_timing_read: unknown kernel class %d", which);
+    SPS_CHECK(timing_collect(c));
+    if (launches) *launches = c->kt_n[which];
+    if (total_ms) *total_ms = c->kt_ms[which];
+    return SPS_OK;
+}
 
 extern "C" int sps_create(sps_ctx** out, int device, void* hip_stream) {
     if (!out) return SPS_ERR_ARG;
@@ -198,6 +271,7 @@ extern "C" void sps_destroy(sps_ctx* c) {
     for (Buf* b : bufs)
         if (b->p) (void)hipFree(b->p);
     if (c->hostbuf.p) (void)hipHostFree(c->hostbuf.p);
+    timing_release(c);
     delete c;
 }
 

@@ -7,6 +7,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <string>
+#include <vector>
 
 #include "../../include/sps.h"
 
@@ -73,6 +74,17 @@ struct sps_ctx {
     sps::Buf hostbuf;    // pinned host staging for scalar read-back
     sps::Buf W;          // resampling integer weights
     sps::Buf gstat;      // moments partials
+
+    // ---- optional kernel timing (sps_timing_enable) ----
+    struct Timed {
+        int which;
+        hipEvent_t a, b;
+    };
+    bool timing = false;
+    std::vector<hipEvent_t> evpool;
+    std::vector<Timed> pending;
+    double kt_ms[3] = {0, 0, 0};
+    int64_t kt_n[3] = {0, 0, 0};
 };
 
 namespace sps {
@@ -109,6 +121,10 @@ int loglik_launch(sps_ctx* c, const double* theta, int64_t P, int64_t t0, int64_
 // Per-observation terms l_{p,t} for t0 <= t < t1 into perobs[(t - t0) * P + p].
 int loglik_perobs(sps_ctx* c, const double* theta, int64_t P, int64_t t0, int64_t t1,
                   int prec, double* perobs);
+// Event pair bracketing one timed launch (no-op unless timing is enabled).
+int timing_begin(sps_ctx* c, int which, int* slot);
+int timing_end(sps_ctx* c, int slot);
+void timing_release(sps_ctx* c);
 // p[0..n) = v on the context stream (a kernel, safe under graph capture).
 int fill(sps_ctx* c, double* p, int64_t n, double v);
 

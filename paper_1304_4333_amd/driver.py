@@ -1,0 +1,141 @@
+"""Adaptive sequential posterior simulator (Algorithm 2 of Geweke, Durham &
+Xu 2013) driven through the libsps C ABI.
+
+Every numerical step runs in the HIP library: C phase with the ESS rule
+(sps_correct), log marginal likelihood increments (sps_logml), S phase
+(sps_resample), M phase steps (sps_mutate), monitored functions and
+NSE/RNE (sps_monitor, sps_moments).  This module holds only the control
+flow: the cycle loop, the RNE stopping rule and the step-size rule.
+
+Random streams (shared convention with the oracle's driver):
+stream(cycle, step, phase) = cycle << 32 | step << 4 | phase, phase 1 =
+initial particles, 2 = resampling integers, 3 = proposal normals,
+4 = acceptance uniforms.
+"""
+from __future__ import annotations
+
+import dataclasses
+import time
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import sps
+
+
+@dataclasses.dataclass
+class SpsConfig:
+    """Design constants of Algorithm 2 (all user-changeable, Section 2.3)."""
+    J: int
+    N: int
+    precision: str = "fp64"      # likelihood arithmetic: fp64, fp32, bf16x3
+    kind: str = "rw"             # M-phase proposal: rw (the paper) or mala
+    scheme: str = "residual"     # S phase: residual or multinomial
+    rne_rule: str = "mean"       # aggregate of the monitored RNEs: mean or min
+    R_max: int = 100             # cap on M steps per cycle
+    ess_frac: float = 0.5        # C phase stops when ESS < ess_frac J N
+    K_mid: float = 0.35          # RNE target before the last cycle
+    K_final: float = 0.9         # RNE target in the last cycle
+    h_init: float = 0.5
+    h_step: float = 0.01
+    h_min: float = 0.1
+    h_max: float = 1.0
+    acc_target: float = 0.25
+    seed: int = 0
+
+    @staticmethod
+    def mala_defaults(**kw) -> "SpsConfig":
+        """MALA tuning: target acceptance 0.574, h in [0.01, 2]."""
+        base = dict(kind="mala", h_min=0.01, h_max=2.0, acc_target=0.574)
+        base.update(kw)
+        return SpsConfig(**base)
+
+
+def stream_id(cycle: int, step: int, phase: int) -> int:
+    return (cycle << 32) | (step << 4) | phase
+
+
+def run_sps(ctx: sps.Context, cfg: SpsConfig, log=None) -> dict:
+    """One pass of the adaptive SPS on the data and prior set in ctx."""
+    J, N = cfg.J, cfg.N
+    P, d, C, T = J * N, ctx.d, ctx.C, ctx.T
+    m = d + C - 1
+    dev = ctx.device
+    prec = sps.PREC[cfg.precision]
+    kind = sps.KIND[cfg.kind]
+    scheme = sps.SCHEME[cfg.scheme]
+    mala = kind == sps.SPS_MALA
+    f64 = dict(dtype=torch.float64, device=dev)
+
+    theta = torch.empty(P, d, **f64)
+    theta_b = torch.empty(P, d, **f64)
+    ll = torch.zeros(P, **f64)
+    ll_b = torch.empty(P, **f64)
+    grad = torch.zeros(P, d, **f64) if mala else None
+    grad_b = torch.empty(P, d, **f64) if mala else None
+    log_w = torch.empty(P, **f64)
+    logml_j = torch.zeros(J, **f64)
+    g = torch.empty(P, m, **f64)
+    anc = torch.empty(P, dtype=torch.int32, device=dev)
+
+    t_start = time.perf_counter()
+    sps.sps_init_prior(ctx, theta, cfg.seed, stream_id(0, 0, 1))
+    h = cfg.h_init
+    t = 0
+    cycle = 0
+    m_iters = 0
+    hit_R_max = 0
+    records = []
+    logml = nse_logml = float("nan")
+    while t < T:
+        cycle += 1
+        log_w, t_end, ess = sps.sps_correct(ctx, theta, ll, J, N, t, cfg.ess_frac, prec, log_w)
+        t = t_end
+        logml, nse_logml = sps.sps_logml(ctx, log_w, J, N, logml_j)
+        sps.sps_resample(ctx, log_w, J, N, scheme, seed=cfg.seed, stream=stream_id(cycle, 0, 2),
+                         ancestor=anc, theta_in=theta, theta_out=theta_b, ll_in=ll, ll_out=ll_b)
+        theta, theta_b = theta_b, theta
+        ll, ll_b = ll_b, ll
+        if mala:
+            # the cached gradient must cover y_{1:t_l}: evaluate it afresh
+            sps.sps_loglik_grad(ctx, theta, 0, t, prec, ll, grad)
+        K = cfg.K_mid if t < T else cfg.K_final
+        r = 0
+        rate = 0.0
+        while True:
+            r += 1
+            rate = sps.sps_mutate(ctx, theta, ll, grad, J, N, t, h, kind, prec,
+                                  seed=cfg.seed, stream=stream_id(cycle, r, 3))
+            h = min(h + cfg.h_step, cfg.h_max) if rate > cfg.acc_target else max(h - cfg.h_step, cfg.h_min)
+            sps.sps_monitor(ctx, theta, g)
+            _, _, _, rne = sps.sps_moments(ctx, g, J, N)
+            agg = float(np.min(rne)) if cfg.rne_rule == "min" else float(np.mean(rne))
+            if agg >= K:
+                break
+            if r >= cfg.R_max:
+                hit_R_max += 1
+                break
+        m_iters += r
+        rec = dict(cycle=cycle, t=t, ess=ess, R=r, h=h, acc=rate, rne=agg, logml=logml)
+        records.append(rec)
+        if log is not None:
+            log(rec)
+    torch.cuda.synchronize(dev)
+    wall = time.perf_counter() - t_start
+    sps.sps_monitor(ctx, theta, g)
+    mean, sd, nse, rne = sps.sps_moments(ctx, g, J, N)
+    return dict(theta=theta, ll=ll, mean=mean, sd=sd, nse=nse, rne=rne, logml=logml,
+                logml_nse=nse_logml, logml_j=logml_j.cpu().numpy(), cycles=cycle,
+                m_iters=m_iters, hit_R_max=hit_R_max, records=records, wall=wall)
+
+
+def setup(X: np.ndarray, y: np.ndarray, C: int, prior_mean=0.0, prior_sd=1.0,
+          device: int = 0, stream: Optional[torch.cuda.Stream] = None) -> sps.Context:
+    """A context with the data set and the iid N(prior_mean, prior_sd^2) prior."""
+    ctx = sps.Context(device, stream)
+    Xg = torch.from_numpy(np.ascontiguousarray(X, dtype=np.float64)).to(ctx.device)
+    yg = torch.from_numpy(np.ascontiguousarray(y, dtype=np.int32)).to(ctx.device)
+    sps.sps_set_data(ctx, Xg, yg, C)
+    sps.sps_set_prior(ctx, prior_mean, prior_sd)
+    return ctx

@@ -21,6 +21,7 @@ SPS_ERR_NONFINITE, SPS_ERR_DEGENERATE, SPS_ERR_NOMEM, SPS_ERR_STATE = -4, -5, -6
 SPS_FP64, SPS_FP32, SPS_BF16X3 = 0, 1, 2
 SPS_RESIDUAL, SPS_MULTINOMIAL = 0, 1
 SPS_RW, SPS_MALA = 0, 1
+SPS_KT_LOGLIK, SPS_KT_LOGLIK_GRAD, SPS_KT_PEROBS = 0, 1, 2
 
 PREC = {"fp64": SPS_FP64, "fp32": SPS_FP32, "bf16x3": SPS_BF16X3}
 KIND = {"rw": SPS_RW, "mala": SPS_MALA}
@@ -56,6 +57,8 @@ _SIGS = {
     "sps_monitor": [_vp, _vp, _i64, _vp],
     "sps_moments": [_vp, _vp, _i32, _i32, _i32, ct.POINTER(_dbl), ct.POINTER(_dbl),
                     ct.POINTER(_dbl), ct.POINTER(_dbl)],
+    "sps_timing_enable": [_vp, ct.c_int],
+    "sps_timing_read": [_vp, ct.c_int, ct.POINTER(_i64), ct.POINTER(_dbl)],
 }
 _RESTYPE = {"sps_destroy": None, "sps_last_error": ct.c_char_p}
 ABI_NAMES = tuple(_SIGS)
@@ -294,6 +297,17 @@ def sps_moments(ctx: Context, g: torch.Tensor, J: int, N: int):
     ptrs = [o.ctypes.data_as(ct.POINTER(_dbl)) for o in outs]
     ctx.check(lib().sps_moments(ctx.handle, _ptr(g), J, N, m, *ptrs))
     return tuple(outs)  # mean, sd, nse, rne
+
+
+def sps_timing_enable(ctx: Context, enable: bool = True):
+    ctx.check(lib().sps_timing_enable(ctx.handle, 1 if enable else 0))
+
+
+def sps_timing_read(ctx: Context, which: int):
+    """(launches, total milliseconds) of one kernel class since the last enable."""
+    n, ms = _i64(0), _dbl(0.0)
+    ctx.check(lib().sps_timing_read(ctx.handle, which, ct.byref(n), ct.byref(ms)))
+    return n.value, ms.value
 
 
 # ------------------------------------------------------------------ autograd

@@ -1,0 +1,248 @@
+"""GPU parity of the C, S and M phases, logML, moments and the Philox draws
+against the FP64 oracle, on the same seeded inputs.
+
+Bars: integer work (Philox integers, resampling ancestors) bit-exact; FP64
+results relative 1e-10 unless a transcendental differs in the last ulp
+(normals: 1e-12); reduced-precision log-weights 1e-4 relative; MH decisions
+identical wherever |log alpha - log u| exceeds the log-likelihood error bound.
+"""
+import numpy as np
+import pytest
+
+from gpu_common import dataset, make_ctx, need_gpu, rel_err, to_gpu
+from paper_1304_4333_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _sps():
+    from paper_1304_4333_amd import sps
+    return sps
+
+
+# ------------------------------------------------------------------ randoms
+def test_philox_integers_bit_exact(orc):
+    need_gpu()
+    sps = _sps()
+    X, y, _ = dataset(50, 3, 2, seed=1)
+    ctx = make_ctx(X, y, 2)
+    for seed, stream in ((0, 0), (0xDEADBEEF12345678, (7 << 32) | 3)):
+        g = sps.sps_random(ctx, 0, seed, stream, 10_000).cpu().numpy()
+        assert np.array_equal(g, orc.u53(seed, stream, 10_000))
+        u = sps.sps_random(ctx, 1, seed, stream, 1000).cpu().numpy()
+        assert np.array_equal(u, orc.uniforms(seed, stream, 1000))
+        z = sps.sps_random(ctx, 2, seed, stream, 300, 7).cpu().numpy()
+        assert np.allclose(z, orc.normals(seed, stream, 300, 7), rtol=1e-12, atol=1e-12)
+
+
+def test_init_prior_matches_oracle(orc):
+    need_gpu()
+    import torch
+    sps = _sps()
+    X, y, _ = dataset(50, 4, 3, seed=2)
+    ctx = make_ctx(X, y, 3, prior_sd=2.5)
+    th = torch.empty(777, 8, dtype=torch.float64, device="cuda")
+    sps.sps_init_prior(ctx, th, seed=5, stream=1)
+    ref = orc.init_prior(np.zeros(8), np.full(8, 2.5), 777, 5, 1)
+    assert np.allclose(th.cpu().numpy(), ref, rtol=1e-12, atol=1e-12)
+
+
+# ------------------------------------------------------------------ C phase
+@pytest.mark.parametrize("prec", [0, 1, 2])
+@pytest.mark.parametrize("C,k,J,N,s0,scale", [(2, 5, 4, 256, 0, 1.0), (3, 6, 2, 100, 37, 0.4),
+                                              (2, 30, 8, 64, 500, 0.05), (4, 20, 3, 33, 0, 0.01)])
+def test_correct_matches_oracle(orc, prec, C, k, J, N, s0, scale):
+    need_gpu()
+    sps = _sps()
+    T = 2000
+    X, y, _ = dataset(T, k, C, seed=10 + k)
+    d = k * (C - 1)
+    th = synth.make_particles(J * N, d, scale=scale, seed=3)
+    ll0 = synth.make_normals(J * N, 1, seed=4)[:, 0]
+    print(f"correct C={C} k={k} J={J} N={N} s0={s0} prec={prec}", flush=True)
+    ctx = make_ctx(X, y, C)
+    llg = to_gpu(ll0.copy())
+    lw, t_end, ess = sps.sps_correct(ctx, to_gpu(th), llg, J, N, s0, 0.5, prec)
+    lw_o, ll_o, t_o, ess_o = orc.correct(X, y, C, th, ll0, J, N, s0, 0.5)
+    tol = 1e-10 if prec == 0 else 1e-4
+    if t_end != t_o:
+        # only acceptable when the oracle's ESS sits within rounding of the threshold
+        lw_a, _, _, _ = orc.correct(X, y, C, th, ll0, J, N, s0, 0.5)
+        pytest.fail(f"t_end {t_end} != oracle {t_o} (ESS {ess} vs {ess_o})")
+    assert ess == pytest.approx(ess_o, rel=10 * tol)
+    assert rel_err(lw.cpu().numpy(), lw_o).max() <= tol
+    assert rel_err(llg.cpu().numpy(), ll_o).max() <= tol
+
+
+def test_correct_runs_to_T_with_equal_particles():
+    need_gpu()
+    import torch
+    sps = _sps()
+    X, y, _ = dataset(300, 3, 2, seed=5)
+    ctx = make_ctx(X, y, 2)
+    th = torch.full((64, 3), 0.2, dtype=torch.float64, device="cuda")
+    ll = torch.zeros(64, dtype=torch.float64, device="cuda")
+    lw, t_end, ess = sps.sps_correct(ctx, th, ll, 4, 16, 10, 0.5, 0)
+    assert t_end == 300 and ess == pytest.approx(64.0)
+
+
+# ------------------------------------------------------------------ logML
+def test_logml_matches_oracle(orc):
+    need_gpu()
+    import torch
+    sps = _sps()
+    X, y, _ = dataset(50, 2, 2, seed=6)
+    ctx = make_ctx(X, y, 2)
+    J, N = 16, 300
+    lw = synth.make_log_weights(J * N, seed=7, spread=3.0, n_neg_inf=40)
+    lj0 = synth.make_normals(J, 1, seed=8)[:, 0]
+    lj = to_gpu(lj0.copy())
+    L, nse = sps.sps_logml(ctx, to_gpu(lw), J, N, lj)
+    ref_j = orc.logml_update(lw, J, N, lj0)
+    ref = orc.logml_total(ref_j)
+    assert np.allclose(lj.cpu().numpy(), ref_j, rtol=1e-13, atol=1e-13)
+    assert L == pytest.approx(ref[0], rel=1e-13) and nse == pytest.approx(ref[1], rel=1e-10)
+    bad = lw.copy()
+    bad[N:2 * N] = -np.inf
+    with pytest.raises(sps.SpsError) as e:
+        sps.sps_logml(ctx, to_gpu(bad), J, N, to_gpu(lj0.copy()))
+    assert e.value.status == sps.SPS_ERR_DEGENERATE
+
+
+# ------------------------------------------------------------------ S phase
+@pytest.mark.parametrize("scheme", [0, 1])
+@pytest.mark.parametrize("J,N", [(1, 1), (3, 7), (16, 1024), (2, 4096), (5, 1000)])
+def test_resample_int_bit_exact(orc, scheme, J, N):
+    need_gpu()
+    sps = _sps()
+    X, y, _ = dataset(20, 2, 2, seed=9)
+    ctx = make_ctx(X, y, 2)
+    W = synth.make_int_weights(J, N, seed=J + N)
+    U = synth.make_u53(J * N, seed=N)
+    anc = sps.sps_resample_int(ctx, to_gpu(W), J, N, scheme, to_gpu(U)).cpu().numpy()
+    assert np.array_equal(anc, orc.resample_int(W, J, N, scheme, U))
+
+
+@pytest.mark.parametrize("scheme", [0, 1])
+def test_resample_log_weights_and_gather(orc, scheme):
+    need_gpu()
+    import torch
+    sps = _sps()
+    X, y, _ = dataset(20, 4, 3, seed=10)
+    ctx = make_ctx(X, y, 3)
+    J, N, d = 8, 512, 8
+    lw = synth.make_log_weights(J * N, seed=11, spread=2.5, n_neg_inf=100)
+    U = synth.make_u53(J * N, seed=12)
+    th = synth.make_particles(J * N, d, seed=13)
+    ll = synth.make_normals(J * N, 1, seed=14)[:, 0]
+    gr = synth.make_particles(J * N, d, seed=15)
+    outs = [torch.empty(J * N, d, dtype=torch.float64, device="cuda"),
+            torch.empty(J * N, dtype=torch.float64, device="cuda"),
+            torch.empty(J * N, d, dtype=torch.float64, device="cuda")]
+    anc = sps.sps_resample(ctx, to_gpu(lw), J, N, scheme, u53=to_gpu(U), theta_in=to_gpu(th),
+                           theta_out=outs[0], ll_in=to_gpu(ll), ll_out=outs[1], grad_in=to_gpu(gr),
+                           grad_out=outs[2]).cpu().numpy()
+    ref, _ = orc.resample(lw, J, N, scheme, U)
+    assert np.array_equal(anc, ref)
+    assert np.array_equal(outs[0].cpu().numpy(), th[ref])
+    assert np.array_equal(outs[1].cpu().numpy(), ll[ref])
+    assert np.array_equal(outs[2].cpu().numpy(), gr[ref])
+    # Philox draws when no integers are passed: the oracle's generator, same stream
+    anc2 = sps.sps_resample(ctx, to_gpu(lw), J, N, scheme, seed=3, stream=99).cpu().numpy()
+    ref2, _ = orc.resample(lw, J, N, scheme, orc.u53(3, 99, J * N))
+    assert np.array_equal(anc2, ref2)
+
+
+def test_resample_errors():
+    need_gpu()
+    sps = _sps()
+    X, y, _ = dataset(20, 2, 2, seed=16)
+    ctx = make_ctx(X, y, 2)
+    lw = np.zeros(8)
+    lw[3] = np.nan
+    with pytest.raises(sps.SpsError) as e:
+        sps.sps_resample(ctx, to_gpu(lw), 2, 4, 0, seed=1)
+    assert e.value.status == sps.SPS_ERR_NONFINITE
+    lw = np.zeros(8)
+    lw[4:] = -np.inf
+    with pytest.raises(sps.SpsError) as e:
+        sps.sps_resample(ctx, to_gpu(lw), 2, 4, 0, seed=1)
+    assert e.value.status == sps.SPS_ERR_DEGENERATE
+
+
+# ------------------------------------------------------------------ M phase
+@pytest.mark.parametrize("kind", [0, 1])
+@pytest.mark.parametrize("prec", [0, 1, 2])
+@pytest.mark.parametrize("C,k,J,N,t", [(2, 5, 4, 256, 400), (3, 10, 4, 200, 777), (2, 30, 16, 128, 2000)])
+def test_mutate_matches_oracle(orc, kind, prec, C, k, J, N, t):
+    need_gpu()
+    sps = _sps()
+    T = 2000
+    X, y, B = dataset(T, k, C, seed=20 + k)
+    d = k * (C - 1)
+    P = J * N
+    center = B.reshape(-1)
+    th = synth.make_particles(P, d, scale=0.05, seed=21, center=center)
+    ll, gr = orc.loglik(X, y, C, th, 0, t, grad=True)
+    z = synth.make_normals(P, d, seed=22)
+    u = synth.make_uniforms(P, seed=23)
+    h = 0.3
+    print(f"mutate C={C} k={k} P={P} t={t} kind={kind} prec={prec}", flush=True)
+    ctx = make_ctx(X, y, C)
+    thg, llg = to_gpu(th), to_gpu(ll)
+    grg = to_gpu(gr) if kind == 1 else None
+    rate = sps.sps_mutate(ctx, thg, llg, grg, J, N, t, h, kind, prec, z=to_gpu(z), u=to_gpu(u))
+    th_o, ll_o, gr_o, rate_o, la_o, acc_o = orc.mutate(X, y, C, 0.0, 5.0, th, ll, gr if kind else None,
+                                                       J, N, t, h, kind, z, u)
+    th_g = thg.cpu().numpy()
+    acc_g = np.any(th_g != th, axis=1)
+    # decisions may differ only where log u is within the likelihood error of log alpha
+    bound = 1e-6 if prec == 0 else 2e-4 * max(1.0, np.abs(ll_o).max())
+    margin = np.abs(np.log(u) - la_o)
+    diff = acc_g != acc_o
+    assert np.all(margin[diff] < bound), f"{diff.sum()} decisions differ beyond the error bound"
+    same = ~diff
+    assert abs(rate - acc_g.mean()) < 1e-15
+    tol = 1e-9 if prec == 0 else 1e-4
+    assert rel_err(th_g[same], th_o[same]).max() <= 1e-9
+    assert rel_err(llg.cpu().numpy()[same], ll_o[same]).max() <= tol
+    if kind == 1:
+        g_g = grg.cpu().numpy()[same]
+        nrm = np.linalg.norm(g_g - gr_o[same], axis=1) / np.maximum(1.0, np.linalg.norm(gr_o[same], axis=1))
+        assert nrm.max() <= (1e-9 if prec == 0 else 1e-3)
+
+
+def test_mutate_not_pd_leaves_state():
+    need_gpu()
+    import torch
+    sps = _sps()
+    X, y, _ = dataset(100, 5, 2, seed=24)
+    ctx = make_ctx(X, y, 2)
+    base = synth.make_particles(3, 5, seed=25)
+    th = to_gpu(np.repeat(base, 32, axis=0))
+    ll = torch.zeros(96, dtype=torch.float64, device="cuda")
+    before = th.clone()
+    with pytest.raises(sps.SpsError) as e:
+        sps.sps_mutate(ctx, th, ll, None, 3, 32, 100, 0.5, 0, 0, seed=1, stream=2)
+    assert e.value.status == sps.SPS_ERR_NOT_PD
+    assert torch.equal(th, before)
+
+
+# ------------------------------------------------------------------ moments
+def test_monitor_and_moments_match_oracle(orc):
+    need_gpu()
+    sps = _sps()
+    X, y, _ = dataset(300, 4, 3, seed=26)
+    ctx = make_ctx(X, y, 3)
+    J, N = 16, 250
+    th = synth.make_particles(J * N, 8, scale=0.7, seed=27, center=np.linspace(-1, 1, 8))
+    g = sps.sps_monitor(ctx, to_gpu(th))
+    xbar = X.mean(0)
+    ref_g = np.concatenate([th, th[:, :4] @ xbar[:, None], th[:, 4:] @ xbar[:, None]], axis=1)
+    assert np.allclose(g.cpu().numpy(), ref_g, rtol=1e-13, atol=1e-13)
+    mean, sd, nse, rne = sps.sps_moments(ctx, g, J, N)
+    rm, rs, rn, rr = orc.moments(ref_g, J, N)
+    assert np.allclose(mean, rm, rtol=1e-12, atol=1e-13)
+    assert np.allclose(sd, rs, rtol=1e-9)
+    assert np.allclose(nse, rn, rtol=1e-9)
+    assert np.allclose(rne, rr, rtol=1e-9)

@@ -1,0 +1,72 @@
+"""End-to-end: the adaptive SPS on the GPU against the oracle's own SPS
+driver (independent runs, different seeds).  Posterior means and the log
+marginal likelihood must agree within the combined numerical standard
+errors; both must agree with quadrature where it is available."""
+import math
+
+import numpy as np
+import pytest
+from scipy import integrate, special, stats
+
+from gpu_common import need_gpu
+from paper_1304_4333_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _z(a, b, na, nb):
+    return np.abs(a - b) / np.sqrt(na ** 2 + nb ** 2)
+
+
+@pytest.mark.parametrize("prec,kind", [("fp64", "rw"), ("fp32", "rw"), ("bf16x3", "mala")])
+def test_sps_small_workload_vs_oracle(orc, prec, kind):
+    need_gpu()
+    from paper_1304_4333_amd import driver
+    w = synth.workload("small")
+    X, y, _ = synth.make_data(w)
+    J, N = 16, 256
+    cfg = driver.SpsConfig(J=J, N=N, precision=prec, seed=11) if kind == "rw" else \
+        driver.SpsConfig.mala_defaults(J=J, N=N, precision=prec, seed=11)
+    print(f"sps small prec={prec} kind={kind}", flush=True)
+    ctx = driver.setup(X, y, w.C, 0.0, w.prior_sd)
+    g = driver.run_sps(ctx, cfg)
+    okw = dict(kind=orc.MALA if kind == "mala" else orc.RW)
+    if kind == "mala":
+        okw.update(h_min=0.01, h_max=2.0, acc_target=0.574)
+    o = orc.sps_run(X, y, w.C, 0.0, w.prior_sd, J, N, seed=12, **okw)
+    assert g["hit_R_max"] == 0
+    z = _z(g["mean"], o["mean"], g["nse"], o["nse"])
+    print("z-scores of the monitored means:", np.round(z, 2))
+    assert z.max() < 4.0
+    zl = abs(g["logml"] - o["logml"]) / math.hypot(g["logml_nse"], o["logml_nse"])
+    print("logML gpu %.4f [%.4f] oracle %.4f [%.4f]" % (g["logml"], g["logml_nse"], o["logml"], o["logml_nse"]))
+    assert zl < 4.0
+    assert np.allclose(g["sd"], o["sd"], rtol=0.1)
+
+
+def test_sps_intercept_model_vs_quadrature():
+    need_gpu()
+    from paper_1304_4333_amd import driver
+    T = 60
+    X = np.ones((T, 1))
+    y = (synth.rng(2).random(T) < 0.75).astype(np.int32)
+    m = int(y.sum())
+    f = lambda a: math.exp(stats.norm.logpdf(a, 0, 5) + m * special.log_expit(a) + (T - m) * special.log_expit(-a))
+    Z = integrate.quad(f, -12, 12, epsabs=0, epsrel=1e-12, limit=400)[0]
+    m1 = integrate.quad(lambda a: a * f(a), -12, 12, epsabs=0, epsrel=1e-12, limit=400)[0] / Z
+    ctx = driver.setup(X, y, 2, 0.0, 5.0)
+    r = driver.run_sps(ctx, driver.SpsConfig(J=16, N=1024, precision="fp64", seed=3))
+    assert abs(r["mean"][0] - m1) < 4 * r["nse"][0] + 1e-4
+    assert abs(r["logml"] - math.log(Z)) < 4 * r["logml_nse"] + 0.01
+
+
+def test_sps_single_observation_logml():
+    """T = 1, binary, symmetric prior: logML = -log 2 exactly."""
+    need_gpu()
+    from paper_1304_4333_amd import driver
+    w = synth.workload("small", T=1)
+    X, y, _ = synth.make_data(w)
+    ctx = driver.setup(X, y, 2, 0.0, 5.0)
+    r = driver.run_sps(ctx, driver.SpsConfig(J=16, N=2048, precision="fp32", seed=4))
+    assert r["cycles"] == 1
+    assert abs(r["logml"] + math.log(2.0)) < 4 * r["logml_nse"] + 1e-12
