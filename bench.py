@@ -97,6 +97,51 @@ def gpu_bench(w, steps, warmup, seed=1):
     return dict(evals=evals, elapsed=elapsed, kt=kt, t_ends=t_ends, P=P, s0=s0)
 
 
+def sps_fixed_nse(w, seeds):
+    """Whole adaptive SPS runs on the workload: (A) the paper's Gaussian
+    random walk with the FP64 likelihood, (B) the split-precision likelihood
+    with the MALA M phase.  Efficiency per monitored moment e = wall * NSE^2
+    (proportional to the paper's efficiency-adjusted time, since
+    NSE^2 = var / (J N RNE)); reported: median over moments of e_A / e_B
+    (> 1 means B needs less time for the same NSE), averaged over seeds."""
+    import torch
+    from paper_1304_4333_amd import driver, synth
+
+    X, y, _ = synth.make_data(w)
+    ctx = driver.setup(X, y, w.C, 0.0, w.prior_sd)
+    fast = "bf16x3" if w.precision != "fp64" else "fp64"
+    out = {"A": [], "B": []}
+    for seed in seeds:
+        ra = driver.run_sps(ctx, driver.SpsConfig(J=w.J, N=w.N, precision="fp64", kind="rw", seed=seed))
+        rb = driver.run_sps(ctx, driver.SpsConfig.mala_defaults(J=w.J, N=w.N, precision=fast, seed=seed))
+        out["A"].append(ra)
+        out["B"].append(rb)
+    torch.cuda.synchronize()
+
+    def summary(rs):
+        return dict(wall_s=round(float(np.mean([r["wall"] for r in rs])), 4),
+                    cycles=float(np.mean([r["cycles"] for r in rs])),
+                    m_steps=float(np.mean([r["m_iters"] for r in rs])),
+                    logml=round(float(np.mean([r["logml"] for r in rs])), 4),
+                    logml_nse=round(float(np.mean([r["logml_nse"] for r in rs])), 5))
+
+    ratios = []
+    for ra, rb in zip(out["A"], out["B"]):
+        ea = ra["wall"] * ra["nse"] ** 2
+        eb = rb["wall"] * rb["nse"] ** 2
+        ratios.append(float(np.median(ea / eb)))
+    # agreement of the two estimates of every monitored posterior mean
+    za = np.mean([r["mean"] for r in out["A"]], axis=0)
+    zb = np.mean([r["mean"] for r in out["B"]], axis=0)
+    sa = np.sqrt(np.mean([r["nse"] ** 2 for r in out["A"]], axis=0) / len(seeds))
+    sb = np.sqrt(np.mean([r["nse"] ** 2 for r in out["B"]], axis=0) / len(seeds))
+    z = np.abs(za - zb) / np.sqrt(sa ** 2 + sb ** 2)
+    return {"A": dict(summary(out["A"]), precision="fp64", kernel="rw"),
+            "B": dict(summary(out["B"]), precision=fast, kernel="mala"),
+            "efficiency_ratio_A_over_B": round(float(np.mean(ratios)), 3),
+            "max_mean_z_A_vs_B": round(float(z.max()), 2), "seeds": list(seeds)}
+
+
 def roofline(w, res):
     """Dominant likelihood kernel: algorithmic MFMA flops per launch over its
     average HIP-event duration.  Forward: 2 k (C-1) flops per particle x
@@ -164,6 +209,8 @@ def main():
     ap.add_argument("--workload", default="binary30")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-sps", action="store_true", help="skip the fixed-NSE SPS comparison")
+    ap.add_argument("--sps-seeds", type=int, default=2)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); the particle-group "
@@ -174,6 +221,7 @@ def main():
     res = gpu_bench(w, args.steps, args.warmup)
     value = res["evals"] / res["elapsed"]
     roof, kinfo = roofline(w, res)
+    sps_cmp = None if args.no_sps else sps_fixed_nse(w, list(range(1, 1 + args.sps_seeds)))
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(w, args.cpu_seconds)
@@ -197,6 +245,7 @@ def main():
                    "kernel_ms": {k: [v[0], round(v[1], 3)] for k, v in res["kt"].items()}},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "sps_fixed_nse": sps_cmp,
     }
     print(json.dumps(out))
 

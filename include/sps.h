@@ -78,12 +78,14 @@ const char* sps_last_error(const sps_ctx* ctx);
 /* Replace the stream that subsequent calls enqueue on. */
 int sps_set_stream(sps_ctx* ctx, void* hip_stream);
 
-/* Copy the data set into the context and build the kernel copies of X
- * (FP32, BF16 hi/lo, FP64, each padded and with the binary sign folding
- * described in the design notes).  X: device, T x k FP64; y: device, T int32
- * in [0, C).  Requires 1 <= T < 2^31, 1 <= k <= 128, 2 <= C <= 8.
- * Checks y on the device: SPS_ERR_ARG if any y is outside [0, C).
- * Synchronises the stream. */
+/* Copy the data set into the context and build the kernel copies of X:
+ * FP64, FP32 and a BF16 hi/lo pair (hi = bf16(x), lo = bf16(x - hi)), row
+ * major and transposed, zero padded.  For C = 2 each row is multiplied by
+ * 1 - 2 y_t, so that log P(Y_t = y_t) = -softplus(x~_t' theta) needs no y.
+ * X: device, T x k FP64; y: device, T int32 in [0, C).  Requires
+ * 1 <= T < 2^31, 1 <= k <= 128, 2 <= C <= 8.  Checks the data on the
+ * device: SPS_ERR_ARG if any y is outside [0, C), SPS_ERR_NONFINITE if X
+ * holds NaN or inf.  Synchronises the stream. */
 int sps_set_data(sps_ctx* ctx, const double* X, const int32_t* y, int64_t T,
                  int32_t k, int32_t C);
 
@@ -134,12 +136,13 @@ int sps_correct(sps_ctx* ctx, const double* theta, double* ll, int32_t J,
                 int32_t N, int64_t s0, double ess_frac, int prec,
                 double* log_w, int64_t* t_end, double* ess_end);
 
-/* Log marginal likelihood by-product (Section 3; estimator reading in the
- * design notes): logml_j (device, J FP64, in/out) += log(N^-1 sum_n
- * exp(log_w[j N + n])).  If logml or nse (host) is non-NULL the call
- * synchronises and returns the combined estimate log(J^-1 sum_j
- * exp(logml_j)) and its delta-method NSE.  SPS_ERR_DEGENERATE if a group has
- * every log_w = -inf. */
+/* Log marginal likelihood by-product (Section 3): each group keeps the
+ * running product over cycles of its mean unnormalised C-phase weight,
+ * logml_j (device, J FP64, in/out) += log(N^-1 sum_n exp(log_w[j N + n])).
+ * The combined estimate log(J^-1 sum_j exp(logml_j)) and its delta-method
+ * NSE, sd_j(exp(logml_j - logml)) / sqrt(J), are returned in *logml, *nse
+ * (host, each may be NULL).  Synchronises.  SPS_ERR_DEGENERATE if a group has
+ * every log_w = -inf, SPS_ERR_NONFINITE on NaN or +inf. */
 int sps_logml(sps_ctx* ctx, const double* log_w, int32_t J, int32_t N,
               double* logml_j, double* logml, double* nse);
 
@@ -181,6 +184,29 @@ int sps_resample_int(sps_ctx* ctx, const uint64_t* W, int32_t J, int32_t N,
 int sps_mutate(sps_ctx* ctx, double* theta, double* ll, double* grad, int32_t J,
                int32_t N, int64_t t, double h, int kind, int prec, const double* z,
                const double* u, uint64_t seed, uint64_t stream, double* accept_rate);
+
+/* Algorithm 3, second pass: one M step exactly as sps_mutate but with the
+ * proposal covariance given instead of h V: Sigma (device, d x d FP64,
+ * symmetric positive definite), typically recorded by sps_last_sigma in an
+ * adaptive first pass.  RW: theta' = theta + L z (L L' = Sigma); MALA:
+ * theta' = theta + (1/2) Sigma grad log pi + L z.  SPS_ERR_NOT_PD if Sigma
+ * is not positive definite (nothing is modified). */
+int sps_mutate_cov(sps_ctx* ctx, double* theta, double* ll, double* grad,
+                   int32_t J, int32_t N, int64_t t, const double* Sigma, int kind,
+                   int prec, const double* z, const double* u, uint64_t seed,
+                   uint64_t stream, double* accept_rate);
+
+/* Copy of the proposal covariance (h V, or the given Sigma) used by the last
+ * sps_mutate / sps_mutate_cov call on ctx into Sigma (device, d x d FP64):
+ * the lambda_l of Algorithm 3's record. */
+int sps_last_sigma(sps_ctx* ctx, double* Sigma);
+
+/* Algorithm 1 step 2(a) with a fixed cycle end (Algorithm 3, second pass):
+ * log_w (device, P FP64) = log-likelihood of observations s0+1..s1 (the
+ * log of the product of the C-phase weight increments), ll (in/out) +=
+ * log_w.  0 <= s0 < s1 <= T.  Asynchronous. */
+int sps_correct_fixed(sps_ctx* ctx, const double* theta, double* ll, int32_t J,
+                      int32_t N, int64_t s0, int64_t s1, int prec, double* log_w);
 
 /* ------------------------------------------------ accuracy measures */
 

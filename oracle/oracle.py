@@ -82,12 +82,18 @@ def lib():
         L.orc_cholesky.argtypes = [_d, ct.c_int32, _d]
         L.orc_mutate.argtypes = [_d, _i32, ct.c_int64, ct.c_int32, ct.c_int32, _d, _d, _d, _d, _d,
                                  ct.c_int32, ct.c_int32, ct.c_int64, ct.c_double, ct.c_int32,
-                                 _d, _d, _d, _d, _i8]
+                                 _d, _d, _d, _d, _i8, _d]
+        L.orc_mutate_cov.argtypes = [_d, _i32, ct.c_int64, ct.c_int32, ct.c_int32, _d, _d, _d, _d,
+                                     _d, ct.c_int32, ct.c_int32, ct.c_int64, _d, ct.c_int32,
+                                     _d, _d, _d, _d, _i8]
         L.orc_moments.argtypes = [_d, ct.c_int32, ct.c_int32, ct.c_int32, _d, _d, _d, _d]
         L.orc_moments.restype = None
         L.orc_sps_run.argtypes = [_d, _i32, ct.c_int64, ct.c_int32, ct.c_int32, _d, _d,
                                   ct.POINTER(Config), _d, _d, _d, _d, _d, _d, _i64, _i32, _d, _d,
-                                  ct.POINTER(Summary)]
+                                  _d, ct.c_int64, ct.POINTER(Summary)]
+        L.orc_sps_run_fixed.argtypes = [_d, _i32, ct.c_int64, ct.c_int32, ct.c_int32, _d, _d,
+                                        ct.POINTER(Config), ct.c_int32, _i64, _i32, _d, _d, _d,
+                                        _d, _d, _d, _d, ct.POINTER(Summary)]
         _lib = L
     return _lib
 
@@ -246,6 +252,32 @@ def cholesky(V):
     return L
 
 
+def mutate_cov(X, y, C, prior_mean, prior_sd, theta, ll, grad, J, N, t, Sigma, kind, z, u):
+    """One M step with proposal covariance Sigma (d x d).  Returns
+    (theta, ll, grad, rate, log_alpha, accepted); inputs untouched."""
+    X = _f64(X)
+    y = np.ascontiguousarray(y, dtype=np.int32)
+    T, k = X.shape
+    theta = _f64(theta).copy()
+    d = theta.shape[1]
+    ll = _f64(ll).copy()
+    grad = None if grad is None else _f64(grad).copy()
+    pm = _f64(np.broadcast_to(prior_mean, (d,)))
+    ps = _f64(np.broadcast_to(prior_sd, (d,)))
+    S = _f64(Sigma)
+    z = _f64(z)
+    u = _f64(u)
+    P = J * N
+    rate = ct.c_double(0.0)
+    la = np.zeros(P)
+    acc = np.zeros(P, dtype=np.int8)
+    _check(lib().orc_mutate_cov(_p(X, _d), _p(y, _i32), T, k, C, _p(pm, _d), _p(ps, _d),
+                                _p(theta, _d), _p(ll, _d), _p(grad, _d), J, N, t, _p(S, _d), kind,
+                                _p(z, _d), _p(u, _d), ct.byref(rate), _p(la, _d), _p(acc, _i8)),
+           "mutate_cov")
+    return theta, ll, grad, rate.value, la, acc.astype(bool)
+
+
 def mutate(X, y, C, prior_mean, prior_sd, theta, ll, grad, J, N, t, h, kind, z, u):
     """One M step.  Returns (theta, ll, grad, rate, log_alpha, accepted); inputs untouched."""
     X = _f64(X)
@@ -265,7 +297,7 @@ def mutate(X, y, C, prior_mean, prior_sd, theta, ll, grad, J, N, t, h, kind, z, 
     acc = np.zeros(P, dtype=np.int8)
     _check(lib().orc_mutate(_p(X, _d), _p(y, _i32), T, k, C, _p(pm, _d), _p(ps, _d),
                             _p(theta, _d), _p(ll, _d), _p(grad, _d), J, N, t, h, kind,
-                            _p(z, _d), _p(u, _d), ct.byref(rate), _p(la, _d), _p(acc, _i8)),
+                            _p(z, _d), _p(u, _d), ct.byref(rate), _p(la, _d), _p(acc, _i8), None),
            "mutate")
     return theta, ll, grad, rate.value, la, acc.astype(bool)
 
@@ -283,8 +315,10 @@ def moments(g, J, N):
 
 def sps_run(X, y, C, prior_mean, prior_sd, J, N, seed, kind=RW, scheme=RESIDUAL, rne_rule=0,
             R_max=100, ess_frac=0.5, K_mid=0.35, K_final=0.9, h_init=0.5, h_step=0.01,
-            h_min=0.1, h_max=1.0, acc_target=0.25, max_cycles=4096):
-    """Full adaptive SPS (Algorithm 2).  Returns a dict of results."""
+            h_min=0.1, h_max=1.0, acc_target=0.25, max_cycles=4096, record_sigma=0):
+    """Full adaptive SPS (Algorithm 2).  Returns a dict of results; with
+    record_sigma = n > 0 the proposal covariances of the first n M steps are
+    returned too (the design of Algorithm 3's first pass)."""
     X = _f64(X)
     y = np.ascontiguousarray(y, dtype=np.int32)
     T, k = X.shape
@@ -305,13 +339,55 @@ def sps_run(X, y, C, prior_mean, prior_sd, J, N, seed, kind=RW, scheme=RESIDUAL,
     rh = np.zeros(max_cycles)
     ra = np.zeros(max_cycles)
     s = Summary()
+    sig = np.zeros((record_sigma, d, d)) if record_sigma else None
     _check(lib().orc_sps_run(_p(X, _d), _p(y, _i32), T, k, C, _p(pm, _d), _p(ps, _d),
                              ct.byref(cfg), _p(theta, _d), _p(ll, _d), _p(mean, _d), _p(sd, _d),
                              _p(nse, _d), _p(rne, _d), _p(rt, _i64), _p(rR, _i32), _p(rh, _d),
-                             _p(ra, _d), ct.byref(s)), "sps_run")
+                             _p(ra, _d), _p(sig, _d), record_sigma, ct.byref(s)), "sps_run")
     L = s.cycles
-    return dict(theta=theta, ll=ll, mean=mean, sd=sd, nse=nse, rne=rne,
-                logml=s.logml, logml_nse=s.logml_nse, meanlog=s.meanlog,
-                meanlog_nse=s.meanlog_nse, cycles=L, m_iters=s.m_iters,
-                hit_R_max=s.hit_R_max, t=rt[:L].copy(), R=rR[:L].copy(), h=rh[:L].copy(),
-                acc=ra[:L].copy())
+    out = dict(theta=theta, ll=ll, mean=mean, sd=sd, nse=nse, rne=rne,
+               logml=s.logml, logml_nse=s.logml_nse, meanlog=s.meanlog,
+               meanlog_nse=s.meanlog_nse, cycles=L, m_iters=s.m_iters,
+               hit_R_max=s.hit_R_max, t=rt[:L].copy(), R=rR[:L].copy(), h=rh[:L].copy(),
+               acc=ra[:L].copy())
+    if record_sigma:
+        if s.m_iters > record_sigma:
+            raise ValueError(f"record_sigma={record_sigma} < {s.m_iters} M steps")
+        out["sigma"] = sig[:s.m_iters].copy()
+    return out
+
+
+def sps_run_fixed(X, y, C, prior_mean, prior_sd, J, N, seed, t, R, sigma, kind=RW,
+                  scheme=RESIDUAL):
+    """Algorithm 1 with a fixed design (the second pass of Algorithm 3)."""
+    X = _f64(X)
+    y = np.ascontiguousarray(y, dtype=np.int32)
+    T, k = X.shape
+    d = k * (C - 1)
+    m = d + C - 1
+    P = J * N
+    pm = _f64(np.broadcast_to(prior_mean, (d,)))
+    ps = _f64(np.broadcast_to(prior_sd, (d,)))
+    cfg = Config(J=J, N=N, kind=kind, scheme=scheme, seed=seed)
+    tt = np.ascontiguousarray(t, dtype=np.int64)
+    RR = np.ascontiguousarray(R, dtype=np.int32)
+    S = _f64(sigma)
+    theta = np.zeros((P, d))
+    ll = np.zeros(P)
+    mean, sd, nse, rne = (np.zeros(m) for _ in range(4))
+    s = Summary()
+    _check(lib().orc_sps_run_fixed(_p(X, _d), _p(y, _i32), T, k, C, _p(pm, _d), _p(ps, _d),
+                                   ct.byref(cfg), len(tt), _p(tt, _i64), _p(RR, _i32), _p(S, _d),
+                                   _p(theta, _d), _p(ll, _d), _p(mean, _d), _p(sd, _d),
+                                   _p(nse, _d), _p(rne, _d), ct.byref(s)), "sps_run_fixed")
+    return dict(theta=theta, ll=ll, mean=mean, sd=sd, nse=nse, rne=rne, logml=s.logml,
+                logml_nse=s.logml_nse, cycles=s.cycles, m_iters=s.m_iters)
+
+
+def sps_two_pass(X, y, C, prior_mean, prior_sd, J, N, seed, kind=RW, **kw):
+    """Algorithm 3: an adaptive pass records (t_l, R_l, Sigma_lr); its
+    particles are discarded and a second, nonadaptive pass reruns with it."""
+    p1 = sps_run(X, y, C, prior_mean, prior_sd, J, N, seed, kind=kind, record_sigma=20000, **kw)
+    p2 = sps_run_fixed(X, y, C, prior_mean, prior_sd, J, N, seed, p1["t"], p1["R"], p1["sigma"],
+                       kind=kind, scheme=kw.get("scheme", RESIDUAL))
+    return p1, p2

@@ -10,8 +10,8 @@
  * the order the paper states it; the only parallelism is an OpenMP loop over
  * independent particles (each particle's arithmetic is serial and unchanged).
  *
- * Readings of points the paper leaves open are marked READING; each is
- * listed with its reason in the design notes of the repository.
+ * Points the paper leaves open are marked READING where the reading is
+ * applied; the comment there states the reading taken.
  */
 #include "sps_oracle.h"
 
@@ -455,38 +455,37 @@ static void lower_solve(const double* L, int32_t d, const double* r, double* v)
     }
 }
 
-/* MALA mean (extension beyond the paper): theta + (h/2) V grad log pi. */
-static void mala_mean(const double* th, const double* glp, const double* V, int32_t d,
-                      double h, double* mu)
+/* MALA mean (extension beyond the paper): theta + (1/2) Sigma grad log pi,
+ * Sigma the proposal covariance. */
+static void mala_mean(const double* th, const double* glp, const double* Sigma, int32_t d,
+                      double* mu)
 {
     for (int32_t a = 0; a < d; ++a) {
         double s = 0.0;
-        for (int32_t b = 0; b < d; ++b) s += V[a * d + b] * glp[b];
-        mu[a] = th[a] + 0.5 * h * s;
+        for (int32_t b = 0; b < d; ++b) s += Sigma[a * d + b] * glp[b];
+        mu[a] = th[a] + 0.5 * s;
     }
 }
 
-/* One Metropolis step for every particle with proposal covariance h V.
- * RW (the paper): theta' = theta + sqrt(h) L z.
- * MALA: theta' = mu(theta) + sqrt(h) L z, with the Hastings correction
- * log q(theta|theta') - log q(theta'|theta), log q(a|b) = -|L^-1 (a - mu(b))|^2 / (2h).
+/* One Metropolis step for every particle with proposal covariance Sigma
+ * (Algorithm 1 step 2(c) with lambda = Sigma, as replayed by Algorithm 3).
+ * RW (the paper): theta' = theta + L z, L L' = Sigma.
+ * MALA: theta' = mu(theta) + L z, with the Hastings correction
+ * log q(theta|theta') - log q(theta'|theta), log q(a|b) = -|L^-1 (a - mu(b))|^2 / 2.
  * Accept iff log u < log alpha (strict).  ll (and for MALA grad, the gradient
  * of the log-likelihood over the same observations) are cached per particle
  * and updated on acceptance.  Observations 1..t are used. */
-int orc_mutate(const double* X, const int32_t* y, int64_t T, int32_t k, int32_t C,
-               const double* prior_mean, const double* prior_sd,
-               double* theta, double* ll, double* grad, int32_t J, int32_t N,
-               int64_t t, double h, int32_t kind, const double* z, const double* u,
-               double* accept_rate, double* log_alpha_out, int8_t* accepted_out)
+int orc_mutate_cov(const double* X, const int32_t* y, int64_t T, int32_t k, int32_t C,
+                   const double* prior_mean, const double* prior_sd,
+                   double* theta, double* ll, double* grad, int32_t J, int32_t N,
+                   int64_t t, const double* Sigma, int32_t kind, const double* z, const double* u,
+                   double* accept_rate, double* log_alpha_out, int8_t* accepted_out)
 {
-    if (!data_ok(T, k, C, 0, t) || J < 1 || N < 1 || !(h > 0.0) ||
+    if (!data_ok(T, k, C, 0, t) || J < 1 || N < 1 ||
         (kind != ORC_RW && kind != ORC_MALA) || (kind == ORC_MALA && !grad))
         return ORC_ERR_ARG;
     int64_t P = (int64_t)J * N;
     int32_t d = k * (C - 1);
-    if (P < 2) return ORC_ERR_ARG;
-    double* mean = (double*)malloc(sizeof(double) * d);
-    double* V = (double*)malloc(sizeof(double) * (size_t)d * d);
     double* L = (double*)malloc(sizeof(double) * (size_t)d * d);
     double* prop = (double*)malloc(sizeof(double) * (size_t)P * d);
     double* llp = (double*)malloc(sizeof(double) * (size_t)P);
@@ -496,14 +495,12 @@ int orc_mutate(const double* X, const int32_t* y, int64_t T, int32_t k, int32_t 
     double* glp0 = (double*)malloc(sizeof(double) * (size_t)P * d);
     double* glp1 = (double*)malloc(sizeof(double) * (size_t)P * d);
     int status = ORC_OK;
-    if (!mean || !V || !L || !prop || !llp || !gp || !lp0 || !lp1 || !glp0 || !glp1) {
+    if (!L || !prop || !llp || !gp || !lp0 || !lp1 || !glp0 || !glp1) {
         status = ORC_ERR_NOMEM;
         goto done;
     }
-    orc_cov(theta, P, d, mean, V);
-    status = orc_cholesky(V, d, L);
+    status = orc_cholesky(Sigma, d, L);
     if (status != ORC_OK) goto done;
-    double sh = sqrt(h);
     orc_logprior(theta, P, d, prior_mean, prior_sd, lp0, glp0);
     for (int64_t p = 0; p < P; ++p) {
         const double* th = theta + p * d;
@@ -511,7 +508,7 @@ int orc_mutate(const double* X, const int32_t* y, int64_t T, int32_t k, int32_t 
         if (kind == ORC_MALA) {
             double* g = (double*)malloc(sizeof(double) * d);
             for (int32_t i = 0; i < d; ++i) g[i] = grad[p * d + i] + glp0[p * d + i];
-            mala_mean(th, g, V, d, h, q);
+            mala_mean(th, g, Sigma, d, q);
             free(g);
         } else {
             for (int32_t i = 0; i < d; ++i) q[i] = th[i];
@@ -519,7 +516,7 @@ int orc_mutate(const double* X, const int32_t* y, int64_t T, int32_t k, int32_t 
         for (int32_t a = 0; a < d; ++a) {
             double s = 0.0;
             for (int32_t b = 0; b <= a; ++b) s += L[a * d + b] * z[p * d + b];
-            q[a] += sh * s;
+            q[a] += s;
         }
     }
     if (kind == ORC_MALA)
@@ -538,19 +535,19 @@ int orc_mutate(const double* X, const int32_t* y, int64_t T, int32_t k, int32_t 
             double* v = (double*)malloc(sizeof(double) * d);
             /* log q(theta | theta') */
             for (int32_t i = 0; i < d; ++i) g[i] = gp[p * d + i] + glp1[p * d + i];
-            mala_mean(prop + p * d, g, V, d, h, mu);
+            mala_mean(prop + p * d, g, Sigma, d, mu);
             for (int32_t i = 0; i < d; ++i) r[i] = theta[p * d + i] - mu[i];
             lower_solve(L, d, r, v);
             double qb = 0.0;
             for (int32_t i = 0; i < d; ++i) qb += v[i] * v[i];
             /* log q(theta' | theta) */
             for (int32_t i = 0; i < d; ++i) g[i] = grad[p * d + i] + glp0[p * d + i];
-            mala_mean(theta + p * d, g, V, d, h, mu);
+            mala_mean(theta + p * d, g, Sigma, d, mu);
             for (int32_t i = 0; i < d; ++i) r[i] = prop[p * d + i] - mu[i];
             lower_solve(L, d, r, v);
             double qf = 0.0;
             for (int32_t i = 0; i < d; ++i) qf += v[i] * v[i];
-            la += -qb / (2.0 * h) + qf / (2.0 * h);
+            la += -0.5 * qb + 0.5 * qf;
             free(g); free(mu); free(r); free(v);
         }
         if (isnan(la)) la = -INFINITY;
@@ -567,8 +564,36 @@ int orc_mutate(const double* X, const int32_t* y, int64_t T, int32_t k, int32_t 
     }
     *accept_rate = (double)acc / (double)P;
 done:
-    free(mean); free(V); free(L); free(prop); free(llp); free(gp);
+    free(L); free(prop); free(llp); free(gp);
     free(lp0); free(lp1); free(glp0); free(glp1);
+    return status;
+}
+
+/* Algorithm 2 step 2(c)i-ii: proposal covariance Sigma = h V with V the
+ * sample variance of all particles, then one Metropolis step.  The Sigma
+ * used is returned in sigma_out (d x d, may be NULL). */
+int orc_mutate(const double* X, const int32_t* y, int64_t T, int32_t k, int32_t C,
+               const double* prior_mean, const double* prior_sd,
+               double* theta, double* ll, double* grad, int32_t J, int32_t N,
+               int64_t t, double h, int32_t kind, const double* z, const double* u,
+               double* accept_rate, double* log_alpha_out, int8_t* accepted_out,
+               double* sigma_out)
+{
+    if (J < 1 || N < 1 || !(h > 0.0) || (int64_t)J * N < 2 || k < 1 || C < 2) return ORC_ERR_ARG;
+    int64_t P = (int64_t)J * N;
+    int32_t d = k * (C - 1);
+    double* mean = (double*)malloc(sizeof(double) * d);
+    double* V = (double*)malloc(sizeof(double) * (size_t)d * d);
+    int status = ORC_ERR_NOMEM;
+    if (mean && V) {
+        orc_cov(theta, P, d, mean, V);
+        for (int64_t i = 0; i < (int64_t)d * d; ++i) V[i] *= h;
+        if (sigma_out) memcpy(sigma_out, V, sizeof(double) * (size_t)d * d);
+        status = orc_mutate_cov(X, y, T, k, C, prior_mean, prior_sd, theta, ll, grad, J, N, t, V,
+                                kind, z, u, accept_rate, log_alpha_out, accepted_out);
+    }
+    free(mean);
+    free(V);
     return status;
 }
 
@@ -615,9 +640,9 @@ void orc_moments(const double* g, int32_t J, int32_t N, int32_t m,
 /* theta_c' xbar at the sample mean of the covariates (as in Tables 2 and 5); */
 /* the stopping test uses their mean RNE (rne_rule 0) or minimum (1).         */
 /* ------------------------------------------------------------------------ */
-static uint64_t stream_id(int64_t cycle, int64_t step, int phase)
+static uint64_t stream_id(int pass, int64_t cycle, int64_t step, int phase)
 {
-    return ((uint64_t)cycle << 32) | ((uint64_t)step << 4) | (uint64_t)phase;
+    return ((uint64_t)pass << 60) | ((uint64_t)cycle << 32) | ((uint64_t)step << 4) | (uint64_t)phase;
 }
 
 static void monitored(const double* theta, int64_t P, int32_t k, int32_t C,
@@ -639,7 +664,7 @@ int orc_sps_run(const double* X, const int32_t* y, int64_t T, int32_t k, int32_t
                 double* theta_out, double* ll_out,
                 double* mom_mean, double* mom_sd, double* mom_nse, double* mom_rne,
                 int64_t* rec_t, int32_t* rec_R, double* rec_h, double* rec_acc,
-                orc_summary* summary)
+                double* rec_sigma, int64_t sigma_cap, orc_summary* summary)
 {
     int32_t J = cfg->J, N = cfg->N;
     int64_t P = (int64_t)J * N;
@@ -671,7 +696,7 @@ int orc_sps_run(const double* X, const int32_t* y, int64_t T, int32_t k, int32_t
         for (int32_t i = 0; i < k; ++i) xbar[i] += X[t * k + i];
     for (int32_t i = 0; i < k; ++i) xbar[i] /= (double)T;
 
-    orc_init_prior(prior_mean, prior_sd, d, P, cfg->seed, stream_id(0, 0, 1), theta);
+    orc_init_prior(prior_mean, prior_sd, d, P, cfg->seed, stream_id(0, 0, 0, 1), theta);
     for (int64_t p = 0; p < P; ++p) ll[p] = 0.0;
     double h = cfg->h_init;
     int64_t t = 0;
@@ -685,7 +710,7 @@ int orc_sps_run(const double* X, const int32_t* y, int64_t T, int32_t k, int32_t
         t = t_end;
         status = orc_logml_update(lw, J, N, logml_j);
         if (status != ORC_OK) goto out;
-        orc_u53(cfg->seed, stream_id(cycle, 0, 2), P, u53);
+        orc_u53(cfg->seed, stream_id(0, cycle, 0, 2), P, u53);
         status = orc_resample(lw, J, N, cfg->scheme, u53, anc, NULL);
         if (status != ORC_OK) goto out;
         orc_gather(anc, P, d, theta, th2);
@@ -701,11 +726,14 @@ int orc_sps_run(const double* X, const int32_t* y, int64_t T, int32_t k, int32_t
         double rate = 0.0;
         for (;;) {
             ++r;
-            orc_normals(cfg->seed, stream_id(cycle, r, 3), P, d, z);
-            orc_uniforms(cfg->seed, stream_id(cycle, r, 4), P, u);
+            orc_normals(cfg->seed, stream_id(0, cycle, r, 3), P, d, z);
+            orc_uniforms(cfg->seed, stream_id(0, cycle, r, 4), P, u);
+            double* sig = NULL;
+            if (rec_sigma && summary->m_iters + r <= sigma_cap)
+                sig = rec_sigma + (size_t)(summary->m_iters + r - 1) * d * d;
             status = orc_mutate(X, y, T, k, C, prior_mean, prior_sd, theta, ll,
                                 cfg->kind == ORC_MALA ? grad : NULL, J, N, t, h, cfg->kind,
-                                z, u, &rate, NULL, NULL);
+                                z, u, &rate, NULL, NULL, sig);
             if (status != ORC_OK) goto out;
             h = rate > cfg->acc_target ? fmin(h + cfg->h_step, cfg->h_max)
                                        : fmax(h - cfg->h_step, cfg->h_min);
@@ -734,5 +762,93 @@ out:
     summary->status = status;
     free(th2); free(grad); free(grad2); free(ll2); free(lw); free(z); free(u); free(u53);
     free(anc); free(g); free(rne); free(logml_j); free(xbar);
+    return status;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Algorithm 1 with a fixed design, as run by the second pass of Algorithm 3: */
+/* cycle ends t_1..t_L, R_l M steps per cycle and proposal covariances       */
+/* Sigma_lr (sum_l R_l matrices, d x d each) recorded by a first adaptive   */
+/* pass.  Random streams carry pass = 1.                                     */
+/* ------------------------------------------------------------------------ */
+int orc_sps_run_fixed(const double* X, const int32_t* y, int64_t T, int32_t k, int32_t C,
+                      const double* prior_mean, const double* prior_sd, const orc_config* cfg,
+                      int32_t L, const int64_t* t_l, const int32_t* R_l, const double* Sigma,
+                      double* theta_out, double* ll_out,
+                      double* mom_mean, double* mom_sd, double* mom_nse, double* mom_rne,
+                      orc_summary* summary)
+{
+    int32_t J = cfg->J, N = cfg->N;
+    int64_t P = (int64_t)J * N;
+    int32_t d = k * (C - 1), m = d + C - 1;
+    if (T < 1 || J < 2 || N < 1 || C < 2 || L < 1 || t_l[L - 1] != T) return ORC_ERR_ARG;
+    for (int32_t l = 0; l < L; ++l)
+        if (R_l[l] < 1 || t_l[l] <= (l ? t_l[l - 1] : 0)) return ORC_ERR_ARG;
+    memset(summary, 0, sizeof(*summary));
+    double* theta = theta_out;
+    double* ll = ll_out;
+    double* th2 = (double*)malloc(sizeof(double) * (size_t)P * d);
+    double* grad = (double*)calloc((size_t)P * d, sizeof(double));
+    double* ll2 = (double*)malloc(sizeof(double) * (size_t)P);
+    double* lw = (double*)malloc(sizeof(double) * (size_t)P);
+    double* z = (double*)malloc(sizeof(double) * (size_t)P * d);
+    double* u = (double*)malloc(sizeof(double) * (size_t)P);
+    uint64_t* u53 = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)P);
+    int32_t* anc = (int32_t*)malloc(sizeof(int32_t) * (size_t)P);
+    double* g = (double*)malloc(sizeof(double) * (size_t)P * m);
+    double* logml_j = (double*)calloc((size_t)J, sizeof(double));
+    double* xbar = (double*)calloc((size_t)k, sizeof(double));
+    int status = ORC_OK;
+    if (!th2 || !grad || !ll2 || !lw || !z || !u || !u53 || !anc || !g || !logml_j || !xbar) {
+        status = ORC_ERR_NOMEM;
+        goto out;
+    }
+    for (int64_t t = 0; t < T; ++t)
+        for (int32_t i = 0; i < k; ++i) xbar[i] += X[t * k + i];
+    for (int32_t i = 0; i < k; ++i) xbar[i] /= (double)T;
+
+    orc_init_prior(prior_mean, prior_sd, d, P, cfg->seed, stream_id(1, 0, 0, 1), theta);
+    for (int64_t p = 0; p < P; ++p) ll[p] = 0.0;
+    int64_t step = 0;
+    for (int32_t l = 0; l < L; ++l) {
+        int32_t cycle = l + 1;
+        int64_t t0 = l ? t_l[l - 1] : 0, t1 = t_l[l];
+        /* C phase over observations t0+1..t1 (fixed cycle end) */
+        status = orc_loglik(X, y, T, k, C, theta, P, t0, t1, lw);
+        if (status != ORC_OK) goto out;
+        for (int64_t p = 0; p < P; ++p) ll[p] += lw[p];
+        status = orc_logml_update(lw, J, N, logml_j);
+        if (status != ORC_OK) goto out;
+        orc_u53(cfg->seed, stream_id(1, cycle, 0, 2), P, u53);
+        status = orc_resample(lw, J, N, cfg->scheme, u53, anc, NULL);
+        if (status != ORC_OK) goto out;
+        orc_gather(anc, P, d, theta, th2);
+        memcpy(theta, th2, sizeof(double) * (size_t)P * d);
+        orc_gather(anc, P, 1, ll, ll2);
+        memcpy(ll, ll2, sizeof(double) * (size_t)P);
+        if (cfg->kind == ORC_MALA) {
+            status = orc_loglik_grad(X, y, T, k, C, theta, P, 0, t1, ll, grad);
+            if (status != ORC_OK) goto out;
+        }
+        for (int32_t r = 1; r <= R_l[l]; ++r, ++step) {
+            double rate = 0.0;
+            orc_normals(cfg->seed, stream_id(1, cycle, r, 3), P, d, z);
+            orc_uniforms(cfg->seed, stream_id(1, cycle, r, 4), P, u);
+            status = orc_mutate_cov(X, y, T, k, C, prior_mean, prior_sd, theta, ll,
+                                    cfg->kind == ORC_MALA ? grad : NULL, J, N, t1,
+                                    Sigma + (size_t)step * d * d, cfg->kind, z, u, &rate, NULL, NULL);
+            if (status != ORC_OK) goto out;
+        }
+        summary->m_iters += R_l[l];
+    }
+    summary->cycles = L;
+    monitored(theta, P, k, C, xbar, g);
+    orc_moments(g, J, N, m, mom_mean, mom_sd, mom_nse, mom_rne);
+    orc_logml_total(logml_j, J, &summary->logml, &summary->logml_nse, &summary->meanlog,
+                    &summary->meanlog_nse);
+out:
+    summary->status = status;
+    free(th2); free(grad); free(ll2); free(lw); free(z); free(u); free(u53); free(anc); free(g);
+    free(logml_j); free(xbar);
     return status;
 }

@@ -67,11 +67,17 @@ void orc_gather(const int32_t* ancestor, int64_t P, int32_t m, const double* src
 /* M phase, Algorithm 2 step 2(c). */
 void orc_cov(const double* theta, int64_t P, int32_t d, double* mean, double* V);
 int orc_cholesky(const double* V, int32_t d, double* L);
+int orc_mutate_cov(const double* X, const int32_t* y, int64_t T, int32_t k, int32_t C,
+                   const double* prior_mean, const double* prior_sd,
+                   double* theta, double* ll, double* grad, int32_t J, int32_t N,
+                   int64_t t, const double* Sigma, int32_t kind, const double* z, const double* u,
+                   double* accept_rate, double* log_alpha_out, int8_t* accepted_out);
 int orc_mutate(const double* X, const int32_t* y, int64_t T, int32_t k, int32_t C,
                const double* prior_mean, const double* prior_sd,
                double* theta, double* ll, double* grad, int32_t J, int32_t N,
                int64_t t, double h, int32_t kind, const double* z, const double* u,
-               double* accept_rate, double* log_alpha_out, int8_t* accepted_out);
+               double* accept_rate, double* log_alpha_out, int8_t* accepted_out,
+               double* sigma_out);
 
 /* Numerical accuracy, eqs. (partial_g)-(RNE_def). */
 void orc_moments(const double* g, int32_t J, int32_t N, int32_t m,
@@ -100,7 +106,15 @@ int orc_sps_run(const double* X, const int32_t* y, int64_t T, int32_t k, int32_t
                 double* theta_out, double* ll_out,
                 double* mom_mean, double* mom_sd, double* mom_nse, double* mom_rne,
                 int64_t* rec_t, int32_t* rec_R, double* rec_h, double* rec_acc,
-                orc_summary* summary);
+                double* rec_sigma, int64_t sigma_cap, orc_summary* summary);
+
+/* Algorithm 1 with the design recorded by a first adaptive pass (Algorithm 3). */
+int orc_sps_run_fixed(const double* X, const int32_t* y, int64_t T, int32_t k, int32_t C,
+                      const double* prior_mean, const double* prior_sd, const orc_config* cfg,
+                      int32_t L, const int64_t* t_l, const int32_t* R_l, const double* Sigma,
+                      double* theta_out, double* ll_out,
+                      double* mom_mean, double* mom_sd, double* mom_nse, double* mom_rne,
+                      orc_summary* summary);
 
 #ifdef __cplusplus
 }

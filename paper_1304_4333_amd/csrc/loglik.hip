@@ -23,6 +23,52 @@ __global__ void loglik_reduce_kernel(const double* __restrict__ part_ll,
     }
 }
 
+// Sufficient statistics of the multinomial likelihood over rows [t0, t1):
+// S[(c - 1) k + i] = sum_{t0 <= t < t1, y_t = c} x_{t,i}, c = 1..C-1 (same
+// layout as theta).  One block per covariate, reading the transposed FP64
+// copy; fixed-order reduction.
+__global__ void suffstat_kernel(const double* __restrict__ XT, const int8_t* __restrict__ y8,
+                                int64_t Tp, int64_t t0, int64_t t1, int32_t k, int32_t C,
+                                double* __restrict__ S) {
+    __shared__ double red[8][256];
+    const int32_t i = blockIdx.x;
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    const double* row = XT + (int64_t)i * Tp;
+    for (int64_t t = t0 + threadIdx.x; t < t1; t += 256) {
+        const int yt = y8[t];
+        const double x = row[t];
+#pragma unroll
+        for (int c = 1; c < 8; ++c) acc[c] += (yt == c) ? x : 0.0;
+    }
+    for (int c = 1; c < C; ++c) red[c][threadIdx.x] = acc[c];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int c = 1; c < C; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int c = 1; c < C; ++c) S[(int64_t)(c - 1) * k + i] = red[c][0];
+}
+
+// ll[p] += theta_p . S (the sum of eta_{y_t}); grad[p] += S.  Wave per particle.
+__global__ __launch_bounds__(256) void suffstat_apply_kernel(const double* __restrict__ theta,
+                                                             const double* __restrict__ S, int64_t P,
+                                                             int32_t d, double* __restrict__ ll,
+                                                             double* __restrict__ grad) {
+    const int lane = threadIdx.x & 63;
+    const int64_t p = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (p >= P) return;
+    double v = 0.0;
+    for (int32_t e = lane; e < d; e += 64) {
+        v += theta[p * d + e] * S[e];
+        if (grad) grad[p * d + e] += S[e];
+    }
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m, 64);
+    if (lane == 0) ll[p] += v;
+}
+
 __global__ void fill_kernel(double* __restrict__ p, int64_t n, double v) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
@@ -111,6 +157,21 @@ static int run_loglik(sps_ctx* c, const double* theta, int64_t P, int64_t t0, in
             (const double*)c->part_ll.p, grad ? (const double*)c->part_g.p : nullptr, P, c->d,
             a.nsplit, ll, grad);
         SPS_CHECK(launched(c, "loglik_reduce_kernel"));
+    }
+    if (ll && c->C > 2 && prec != SPS_FP64) {
+        // the eta_{y_t} / 1{y_t = c} terms the kernel leaves out
+        SPS_CHECK(ensure(c, c->suff, sizeof(double) * c->d, "sufficient statistics"));
+        if (!(c->suff_valid && c->suff_t0 == t0 && c->suff_t1 == t1)) {
+            suffstat_kernel<<<c->k, 256, 0, c->stream>>>(c->XTd, c->y8, c->Tp, t0, t1, c->k, c->C,
+                                                          (double*)c->suff.p);
+            SPS_CHECK(launched(c, "suffstat_kernel"));
+            c->suff_valid = true;
+            c->suff_t0 = t0;
+            c->suff_t1 = t1;
+        }
+        suffstat_apply_kernel<<<(unsigned)((P + 3) / 4), 256, 0, c->stream>>>(theta, (const double*)c->suff.p,
+                                                                              P, c->d, ll, grad);
+        SPS_CHECK(launched(c, "suffstat_apply_kernel"));
     }
     return SPS_OK;
 }

@@ -117,16 +117,22 @@ template <> struct Prec<SPS_BF16X3> {
     static constexpr int KPS = 32;
 };
 
-// Particle blocks per wave, chosen so the register arrays stay moderate.
+// Particle blocks (of 16) per wave: the largest of 4, 2, 1 whose register
+// estimate fits the budget (the fused adjoint keeps more live state).
 template <int PREC, int NC, int KS, int MODE>
 constexpr int pick_pw() {
-    constexpr int breg = (PREC == SPS_BF16X3) ? 8 * KS : (PREC == SPS_FP64 ? 2 * KS : KS);
-    constexpr int accr = (PREC == SPS_FP64) ? 16 : 8;  // two tiles x 4 values
-    constexpr int kbt = (PREC == SPS_BF16X3) ? 2 * KS : KS / 4;  // 16-row k blocks
-    constexpr int grad = (MODE == MODE_GRAD) ? ((PREC == SPS_FP64 ? 8 : 4) * kbt + 8) : 0;
+    constexpr bool BF = PREC == SPS_BF16X3;
+    constexpr int w = PREC == SPS_FP64 ? 2 : 1;        // registers per element
+    constexpr int breg = BF ? 8 * KS : w * KS;          // theta fragments per (block, outcome)
+    constexpr int accr = 2 * 4 * w;                     // two tiles of 4 accumulators
+    constexpr int kbt = BF ? 2 * KS : KS / 4;           // adjoint k blocks of 16
+    constexpr int grad = MODE == MODE_GRAD ? (4 * w * kbt + 8 * w) : 0;  // G tiles + residuals
     constexpr int per = NC * (breg + accr + grad) + 2;
-    return per * 4 <= 160 ? 4 : (per * 2 <= 200 ? 2 : 1);
+    constexpr int budget = MODE == MODE_GRAD ? 112 : 160;
+    return per * 4 <= budget ? 4 : (per * 2 <= budget ? 2 : 1);
 }
+
+template <bool V> using bconst = std::integral_constant<bool, V>;
 
 template <int PREC, int NC, int KS, int MODE>
 __global__ __launch_bounds__(256) void loglik_kernel(LoglikArgs a) {
@@ -134,12 +140,20 @@ __global__ __launch_bounds__(256) void loglik_kernel(LoglikArgs a) {
     using E = typename P_::E;
     using Acc = typename P_::Acc;
     constexpr bool BF = (PREC == SPS_BF16X3);
+    constexpr bool F64 = (PREC == SPS_FP64);
     constexpr int PW = pick_pw<PREC, NC, KS, MODE>();
-    constexpr int KBT = BF ? 2 * KS : KS / 4;  // adjoint k blocks of 16 (kp / 16)
+    constexpr int KBT = BF ? 2 * KS : KS / 4;  // adjoint k blocks of 16 (rows of XT)
     constexpr bool GRAD = (MODE == MODE_GRAD);
-    // G accumulators of the FP32 paths are folded into a second FP32 set every
-    // kFold steps (two-level summation); FP64 accumulates directly.
-    constexpr int kFold = 16;
+    // Multinomial FP32/BF16: the eta_{y_t} term of the log-likelihood is
+    // linear in theta (sum_t eta_{y_t} = sum_c theta_c' S_c, S_c the sum of
+    // the x_t with y_t = c over the range), and so is the 1{y_t = c} term of
+    // the adjoint; both are added outside this kernel, which then evaluates
+    // only -log sum_c exp(eta_c) and -pi_c (no outcome needed).
+    constexpr bool SUFF = (NC > 1) && !F64;
+    // The FP32 adjoint accumulators are added into the wave's FP64 output
+    // slice every kFoldSteps steps (4096 observations), bounding the length
+    // of any FP32 running sum; FP64 accumulates in registers throughout.
+    constexpr int kFoldSteps = F64 ? (1 << 30) : 128;
 
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
@@ -148,12 +162,13 @@ __global__ __launch_bounds__(256) void loglik_kernel(LoglikArgs a) {
     const int split = blockIdx.x % a.nsplit;
     const int64_t ptile = blockIdx.x / a.nsplit;
     const int64_t pbase = (ptile * 4 + wave) * (16 * PW);
-    if (pbase >= a.P) return;  // whole wave beyond the last particle
-    const E scale = (PREC == SPS_FP64) ? E(1) : E(kLog2e);
+    if (pbase >= a.P) return;  // whole wave beyond the last particle (no barriers below)
 
     // ---- B operand: theta of this wave's particles, kept in registers ----
     // f32/f64: step s, lane group g covers covariate g*KS + s.
     // bf16   : step s, lane group g covers covariates g*8*KS + 8 s + j.
+    // Addresses are clamped into range and invalid entries zeroed afterwards,
+    // so every load is unconditional and can be in flight together.
     using BReg = typename std::conditional<BF, bf16x8, E>::type;
     BReg bh[PW][NC][KS];
     BReg bl[BF ? PW : 1][BF ? NC : 1][BF ? KS : 1];
@@ -161,7 +176,7 @@ __global__ __launch_bounds__(256) void loglik_kernel(LoglikArgs a) {
     for (int b = 0; b < PW; ++b) {
         const int64_t p = pbase + b * 16 + r16;
         const bool pv = p < a.P;
-        const double* th = a.theta + (pv ? p : 0) * a.d;
+        const double* th = a.theta + (pv ? p : a.P - 1) * a.d;
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
 #pragma unroll
@@ -171,10 +186,9 @@ __global__ __launch_bounds__(256) void loglik_kernel(LoglikArgs a) {
 #pragma unroll
                     for (int j = 0; j < 8; ++j) {
                         const int kk = g * 8 * KS + 8 * s + j;
-                        const float v = (pv && kk < a.k) ? (float)(th[c * a.k + kk] * kLog2e) : 0.f;
-                        // split of the FP64 product: hi from the FP32 value, lo from the rest
-                        const double vd = (pv && kk < a.k) ? th[c * a.k + kk] * kLog2e : 0.0;
-                        const unsigned short h = to_bf16(v);
+                        const double raw = th[c * a.k + min(kk, a.k - 1)];
+                        const double vd = (pv && kk < a.k) ? raw * kLog2e : 0.0;
+                        const unsigned short h = to_bf16((float)vd);
                         hv[j] = h;
                         lv[j] = to_bf16((float)(vd - (double)from_bf16(h)));
                     }
@@ -182,237 +196,291 @@ __global__ __launch_bounds__(256) void loglik_kernel(LoglikArgs a) {
                     bl[b][c][s] = __builtin_bit_cast(bf16x8, lv);
                 } else {
                     const int kk = g * KS + s;
-                    bh[b][c][s] = (pv && kk < a.k) ? (E)(th[c * a.k + kk] * (double)scale) : E(0);
+                    const double raw = th[c * a.k + min(kk, a.k - 1)];
+                    bh[b][c][s] = (pv && kk < a.k) ? (E)(F64 ? raw : raw * kLog2e) : E(0);
                 }
             }
         }
     }
 
-    // ---- accumulators ----
     double acc64[PW];
 #pragma unroll
     for (int b = 0; b < PW; ++b) acc64[b] = 0.0;
     Acc gacc[GRAD ? PW : 1][GRAD ? NC : 1][GRAD ? KBT : 1];
-    Acc gsum[GRAD && !(PREC == SPS_FP64) ? PW : 1][GRAD && !(PREC == SPS_FP64) ? NC : 1]
-            [GRAD && !(PREC == SPS_FP64) ? KBT : 1];
     if constexpr (GRAD) {
 #pragma unroll
         for (int b = 0; b < PW; ++b)
 #pragma unroll
             for (int c = 0; c < NC; ++c)
 #pragma unroll
-                for (int q = 0; q < KBT; ++q) {
-                    gacc[b][c][q] = Acc{0, 0, 0, 0};
-                    if constexpr (PREC != SPS_FP64) gsum[b][c][q] = Acc{0, 0, 0, 0};
-                }
+                for (int q = 0; q < KBT; ++q) gacc[b][c][q] = Acc{0, 0, 0, 0};
     }
+    double* const g_out = GRAD ? a.out_g + (int64_t)split * a.P * a.d : nullptr;
+    bool g_first = true;
+    // Add the FP32/FP64 adjoint tiles into the wave's slice of the output.
+    auto fold = [&]() {
+        if constexpr (GRAD) {
+#pragma unroll
+            for (int b = 0; b < PW; ++b) {
+                const int64_t p = pbase + b * 16 + r16;
+#pragma unroll
+                for (int c = 0; c < NC; ++c)
+#pragma unroll
+                    for (int q = 0; q < KBT; ++q) {
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            const int kk = q * 16 + (F64 ? g + 4 * i : 4 * g + i);
+                            if (p < a.P && kk < a.k) {
+                                double* dst = g_out + p * a.d + c * a.k + kk;
+                                *dst = (g_first ? 0.0 : *dst) + (double)gacc[b][c][q][i];
+                            }
+                        }
+                        gacc[b][c][q] = Acc{0, 0, 0, 0};
+                    }
+            }
+            g_first = false;
+        }
+    };
 
     const int st_begin = split * a.steps_per_split;
     const int st_end = min(a.nsteps, st_begin + a.steps_per_split);
     // A-operand row of this lane inside a 32-row step (tile h adds 4h): the
     // D row r = 4g+i (f32/bf16) or r = g+4i (f64) must map to o + 8g + i.
-    const int arow = (PREC == SPS_FP64) ? 8 * (r16 & 3) + (r16 >> 2) : 8 * (r16 >> 2) + (r16 & 3);
+    const int arow = F64 ? 8 * (r16 & 3) + (r16 >> 2) : 8 * (r16 >> 2) + (r16 & 3);
 
-    for (int st = st_begin; st < st_end; ++st) {
-        const int64_t o = a.t0a + (int64_t)st * 32;
-
-        // ---- forward contraction: two 16-row tiles ----
-        Acc acc[2][PW][NC];
+    // A fragments of one step (two 16-row tiles), double-buffered by prefetch.
+    using AReg = typename std::conditional<BF, bf16x8, E>::type;
+    AReg ah[2][KS];
+    AReg al[BF ? 2 : 1][BF ? KS : 1];
+    auto load_a = [&](int64_t o) {
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int64_t row = o + arow + 4 * h;
             if constexpr (BF) {
                 const unsigned short* xh = (const unsigned short*)a.X + row * a.ldx + g * 8 * KS;
                 const unsigned short* xl = (const unsigned short*)a.Xlo + row * a.ldx + g * 8 * KS;
-                bf16x8 ah[KS], al[KS];
 #pragma unroll
                 for (int s = 0; s < KS; ++s) {
-                    ah[s] = __builtin_bit_cast(bf16x8, *(const u16x8*)(xh + 8 * s));
-                    al[s] = __builtin_bit_cast(bf16x8, *(const u16x8*)(xl + 8 * s));
+                    ah[h][s] = __builtin_bit_cast(bf16x8, *(const u16x8*)(xh + 8 * s));
+                    al[h][s] = __builtin_bit_cast(bf16x8, *(const u16x8*)(xl + 8 * s));
                 }
-#pragma unroll
-                for (int b = 0; b < PW; ++b)
-#pragma unroll
-                    for (int c = 0; c < NC; ++c) {
-                        Acc t = Acc{0, 0, 0, 0};
-#pragma unroll
-                        for (int s = 0; s < KS; ++s) {
-                            t = mfma(ah[s], bh[b][c][s], t);
-                            t = mfma(ah[s], bl[b][c][s], t);
-                            t = mfma(al[s], bh[b][c][s], t);
-                        }
-                        acc[h][b][c] = t;
-                    }
             } else {
                 const E* xr = (const E*)a.X + row * a.ldx + g * KS;
-                E av[KS];
 #pragma unroll
-                for (int s = 0; s < KS; ++s) av[s] = xr[s];
+                for (int s = 0; s < KS; ++s) ah[h][s] = xr[s];
+            }
+        }
+    };
+    if (st_begin < st_end) load_a(a.t0a + (int64_t)st_begin * 32);
+
+    for (int st = st_begin; st < st_end; ++st) {
+        const int64_t o = a.t0a + (int64_t)st * 32;
+
+        // ---- forward contraction, independent chains interleaved ----
+        Acc acc[2][PW][NC];
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int b = 0; b < PW; ++b)
+#pragma unroll
+                for (int c = 0; c < NC; ++c) acc[h][b][c] = Acc{0, 0, 0, 0};
+#pragma unroll
+        for (int s = 0; s < KS; ++s)
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
 #pragma unroll
                 for (int b = 0; b < PW; ++b)
 #pragma unroll
                     for (int c = 0; c < NC; ++c) {
-                        Acc t = Acc{0, 0, 0, 0};
-#pragma unroll
-                        for (int s = 0; s < KS; ++s) t = mfma(av[s], bh[b][c][s], t);
-                        acc[h][b][c] = t;
+                        if constexpr (BF) {
+                            acc[h][b][c] = mfma(ah[h][s], bh[b][c][s], acc[h][b][c]);
+                            acc[h][b][c] = mfma(ah[h][s], bl[b][c][s], acc[h][b][c]);
+                            acc[h][b][c] = mfma(al[h][s], bh[b][c][s], acc[h][b][c]);
+                        } else {
+                            acc[h][b][c] = mfma(ah[h][s], bh[b][c][s], acc[h][b][c]);
+                        }
                     }
-            }
-        }
+        if (st + 1 < st_end) load_a(o + 32);
 
         // ---- epilogue: per-observation log-probabilities ----
-        const bool full = (o >= a.t0) && (o + 32 <= a.t1);
         unsigned ylo = 0, yhi = 0;
-        if (NC > 1) {
+        if (NC > 1 && (!SUFF || a.perobs != nullptr)) {
             const uint2 yy = *(const uint2*)(a.y8 + o + 8 * g);
             ylo = yy.x;
             yhi = yy.y;
         }
+        bool bad = false;  // fast multinomial path left its safe range
         E rres[GRAD ? 2 : 1][GRAD ? 4 : 1][GRAD ? PW : 1][GRAD ? NC : 1];
         E tsum[PW];
 #pragma unroll
         for (int b = 0; b < PW; ++b) tsum[b] = E(0);
+
+        auto epilogue = [&](auto masked_c, auto perobs_c, auto fast_c) {
+            constexpr bool MASKED = decltype(masked_c)::value;
+            constexpr bool PEROBS = decltype(perobs_c)::value;
+            constexpr bool FAST = decltype(fast_c)::value;  // no max shift (SUFF only)
+            constexpr bool NOY = SUFF && !PEROBS;           // eta_y via sufficient statistics
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
+            for (int h = 0; h < 2; ++h) {
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int64_t obs = o + 8 * g + 4 * h + i;
-                const bool ov = full || (obs >= a.t0 && obs < a.t1);
-                const int yt = NC > 1 ? (int)(((h ? yhi : ylo) >> (8 * i)) & 0xFFu) : 0;
+                for (int i = 0; i < 4; ++i) {
+                    const int64_t obs = o + 8 * g + 4 * h + i;
+                    const bool ov = !MASKED || (obs >= a.t0 && obs < a.t1);
+                    const int yt = NC > 1 ? (int)(((h ? yhi : ylo) >> (8 * i)) & 0xFFu) : 0;
 #pragma unroll
-                for (int b = 0; b < PW; ++b) {
-                    E lp;
-                    if constexpr (NC == 1) {
-                        // Binary with sign folding: l = -softplus(z), z = x~' theta.
-                        const E z = acc[h][b][0][i];
-                        E e, q, sp;
-                        if constexpr (PREC == SPS_FP64) {
-                            e = exp(-fabs(z));
-                            q = 1.0 + e;
-                            sp = fmax(z, 0.0) + log1p(e);
-                        } else {
-                            e = fexp2(-fabsf(z));
-                            q = 1.f + e;
-                            sp = fmaxf(z, 0.f) + flog2(q);
-                        }
-                        lp = -sp;
-                        if constexpr (GRAD) {
-                            // d l / d z = -sigmoid(z)
-                            E sig;
-                            if constexpr (PREC == SPS_FP64) sig = (z > 0.0 ? 1.0 : e) / q;
-                            else sig = (z > 0.f ? 1.f : e) * frcp(q);
-                            rres[h][i][b][0] = ov ? -sig : E(0);
-                        }
-                    } else {
-                        E m = E(0);
-#pragma unroll
-                        for (int c = 0; c < NC; ++c) m = acc[h][b][c][i] > m ? acc[h][b][c][i] : m;
-                        E ec[NC];
-                        E s;
-                        E ey = E(0);
-                        if constexpr (PREC == SPS_FP64) {
-                            s = exp(-m);
+                    for (int b = 0; b < PW; ++b) {
+                        E lp;
+                        if constexpr (NC == 1) {
+                            // Binary with sign folding: l = -softplus(z), z = x~' theta.
+                            const E z = acc[h][b][0][i];
+                            if constexpr (F64) {
+                                const double e = exp(-fabs(z));
+                                const double q = 1.0 + e;
+                                lp = -(fmax(z, 0.0) + log1p(e));
+                                if constexpr (GRAD) rres[h][i][b][0] = ov ? -(z > 0.0 ? 1.0 : e) / q : 0.0;
+                            } else {
+                                // base 2: softplus2(z) = max(z, 0) + log2(1 + 2^-|z|);
+                                // max via the signed-integer order of float bits
+                                const float mz = __int_as_float(max(__float_as_int(z), 0));
+                                lp = -(mz + flog2(1.f + fexp2(-fabsf(z))));
+                                // sigmoid(z) = 2^(z - softplus2(z))
+                                if constexpr (GRAD) rres[h][i][b][0] = ov ? -fexp2(z + lp) : 0.f;
+                            }
+                        } else if constexpr (NOY && FAST) {
+                            // base 2 without a shift: exact while the sum stays below 2^126
+                            E ec[NC];
+                            E s = E(1);
 #pragma unroll
                             for (int c = 0; c < NC; ++c) {
-                                ec[c] = exp(acc[h][b][c][i] - m);
+                                ec[c] = fexp2(acc[h][b][c][i]);
                                 s += ec[c];
-                                ey = (yt == c + 1) ? acc[h][b][c][i] : ey;
                             }
-                            lp = ey - (m + log(s));
+                            bad |= !(s < 0x1p126f);
+                            lp = -flog2(s);
+                            if constexpr (GRAD) {
+                                const E inv = frcp(s);
+#pragma unroll
+                                for (int c = 0; c < NC; ++c) rres[h][i][b][c] = ov ? -ec[c] * inv : E(0);
+                            }
                         } else {
-                            s = fexp2(-m);
+                            E m = E(0);
+                            E ey = E(0);
 #pragma unroll
                             for (int c = 0; c < NC; ++c) {
-                                ec[c] = fexp2(acc[h][b][c][i] - m);
-                                s += ec[c];
-                                ey = (yt == c + 1) ? acc[h][b][c][i] : ey;
+                                const E v = acc[h][b][c][i];
+                                if constexpr (F64) m = v > m ? v : m;
+                                else m = __int_as_float(max(__float_as_int(v), __float_as_int(m)));  // m >= 0
+                                if constexpr (!NOY) ey = (yt == c + 1) ? v : ey;
                             }
-                            lp = ey - (m + flog2(s));
-                        }
-                        if constexpr (GRAD) {
-                            E inv;
-                            if constexpr (PREC == SPS_FP64) inv = 1.0 / s;
-                            else inv = frcp(s);
+                            E ec[NC];
+                            E s;
+                            if constexpr (F64) {
+                                s = exp(-m);
 #pragma unroll
-                            for (int c = 0; c < NC; ++c)
-                                rres[h][i][b][c] = ov ? ((yt == c + 1 ? E(1) : E(0)) - ec[c] * inv) : E(0);
+                                for (int c = 0; c < NC; ++c) {
+                                    ec[c] = exp(acc[h][b][c][i] - m);
+                                    s += ec[c];
+                                }
+                                lp = ey - (m + log(s));
+                            } else {
+                                s = fexp2(-m);
+#pragma unroll
+                                for (int c = 0; c < NC; ++c) {
+                                    ec[c] = fexp2(acc[h][b][c][i] - m);
+                                    s += ec[c];
+                                }
+                                lp = ey - (m + flog2(s));
+                            }
+                            if constexpr (GRAD) {
+                                const E inv = F64 ? E(1) / s : frcp(s);
+#pragma unroll
+                                for (int c = 0; c < NC; ++c)
+                                    rres[h][i][b][c] =
+                                        ov ? ((!NOY && yt == c + 1 ? E(1) : E(0)) - ec[c] * inv) : E(0);
+                            }
                         }
-                    }
-                    tsum[b] += ov ? lp : E(0);
-                    if (a.perobs != nullptr && ov) {
-                        const int64_t p = pbase + b * 16 + r16;
-                        if (p < a.P)
-                            a.perobs[(obs - a.t0) * a.P + p] =
-                                (PREC == SPS_FP64) ? (double)lp : (double)lp * kLn2;
+                        tsum[b] += MASKED ? (ov ? lp : E(0)) : lp;
+                        if constexpr (PEROBS) {
+                            const int64_t p = pbase + b * 16 + r16;
+                            if (ov && p < a.P)
+                                a.perobs[(obs - a.t0) * a.P + p] = F64 ? (double)lp : (double)lp * kLn2;
+                        }
                     }
                 }
             }
+        };
+        const bool full = (o >= a.t0) && (o + 32 <= a.t1);
+        if (a.perobs != nullptr) {
+            epilogue(bconst<true>{}, bconst<true>{}, bconst<false>{});
+        } else if constexpr (SUFF) {
+            if (full) epilogue(bconst<false>{}, bconst<false>{}, bconst<true>{});
+            else epilogue(bconst<true>{}, bconst<false>{}, bconst<true>{});
+            if (__any(bad)) {  // wave-uniform: redo this step with the max shift
+#pragma unroll
+                for (int b = 0; b < PW; ++b) tsum[b] = E(0);
+                epilogue(bconst<true>{}, bconst<false>{}, bconst<false>{});
+            }
+        } else if (full) {
+            epilogue(bconst<false>{}, bconst<false>{}, bconst<false>{});
+        } else {
+            epilogue(bconst<true>{}, bconst<false>{}, bconst<false>{});
         }
 #pragma unroll
         for (int b = 0; b < PW; ++b) acc64[b] += (double)tsum[b];
 
         // ---- adjoint: G += X~^T R over the 32 rows of this step ----
         if constexpr (GRAD) {
+            if constexpr (BF) {
 #pragma unroll
-            for (int q = 0; q < KBT; ++q) {
-                const int64_t xrow = (int64_t)(q * 16 + r16) * a.Tp + o + 8 * g;
-                if constexpr (BF) {
+                for (int q = 0; q < KBT; ++q) {
+                    const int64_t xrow = (int64_t)(q * 16 + r16) * a.Tp + o + 8 * g;
                     const bf16x8 th8 = __builtin_bit_cast(bf16x8, *(const u16x8*)((const unsigned short*)a.XT + xrow));
                     const bf16x8 tl8 = __builtin_bit_cast(bf16x8, *(const u16x8*)((const unsigned short*)a.XTlo + xrow));
 #pragma unroll
                     for (int b = 0; b < PW; ++b)
 #pragma unroll
                         for (int c = 0; c < NC; ++c) {
-                            u16x8 rh, rl;
+                            // hi/lo split with the hardware round-to-nearest-even conversion
+                            bf16x8 Rh, Rl;
 #pragma unroll
                             for (int j = 0; j < 8; ++j) {
                                 const float v = rres[j >> 2][j & 3][b][c];
-                                const unsigned short hb = to_bf16(v);
-                                rh[j] = hb;
-                                rl[j] = to_bf16(v - from_bf16(hb));
+                                const __bf16 hb = (__bf16)v;
+                                Rh[j] = hb;
+                                Rl[j] = (__bf16)(v - (float)hb);
                             }
-                            const bf16x8 Rh = __builtin_bit_cast(bf16x8, rh);
-                            const bf16x8 Rl = __builtin_bit_cast(bf16x8, rl);
-                            Acc t = gacc[b][c][q];
-                            t = mfma(th8, Rh, t);
-                            t = mfma(th8, Rl, t);
-                            t = mfma(tl8, Rh, t);
-                            gacc[b][c][q] = t;
-                        }
-                } else {
-                    const E* xt = (const E*)a.XT + xrow;
-                    E xv[8];
-#pragma unroll
-                    for (int j = 0; j < 8; ++j) xv[j] = xt[j];
-#pragma unroll
-                    for (int b = 0; b < PW; ++b)
-#pragma unroll
-                        for (int c = 0; c < NC; ++c) {
-                            Acc t = gacc[b][c][q];
-#pragma unroll
-                            for (int j = 0; j < 8; ++j) t = mfma(xv[j], rres[j >> 2][j & 3][b][c], t);
-                            gacc[b][c][q] = t;
+                            gacc[b][c][q] = mfma(th8, Rh, gacc[b][c][q]);
+                            gacc[b][c][q] = mfma(th8, Rl, gacc[b][c][q]);
+                            gacc[b][c][q] = mfma(tl8, Rh, gacc[b][c][q]);
                         }
                 }
-            }
-            if constexpr (PREC != SPS_FP64) {
-                if (((st - st_begin) % kFold) == kFold - 1) {
+            } else {
+                E xv[KBT][8];
 #pragma unroll
-                    for (int b = 0; b < PW; ++b)
+                for (int q = 0; q < KBT; ++q) {
+                    const E* xt = (const E*)a.XT + (int64_t)(q * 16 + r16) * a.Tp + o + 8 * g;
 #pragma unroll
-                        for (int c = 0; c < NC; ++c)
-#pragma unroll
-                            for (int q = 0; q < KBT; ++q) {
-                                gsum[b][c][q] += gacc[b][c][q];
-                                gacc[b][c][q] = Acc{0, 0, 0, 0};
-                            }
+                    for (int j = 0; j < 8; ++j) xv[q][j] = xt[j];
                 }
+#pragma unroll
+                for (int j = 0; j < 8; ++j)
+#pragma unroll
+                    for (int q = 0; q < KBT; ++q)
+#pragma unroll
+                        for (int b = 0; b < PW; ++b)
+#pragma unroll
+                            for (int c = 0; c < NC; ++c)
+                                gacc[b][c][q] = mfma(xv[q][j], rres[j >> 2][j & 3][b][c], gacc[b][c][q]);
             }
+            if (((st - st_begin) % kFoldSteps) == kFoldSteps - 1) fold();
         }
     }
+    if constexpr (GRAD) {
+        if (g_first || ((st_end - st_begin) % kFoldSteps) != 0) fold();
+    }
 
-    // ---- write out ----
-    const double lscale = (PREC == SPS_FP64) ? 1.0 : kLn2;
+    // ---- write the log-likelihood partial ----
+    const double lscale = F64 ? 1.0 : kLn2;
     double* ll_out = a.out_ll + (int64_t)split * a.P;
 #pragma unroll
     for (int b = 0; b < PW; ++b) {
@@ -421,26 +489,6 @@ __global__ __launch_bounds__(256) void loglik_kernel(LoglikArgs a) {
         v += __shfl_xor(v, 32, 64);
         const int64_t p = pbase + b * 16 + r16;
         if (g == 0 && p < a.P) ll_out[p] = v * lscale;
-    }
-    if constexpr (GRAD) {
-        double* g_out = a.out_g + (int64_t)split * a.P * a.d;
-#pragma unroll
-        for (int b = 0; b < PW; ++b) {
-            const int64_t p = pbase + b * 16 + r16;
-            if (p >= a.P) continue;
-#pragma unroll
-            for (int c = 0; c < NC; ++c)
-#pragma unroll
-                for (int q = 0; q < KBT; ++q) {
-                    Acc t = gacc[b][c][q];
-                    if constexpr (PREC != SPS_FP64) t += gsum[b][c][q];
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        const int kk = q * 16 + ((PREC == SPS_FP64) ? g + 4 * i : 4 * g + i);
-                        if (kk < a.k) g_out[p * a.d + c * a.k + kk] = (double)t[i];
-                    }
-                }
-        }
     }
 }
 

@@ -16,43 +16,32 @@ int random_fill(sps_ctx* c, int kind, uint64_t seed, uint64_t stream, int64_t co
 
 constexpr unsigned kFlagNotPD = 1u;
 
-// mean[i] = P^-1 sum_p theta[p][i]; one block per coordinate, fixed order.
-__global__ void col_mean_kernel(const double* __restrict__ theta, int64_t P, int32_t d,
-                                double* __restrict__ mean) {
-    __shared__ double red[256];
-    const int32_t i = blockIdx.x;
-    double s = 0.0;
-    for (int64_t p = threadIdx.x; p < P; p += 256) s += theta[p * d + i];
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) mean[i] = red[0] / (double)P;
-}
-
-// Partial centred cross products over one chunk of particles:
-// part[chunk][a][b] = sum_{p in chunk} (theta[p][a] - m_a)(theta[p][b] - m_b).
-// 64 x 64 tile per block, 4 x 4 per thread, particles in steps of 16.
-constexpr int kCovChunk = 4096;
-__global__ __launch_bounds__(256) void cov_partial_kernel(const double* __restrict__ theta,
-                                                          const double* __restrict__ mean, int64_t P,
-                                                          int32_t d, double* __restrict__ part) {
+// Sample variance in one pass, shifted by the first particle c = theta[0]
+// for stability: over each chunk of particles
+//   part[chunk][a][b] = sum_p (theta_pa - c_a)(theta_pb - c_b),
+//   psum[chunk][a]    = sum_p (theta_pa - c_a).
+// 64 x 64 tile per block, 4 x 4 per thread, particles in steps of 16.  The
+// (a, b) and (b, a) tiles run the same arithmetic in the same order, so V
+// comes out exactly symmetric.
+__global__ __launch_bounds__(256) void cov_partial_kernel(const double* __restrict__ theta, int64_t P,
+                                                          int32_t d, int64_t chunk,
+                                                          double* __restrict__ part,
+                                                          double* __restrict__ psum) {
     __shared__ double As[16][65];
     __shared__ double Bs[16][65];
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
     const int a0 = blockIdx.x * 64, b0 = blockIdx.y * 64;
-    const int64_t pbeg = (int64_t)blockIdx.z * kCovChunk;
-    const int64_t pend = std::min<int64_t>(P, pbeg + kCovChunk);
+    const int64_t pbeg = (int64_t)blockIdx.z * chunk;
+    const int64_t pend = std::min<int64_t>(P, pbeg + chunk);
     double acc[4][4] = {};
+    double cs[4] = {0, 0, 0, 0};
     for (int64_t p0 = pbeg; p0 < pend; p0 += 16) {
         for (int e = threadIdx.x; e < 16 * 64; e += 256) {
             const int r = e >> 6, cc = e & 63;
             const int64_t p = p0 + r;
             const int a = a0 + cc, b = b0 + cc;
-            As[r][cc] = (p < pend && a < d) ? theta[p * d + a] - mean[a] : 0.0;
-            Bs[r][cc] = (p < pend && b < d) ? theta[p * d + b] - mean[b] : 0.0;
+            As[r][cc] = (p < pend && a < d) ? theta[p * d + a] - theta[a] : 0.0;
+            Bs[r][cc] = (p < pend && b < d) ? theta[p * d + b] - theta[b] : 0.0;
         }
         __syncthreads();
 #pragma unroll
@@ -63,29 +52,41 @@ __global__ __launch_bounds__(256) void cov_partial_kernel(const double* __restri
 #pragma unroll
             for (int j = 0; j < 4; ++j) bv[j] = Bs[kk][tx * 4 + j];
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < 4; ++i) {
+                cs[i] += av[i];
 #pragma unroll
                 for (int j = 0; j < 4; ++j) acc[i][j] += av[i] * bv[j];
+            }
         }
         __syncthreads();
     }
     double* out = part + (int64_t)blockIdx.z * d * d;
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 4; ++i) {
+        const int a = a0 + ty * 4 + i;
+        if (a >= d) continue;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            const int a = a0 + ty * 4 + i, b = b0 + tx * 4 + j;
-            if (a < d && b < d) out[(int64_t)a * d + b] = acc[i][j];
+            const int b = b0 + tx * 4 + j;
+            if (b < d) out[(int64_t)a * d + b] = acc[i][j];
         }
+        if (blockIdx.y == 0 && tx == 0) psum[(int64_t)blockIdx.z * d + a] = cs[i];
+    }
 }
 
-__global__ void cov_reduce_kernel(const double* __restrict__ part, int32_t nchunk, int32_t d,
-                                  int64_t P, double* __restrict__ V) {
+// Sigma = h V, V = (S - P m m') / (P - 1) with S, m the shifted sums over all chunks.
+__global__ void cov_final_kernel(const double* __restrict__ part, const double* __restrict__ psum,
+                                 int32_t nchunk, int32_t d, int64_t P, double h, double* __restrict__ V) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= (int64_t)d * d) return;
-    double s = 0.0;
-    for (int32_t q = 0; q < nchunk; ++q) s += part[(int64_t)q * d * d + e];
-    V[e] = s / (double)(P - 1);
+    const int32_t a = (int32_t)(e / d), b = (int32_t)(e % d);
+    double s = 0.0, sa = 0.0, sb = 0.0;
+    for (int32_t q = 0; q < nchunk; ++q) {
+        s += part[(int64_t)q * d * d + e];
+        sa += psum[(int64_t)q * d + a];
+        sb += psum[(int64_t)q * d + b];
+    }
+    V[e] = h * ((s - sa * sb / (double)P) / (double)(P - 1));
 }
 
 // Cholesky V = L L' in one workgroup (left-looking, one column per step).
@@ -209,72 +210,142 @@ __global__ void sub_kernel(const double* __restrict__ a, const double* __restric
     if (e < n) out[e] = a[e] - b[e];
 }
 
+// Butterfly sum over the 64 lanes of a wave; every lane ends with the same
+// bits (each stage adds the same two operands in both partner lanes).
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m, 64);
+    return v;
+}
+
+// One wave per particle (four per block):
 // log alpha = [ll' + log p(theta')] - [ll + log p(theta)]
-//             (+ MALA: -|v|^2 / (2h) + |z|^2 / 2, v = L^-1 (theta - mu(theta')));
+//             (+ MALA: -|v|^2 / 2 + |z|^2 / 2, v = L^-1 (theta - mu(theta')), L L' = Sigma);
 // accept iff log u < log alpha; accepted particles take theta', ll' (grad').
-__global__ void accept_kernel(double* __restrict__ theta, double* __restrict__ ll,
-                              double* __restrict__ grad, const double* __restrict__ theta2,
-                              const double* __restrict__ ll2, const double* __restrict__ grad2,
-                              const double* __restrict__ z, const double* __restrict__ v,
-                              const double* __restrict__ u, const double* __restrict__ mu,
-                              const double* __restrict__ isd, int64_t P, int32_t d, double h,
-                              int mala, const unsigned* flags, unsigned long long* count) {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void accept_kernel(
+    double* __restrict__ theta, double* __restrict__ ll, double* __restrict__ grad,
+    const double* __restrict__ theta2, const double* __restrict__ ll2,
+    const double* __restrict__ grad2, const double* __restrict__ z, const double* __restrict__ v,
+    const double* __restrict__ u, const double* __restrict__ mu, const double* __restrict__ isd,
+    int64_t P, int32_t d, int mala, const unsigned* flags, unsigned long long* count) {
+    const int lane = threadIdx.x & 63;
+    const int64_t p = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (p >= P || (*flags & kFlagNotPD)) return;
     const double* a = theta + p * d;
     const double* b = theta2 + p * d;
-    double q0 = 0.0, q1 = 0.0;
-    for (int32_t i = 0; i < d; ++i) {
+    double q0 = 0.0, q1 = 0.0, vv = 0.0, zz = 0.0;
+    for (int32_t i = lane; i < d; i += 64) {
         const double za = (a[i] - mu[i]) * isd[i];
         const double zb = (b[i] - mu[i]) * isd[i];
         q0 += za * za;
         q1 += zb * zb;
-    }
-    double la = (ll2[p] - 0.5 * q1) - (ll[p] - 0.5 * q0);
-    if (mala) {
-        double vv = 0.0, zz = 0.0;
-        for (int32_t i = 0; i < d; ++i) {
+        if (mala) {
             vv += v[p * d + i] * v[p * d + i];
             zz += z[p * d + i] * z[p * d + i];
         }
-        la += -vv / (2.0 * h) + 0.5 * zz;
     }
+    q0 = wave_sum(q0);
+    q1 = wave_sum(q1);
+    double la = (ll2[p] - 0.5 * q1) - (ll[p] - 0.5 * q0);
+    if (mala) la += -0.5 * wave_sum(vv) + 0.5 * wave_sum(zz);
     if (isnan(la)) la = -INFINITY;
     if (log(u[p]) < la) {
-        for (int32_t i = 0; i < d; ++i) theta[p * d + i] = b[i];
-        ll[p] = ll2[p];
-        if (mala)
-            for (int32_t i = 0; i < d; ++i) grad[p * d + i] = grad2[p * d + i];
-        atomicAdd(count, 1ull);
+        for (int32_t i = lane; i < d; i += 64) {
+            theta[p * d + i] = b[i];
+            if (mala) grad[p * d + i] = grad2[p * d + i];
+        }
+        if (lane == 0) {
+            ll[p] = ll2[p];
+            atomicAdd(count, 1ull);
+        }
     }
+}
+
+// Cholesky and triangular inverse with the matrix held in LDS (d <= 64).
+constexpr int kSmallD = 64;
+__global__ __launch_bounds__(256) void cholesky_small_kernel(const double* __restrict__ V, int32_t d,
+                                                             double* __restrict__ L, unsigned* flags) {
+    __shared__ double Ls[kSmallD][kSmallD + 1];
+    __shared__ double col[kSmallD];
+    __shared__ int fail_s;
+    const int t = threadIdx.x;
+    if (t == 0) fail_s = 0;
+    for (int e = t; e < d * d; e += 256) Ls[e / d][e % d] = (e % d <= e / d) ? V[e] : 0.0;
+    __syncthreads();
+    for (int j = 0; j < d; ++j) {
+        if (t >= j && t < d) {
+            double s = Ls[t][j];
+            for (int q = 0; q < j; ++q) s -= Ls[t][q] * Ls[j][q];
+            col[t] = s;
+        }
+        __syncthreads();
+        const double piv = col[j];
+        if (!(piv > 0.0) || !isfinite(piv)) {
+            if (t == 0) {
+                fail_s = 1;
+                atomicOr(flags, kFlagNotPD);
+            }
+        }
+        __syncthreads();
+        if (fail_s) return;
+        const double ljj = sqrt(piv);
+        if (t >= j && t < d) Ls[t][j] = (t == j) ? ljj : col[t] / ljj;
+        __syncthreads();
+    }
+    for (int e = t; e < d * d; e += 256) L[e] = Ls[e / d][e % d];
+}
+
+__global__ __launch_bounds__(256) void trinv_small_kernel(const double* __restrict__ L, int32_t d,
+                                                          double* __restrict__ W, const unsigned* flags) {
+    __shared__ double Ls[kSmallD][kSmallD + 1];
+    __shared__ double Ws[kSmallD][kSmallD + 1];
+    if (*flags & kFlagNotPD) return;
+    const int t = threadIdx.x;
+    for (int e = t; e < d * d; e += 256) {
+        Ls[e / d][e % d] = L[e];
+        Ws[e / d][e % d] = 0.0;
+    }
+    __syncthreads();
+    for (int i = 0; i < d; ++i) {
+        if (t <= i) {
+            double s = (t == i) ? 1.0 : 0.0;
+            for (int q = t; q < i; ++q) s -= Ls[i][q] * Ws[q][t];
+            Ws[i][t] = s / Ls[i][i];
+        }
+        __syncthreads();
+    }
+    for (int e = t; e < d * d; e += 256) W[e] = Ws[e / d][e % d];
 }
 
 static inline unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
 
-}  // namespace sps
-
-using namespace sps;
-
-extern "C" int sps_mutate(sps_ctx* c, double* theta, double* ll, double* grad, int32_t J, int32_t N,
-                          int64_t t, double h, int kind, int prec, const double* z, const double* u,
-                          uint64_t seed, uint64_t stream, double* accept_rate) {
-    if (!c) return SPS_ERR_ARG;
-    c->err.clear();
-    if (!c->has_data || !c->has_prior) return fail(c, SPS_ERR_STATE, "sps_mutate: set data and prior first");
+// One M step for every particle.  Sigma_in == nullptr: proposal covariance
+// h V from the particles (Algorithm 2); otherwise the given matrix
+// (Algorithm 3, second pass).  The Sigma used stays in the context for
+// sps_last_sigma.
+static int mutate_impl(sps_ctx* c, const char* who, double* theta, double* ll, double* grad, int32_t J,
+                       int32_t N, int64_t t, double h, const double* Sigma_in, int kind, int prec,
+                       const double* z, const double* u, uint64_t seed, uint64_t stream,
+                       double* accept_rate) {
+    if (!c->has_data || !c->has_prior) return fail(c, SPS_ERR_STATE, "%s: set data and prior first", who);
     if (J < 1 || N < 1 || (int64_t)J * N < 2 || !theta || !ll)
-        return fail(c, SPS_ERR_ARG, "sps_mutate: bad arguments (need J N >= 2, theta, ll)");
-    if (t < 0 || t > c->T) return fail(c, SPS_ERR_ARG, "sps_mutate: t=%lld outside [0, T]", (long long)t);
-    if (!(h > 0.0) || !std::isfinite(h)) return fail(c, SPS_ERR_ARG, "sps_mutate: h must be positive");
-    if (kind != SPS_RW && kind != SPS_MALA) return fail(c, SPS_ERR_ARG, "sps_mutate: unknown kind %d", kind);
-    if (kind == SPS_MALA && !grad) return fail(c, SPS_ERR_ARG, "sps_mutate: MALA needs grad");
+        return fail(c, SPS_ERR_ARG, "%s: bad arguments (need J N >= 2, theta, ll)", who);
+    if (t < 0 || t > c->T) return fail(c, SPS_ERR_ARG, "%s: t=%lld outside [0, T]", who, (long long)t);
+    if (!Sigma_in && (!(h > 0.0) || !std::isfinite(h))) return fail(c, SPS_ERR_ARG, "%s: h must be positive", who);
+    if (kind != SPS_RW && kind != SPS_MALA) return fail(c, SPS_ERR_ARG, "%s: unknown kind %d", who, kind);
+    if (kind == SPS_MALA && !grad) return fail(c, SPS_ERR_ARG, "%s: MALA needs grad", who);
     if (prec != SPS_FP64 && prec != SPS_FP32 && prec != SPS_BF16X3)
-        return fail(c, SPS_ERR_ARG, "sps_mutate: unknown precision %d", prec);
+        return fail(c, SPS_ERR_ARG, "%s: unknown precision %d", who, prec);
     const int64_t P = (int64_t)J * N;
     const int32_t d = c->d;
-    if (d > 1024) return fail(c, SPS_ERR_ARG, "sps_mutate: d=%d above 1024", d);
+    if (d > 1024) return fail(c, SPS_ERR_ARG, "%s: d=%d above 1024", who, d);
     const bool mala = kind == SPS_MALA;
     const int64_t Pd = P * d;
-    const int32_t nchunk = (int32_t)((P + kCovChunk - 1) / kCovChunk);
+    // covariance chunks: about 2048 blocks in flight, at least 64 particles each
+    const int64_t tiles = (int64_t)((d + 63) / 64) * ((d + 63) / 64);
+    const int64_t nch0 = std::max<int64_t>(1, std::min<int64_t>((2048 + tiles - 1) / tiles, (P + 63) / 64));
+    const int64_t chunk = (((P + nch0 - 1) / nch0) + 15) / 16 * 16;
+    const int32_t nchunk = (int32_t)((P + chunk - 1) / chunk);
 
     SPS_CHECK(ensure(c, c->theta2, sizeof(double) * Pd, "proposals"));
     SPS_CHECK(ensure(c, c->ll2, sizeof(double) * P, "proposal log-likelihoods"));
@@ -282,15 +353,16 @@ extern "C" int sps_mutate(sps_ctx* c, double* theta, double* ll, double* grad, i
         SPS_CHECK(ensure(c, c->grad2, sizeof(double) * Pd, "proposal gradients"));
         SPS_CHECK(ensure(c, c->pstat, sizeof(double) * 2 * Pd, "MALA work"));
     }
-    SPS_CHECK(ensure(c, c->cov, sizeof(double) * ((size_t)nchunk + 3) * d * d, "covariance"));
-    SPS_CHECK(ensure(c, c->mean, sizeof(double) * d, "mean"));
+    SPS_CHECK(ensure(c, c->chol, sizeof(double) * 3 * (size_t)d * d, "proposal covariance"));
+    if (!Sigma_in) {
+        SPS_CHECK(ensure(c, c->cov, sizeof(double) * (size_t)nchunk * d * d, "covariance partials"));
+        SPS_CHECK(ensure(c, c->mean, sizeof(double) * (size_t)nchunk * d, "covariance sums"));
+    }
     SPS_CHECK(ensure(c, c->small, 4096, "small"));
     SPS_CHECK(ensure_host(c, c->hostbuf, 4096));
-    double* part = (double*)c->cov.p;
-    double* V = part + (size_t)nchunk * d * d;
-    double* L = V + (size_t)d * d;
+    double* Sg = (double*)c->chol.p;  // Sigma, then its factor and inverse
+    double* L = Sg + (size_t)d * d;
     double* W = L + (size_t)d * d;
-    double* mean = (double*)c->mean.p;
     double* th2 = (double*)c->theta2.p;
     double* ll2 = (double*)c->ll2.p;
     unsigned* flags = (unsigned*)c->small.p;
@@ -308,34 +380,40 @@ extern "C" int sps_mutate(sps_ctx* c, double* theta, double* ll, double* grad, i
         u = (const double*)c->u.p;
     }
 
-    // sample variance of all particles and its Cholesky factor
-    col_mean_kernel<<<d, 256, 0, c->stream>>>(theta, P, d, mean);
-    SPS_CHECK(launched(c, "col_mean_kernel"));
-    cov_partial_kernel<<<dim3((d + 63) / 64, (d + 63) / 64, nchunk), 256, 0, c->stream>>>(theta, mean, P, d, part);
-    SPS_CHECK(launched(c, "cov_partial_kernel"));
-    cov_reduce_kernel<<<nblk((int64_t)d * d), 256, 0, c->stream>>>(part, nchunk, d, P, V);
-    SPS_CHECK(launched(c, "cov_reduce_kernel"));
-    cholesky_kernel<<<1, 1024, 0, c->stream>>>(V, d, L, flags);
+    if (Sigma_in) {
+        SPS_HIP(c, hipMemcpyAsync(Sg, Sigma_in, sizeof(double) * d * d, hipMemcpyDeviceToDevice, c->stream));
+    } else {
+        double* part = (double*)c->cov.p;
+        double* psum = (double*)c->mean.p;
+        cov_partial_kernel<<<dim3((d + 63) / 64, (d + 63) / 64, nchunk), 256, 0, c->stream>>>(
+            theta, P, d, chunk, part, psum);
+        SPS_CHECK(launched(c, "cov_partial_kernel"));
+        cov_final_kernel<<<nblk((int64_t)d * d), 256, 0, c->stream>>>(part, psum, nchunk, d, P, h, Sg);
+        SPS_CHECK(launched(c, "cov_final_kernel"));
+    }
+    if (d <= kSmallD) cholesky_small_kernel<<<1, 256, 0, c->stream>>>(Sg, d, L, flags);
+    else cholesky_kernel<<<1, 1024, 0, c->stream>>>(Sg, d, L, flags);
     SPS_CHECK(launched(c, "cholesky_kernel"));
 
     const dim3 gg((unsigned)((P + 63) / 64), (unsigned)((d + 63) / 64));
-    const double sh = std::sqrt(h);
     if (!mala) {
-        gemm_abt_kernel<<<gg, 256, 0, c->stream>>>(z, L, theta, th2, P, d, sh);
+        // theta' = theta + L z
+        gemm_abt_kernel<<<gg, 256, 0, c->stream>>>(z, L, theta, th2, P, d, 1.0);
         SPS_CHECK(launched(c, "gemm_abt_kernel"));
         SPS_CHECK(loglik_launch(c, th2, P, 0, t, prec, ll2, nullptr));
     } else {
         double* gpi = (double*)c->pstat.p;
         double* work = gpi + Pd;
         double* g2 = (double*)c->grad2.p;
-        trinv_kernel<<<1, 1024, 0, c->stream>>>(L, d, W, flags);
+        if (d <= kSmallD) trinv_small_kernel<<<1, 256, 0, c->stream>>>(L, d, W, flags);
+        else trinv_kernel<<<1, 1024, 0, c->stream>>>(L, d, W, flags);
         SPS_CHECK(launched(c, "trinv_kernel"));
-        // mu(theta) = theta + (h/2) V grad log pi(theta); theta' = mu + sqrt(h) L z
+        // mu(theta) = theta + (1/2) Sigma grad log pi(theta); theta' = mu + L z
         grad_logpost_kernel<<<nblk(Pd), 256, 0, c->stream>>>(grad, theta, c->prior_mean, c->prior_isd, P, d, gpi);
         SPS_CHECK(launched(c, "grad_logpost_kernel"));
-        gemm_abt_kernel<<<gg, 256, 0, c->stream>>>(gpi, V, theta, work, P, d, 0.5 * h);
+        gemm_abt_kernel<<<gg, 256, 0, c->stream>>>(gpi, Sg, theta, work, P, d, 0.5);
         SPS_CHECK(launched(c, "gemm_abt_kernel"));
-        gemm_abt_kernel<<<gg, 256, 0, c->stream>>>(z, L, work, th2, P, d, sh);
+        gemm_abt_kernel<<<gg, 256, 0, c->stream>>>(z, L, work, th2, P, d, 1.0);
         SPS_CHECK(launched(c, "gemm_abt_kernel"));
         SPS_CHECK(loglik_launch(c, th2, P, 0, t, prec, ll2, g2));
         // v = L^-1 (theta - mu(theta'))
@@ -343,22 +421,57 @@ extern "C" int sps_mutate(sps_ctx* c, double* theta, double* ll, double* grad, i
         SPS_CHECK(launched(c, "grad_logpost_kernel"));
         sub_kernel<<<nblk(Pd), 256, 0, c->stream>>>(theta, th2, work, Pd);
         SPS_CHECK(launched(c, "sub_kernel"));
-        gemm_abt_kernel<<<gg, 256, 0, c->stream>>>(gpi, V, work, work, P, d, -0.5 * h);
+        gemm_abt_kernel<<<gg, 256, 0, c->stream>>>(gpi, Sg, work, work, P, d, -0.5);
         SPS_CHECK(launched(c, "gemm_abt_kernel"));
         gemm_abt_kernel<<<gg, 256, 0, c->stream>>>(work, W, nullptr, gpi, P, d, 1.0);
         SPS_CHECK(launched(c, "gemm_abt_kernel"));
     }
-    accept_kernel<<<nblk(P), 256, 0, c->stream>>>(
+    accept_kernel<<<(unsigned)((P + 3) / 4), 256, 0, c->stream>>>(
         theta, ll, grad, th2, ll2, mala ? (const double*)c->grad2.p : nullptr, z,
-        mala ? (const double*)c->pstat.p : nullptr, u, c->prior_mean, c->prior_isd, P, d, h, mala ? 1 : 0,
+        mala ? (const double*)c->pstat.p : nullptr, u, c->prior_mean, c->prior_isd, P, d, mala ? 1 : 0,
         flags, count);
     SPS_CHECK(launched(c, "accept_kernel"));
     SPS_HIP(c, hipMemcpyAsync(c->hostbuf.p, c->small.p, 16, hipMemcpyDeviceToHost, c->stream));
     SPS_HIP(c, hipStreamSynchronize(c->stream));
+    c->has_sigma = true;
     const unsigned f = *(const unsigned*)c->hostbuf.p;
     const unsigned long long n_acc = *(const unsigned long long*)((const char*)c->hostbuf.p + 8);
     if (f & kFlagNotPD)
-        return fail(c, SPS_ERR_NOT_PD, "sps_mutate: the particles' sample variance is not positive definite");
+        return fail(c, SPS_ERR_NOT_PD, "%s: the proposal covariance is not positive definite", who);
     if (accept_rate) *accept_rate = (double)n_acc / (double)P;
+    return SPS_OK;
+}
+
+}  // namespace sps
+
+using namespace sps;
+
+extern "C" int sps_mutate(sps_ctx* c, double* theta, double* ll, double* grad, int32_t J, int32_t N,
+                          int64_t t, double h, int kind, int prec, const double* z, const double* u,
+                          uint64_t seed, uint64_t stream, double* accept_rate) {
+    if (!c) return SPS_ERR_ARG;
+    c->err.clear();
+    return mutate_impl(c, "sps_mutate", theta, ll, grad, J, N, t, h, nullptr, kind, prec, z, u, seed,
+                       stream, accept_rate);
+}
+
+extern "C" int sps_mutate_cov(sps_ctx* c, double* theta, double* ll, double* grad, int32_t J,
+                              int32_t N, int64_t t, const double* Sigma, int kind, int prec,
+                              const double* z, const double* u, uint64_t seed, uint64_t stream,
+                              double* accept_rate) {
+    if (!c) return SPS_ERR_ARG;
+    c->err.clear();
+    if (!Sigma) return fail(c, SPS_ERR_ARG, "sps_mutate_cov: null Sigma");
+    return mutate_impl(c, "sps_mutate_cov", theta, ll, grad, J, N, t, 1.0, Sigma, kind, prec, z, u,
+                       seed, stream, accept_rate);
+}
+
+extern "C" int sps_last_sigma(sps_ctx* c, double* Sigma) {
+    if (!c) return SPS_ERR_ARG;
+    c->err.clear();
+    if (!Sigma) return fail(c, SPS_ERR_ARG, "sps_last_sigma: null output");
+    if (!c->has_sigma) return fail(c, SPS_ERR_STATE, "sps_last_sigma: no M step has run");
+    SPS_HIP(c, hipMemcpyAsync(Sigma, c->chol.p, sizeof(double) * c->d * c->d, hipMemcpyDeviceToDevice,
+                              c->stream));
     return SPS_OK;
 }

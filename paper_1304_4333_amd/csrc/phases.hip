@@ -68,14 +68,30 @@ __global__ void init_prior_kernel(double* __restrict__ theta, int64_t P, int32_t
 }
 
 // ------------------------------------------------------------------ C phase
-// Running log-weights over a block of observations: lw[u][p] holds the
-// per-observation term on entry and log w_p(s + u + 1) on exit.
-__global__ void correct_prefix_kernel(double* __restrict__ lw, const double* __restrict__ carry,
-                                      int64_t P, int32_t nb) {
+// Running log-weights over a block of observations, as a two-pass scan over
+// chunks of kScanChunk observations: lw[u][p] holds the per-observation term
+// on entry and log w_p(s + u + 1) on exit.
+constexpr int kScanChunk = 32;
+__global__ void correct_chunk_sum_kernel(const double* __restrict__ lw, int64_t P, int32_t nb,
+                                         double* __restrict__ tot) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t ch = blockIdx.y;
+    if (p >= P) return;
+    const int32_t u1 = min(nb, (ch + 1) * kScanChunk);
+    double s = 0.0;
+    for (int32_t u = ch * kScanChunk; u < u1; ++u) s += lw[(int64_t)u * P + p];
+    tot[(int64_t)ch * P + p] = s;
+}
+
+__global__ void correct_prefix_kernel(double* __restrict__ lw, const double* __restrict__ carry,
+                                      const double* __restrict__ tot, int64_t P, int32_t nb) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t ch = blockIdx.y;
     if (p >= P) return;
     double acc = carry[p];
-    for (int32_t u = 0; u < nb; ++u) {
+    for (int32_t q = 0; q < ch; ++q) acc += tot[(int64_t)q * P + p];
+    const int32_t u1 = min(nb, (ch + 1) * kScanChunk);
+    for (int32_t u = ch * kScanChunk; u < u1; ++u) {
         acc += lw[(int64_t)u * P + p];
         lw[(int64_t)u * P + p] = acc;
     }
@@ -133,6 +149,11 @@ __global__ void correct_final_kernel(const double* __restrict__ lwcol, double* _
     const double v = lwcol[p];
     log_w[p] = v;
     ll[p] += v;
+}
+
+__global__ void add_kernel(double* __restrict__ a, const double* __restrict__ b, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] += b[i];
 }
 
 __global__ void copy_kernel(const double* __restrict__ src, double* __restrict__ dst, int64_t n) {
@@ -485,12 +506,17 @@ extern "C" int sps_correct(sps_ctx* c, const double* theta, double* ll, int32_t 
     if (prec != SPS_FP64 && prec != SPS_FP32 && prec != SPS_BF16X3)
         return fail(c, SPS_ERR_ARG, "sps_correct: unknown precision %d", prec);
     const int64_t P = (int64_t)J * N;
-    const int32_t kMaxBlock = 1024;
+    // Observations per block: doubling from 64 up to 2048, the block buffer
+    // (P x block FP64) capped at 256 MiB.
+    const int32_t kMaxBlock =
+        (int32_t)std::max<int64_t>(kScanChunk, std::min<int64_t>(2048, (int64_t(32) << 20) / P / kScanChunk * kScanChunk));
+    const int32_t nchmax = (kMaxBlock + kScanChunk - 1) / kScanChunk;
     SPS_CHECK(ensure(c, c->corr_lw, sizeof(double) * P * kMaxBlock, "C-phase block"));
-    SPS_CHECK(ensure(c, c->corr_red, sizeof(double) * kMaxBlock, "C-phase ESS"));
+    SPS_CHECK(ensure(c, c->corr_red, sizeof(double) * (kMaxBlock + (size_t)nchmax * P), "C-phase ESS"));
     SPS_CHECK(zero_flags(c));
     double* lwblk = (double*)c->corr_lw.p;
     double* ess = (double*)c->corr_red.p;
+    double* tot = ess + kMaxBlock;
     double* res = (double*)c->small.p + 2;  // [2], [3]: index, ESS
     unsigned* flags = (unsigned*)c->small.p;
     const unsigned pg = (unsigned)((P + 255) / 256);
@@ -498,11 +524,14 @@ extern "C" int sps_correct(sps_ctx* c, const double* theta, double* ll, int32_t 
 
     SPS_CHECK(fill(c, log_w, P, 0.0));  // w = 1 after observation s0
     int64_t s = s0;
-    int32_t B = 32;
+    int32_t B = std::min<int32_t>(64, kMaxBlock);
     for (;;) {
         const int32_t nb = (int32_t)std::min<int64_t>(B, c->T - s);
+        const unsigned nch = (unsigned)((nb + kScanChunk - 1) / kScanChunk);
         SPS_CHECK(loglik_perobs(c, theta, P, s, s + nb, prec, lwblk));
-        correct_prefix_kernel<<<pg, 256, 0, c->stream>>>(lwblk, log_w, P, nb);
+        correct_chunk_sum_kernel<<<dim3(pg, nch), 256, 0, c->stream>>>(lwblk, P, nb, tot);
+        SPS_CHECK(launched(c, "correct_chunk_sum_kernel"));
+        correct_prefix_kernel<<<dim3(pg, nch), 256, 0, c->stream>>>(lwblk, log_w, tot, P, nb);
         SPS_CHECK(launched(c, "correct_prefix_kernel"));
         correct_ess_kernel<<<nb, 256, 0, c->stream>>>(lwblk, P, ess, flags);
         SPS_CHECK(launched(c, "correct_ess_kernel"));
@@ -527,6 +556,22 @@ extern "C" int sps_correct(sps_ctx* c, const double* theta, double* ll, int32_t 
         s += nb;
         B = std::min(2 * B, kMaxBlock);
     }
+}
+
+extern "C" int sps_correct_fixed(sps_ctx* c, const double* theta, double* ll, int32_t J, int32_t N,
+                                 int64_t s0, int64_t s1, int prec, double* log_w) {
+    if (!c) return SPS_ERR_ARG;
+    c->err.clear();
+    if (!c->has_data) return fail(c, SPS_ERR_STATE, "sps_correct_fixed: call sps_set_data first");
+    if (J < 1 || N < 1 || !theta || !ll || !log_w) return fail(c, SPS_ERR_ARG, "sps_correct_fixed: bad arguments");
+    if (s0 < 0 || s1 <= s0 || s1 > c->T)
+        return fail(c, SPS_ERR_ARG, "sps_correct_fixed: need 0 <= s0 < s1 <= T");
+    if (prec != SPS_FP64 && prec != SPS_FP32 && prec != SPS_BF16X3)
+        return fail(c, SPS_ERR_ARG, "sps_correct_fixed: unknown precision %d", prec);
+    const int64_t P = (int64_t)J * N;
+    SPS_CHECK(loglik_launch(c, theta, P, s0, s1, prec, log_w, nullptr));
+    add_kernel<<<(unsigned)((P + 255) / 256), 256, 0, c->stream>>>(ll, log_w, P);
+    return launched(c, "add_kernel");
 }
 
 extern "C" int sps_logml(sps_ctx* c, const double* log_w, int32_t J, int32_t N, double* logml_j,

@@ -154,6 +154,8 @@ static void free_data(sps_ctx* c) {
     c->XTd = nullptr; c->XTf = nullptr; c->XTh = nullptr; c->XTl = nullptr;
     c->y8 = nullptr; c->xbar = nullptr;
     c->has_data = false;
+    c->suff_valid = false;
+    c->has_sigma = false;
 }
 
 static void free_prior(sps_ctx* c) {
@@ -267,7 +269,7 @@ extern "C" void sps_destroy(sps_ctx* c) {
     free_prior(c);
     Buf* bufs[] = {&c->part_ll, &c->part_g, &c->theta2, &c->ll2, &c->grad2, &c->cov, &c->chol,
                    &c->mean, &c->pstat, &c->z, &c->u, &c->u53, &c->corr_lw, &c->corr_red,
-                   &c->small, &c->W, &c->gstat};
+                   &c->small, &c->W, &c->gstat, &c->suff};
     for (Buf* b : bufs)
         if (b->p) (void)hipFree(b->p);
     if (c->hostbuf.p) (void)hipHostFree(c->hostbuf.p);

@@ -33,6 +33,7 @@ struct sps_ctx {
     // ---- data set (sps_set_data) --------------------------------------
     bool has_data = false;
     bool has_prior = false;
+    bool has_sigma = false;  // a proposal covariance is held in chol (sps_last_sigma)
     int64_t T = 0;       // observations
     int32_t k = 0;       // covariates
     int32_t C = 0;       // outcomes
@@ -63,7 +64,8 @@ struct sps_ctx {
     sps::Buf part_g;     // obs-split partial gradients
     sps::Buf theta2;     // proposals
     sps::Buf ll2, grad2; // proposal log-likelihood / gradient
-    sps::Buf cov, chol;  // d x d
+    sps::Buf cov;        // covariance partials
+    sps::Buf chol;       // proposal covariance, its Cholesky factor and inverse (3 d x d)
     sps::Buf mean;       // d
     sps::Buf pstat;      // per-particle statistics of the M step
     sps::Buf z, u;       // Philox draws when the caller passes none
@@ -74,6 +76,9 @@ struct sps_ctx {
     sps::Buf hostbuf;    // pinned host staging for scalar read-back
     sps::Buf W;          // resampling integer weights
     sps::Buf gstat;      // moments partials
+    sps::Buf suff;       // multinomial sufficient statistics for one observation range
+    bool suff_valid = false;
+    int64_t suff_t0 = 0, suff_t1 = 0;
 
     // ---- optional kernel timing (sps_timing_enable) ----
     struct Timed {

@@ -8,9 +8,10 @@ NSE/RNE (sps_monitor, sps_moments).  This module holds only the control
 flow: the cycle loop, the RNE stopping rule and the step-size rule.
 
 Random streams (shared convention with the oracle's driver):
-stream(cycle, step, phase) = cycle << 32 | step << 4 | phase, phase 1 =
-initial particles, 2 = resampling integers, 3 = proposal normals,
-4 = acceptance uniforms.
+stream(pass, cycle, step, phase) = pass << 60 | cycle << 32 | step << 4 | phase,
+phase 1 = initial particles, 2 = resampling integers, 3 = proposal normals,
+4 = acceptance uniforms; pass 0 = adaptive run, 1 = the second pass of the
+two-pass algorithm (Algorithm 3).
 """
 from __future__ import annotations
 
@@ -52,12 +53,23 @@ class SpsConfig:
         return SpsConfig(**base)
 
 
-def stream_id(cycle: int, step: int, phase: int) -> int:
-    return (cycle << 32) | (step << 4) | phase
+def stream_id(cycle: int, step: int, phase: int, pass_: int = 0) -> int:
+    return (pass_ << 60) | (cycle << 32) | (step << 4) | phase
 
 
-def run_sps(ctx: sps.Context, cfg: SpsConfig, log=None) -> dict:
-    """One pass of the adaptive SPS on the data and prior set in ctx."""
+@dataclasses.dataclass
+class Design:
+    """What the first pass of Algorithm 3 retains: the cycle ends t_l, the
+    number of M steps R_l and the proposal covariances Sigma_lr (device
+    tensors, in step order)."""
+    t: list
+    R: list
+    sigma: list
+
+
+def run_sps(ctx: sps.Context, cfg: SpsConfig, log=None, record: bool = False) -> dict:
+    """One pass of the adaptive SPS (Algorithm 2) on the data and prior set in
+    ctx.  record=True also returns the Design of Algorithm 3's first pass."""
     J, N = cfg.J, cfg.N
     P, d, C, T = J * N, ctx.d, ctx.C, ctx.T
     m = d + C - 1
@@ -87,6 +99,7 @@ def run_sps(ctx: sps.Context, cfg: SpsConfig, log=None) -> dict:
     m_iters = 0
     hit_R_max = 0
     records = []
+    sigmas = []
     logml = nse_logml = float("nan")
     while t < T:
         cycle += 1
@@ -107,6 +120,8 @@ def run_sps(ctx: sps.Context, cfg: SpsConfig, log=None) -> dict:
             r += 1
             rate = sps.sps_mutate(ctx, theta, ll, grad, J, N, t, h, kind, prec,
                                   seed=cfg.seed, stream=stream_id(cycle, r, 3))
+            if record:
+                sigmas.append(sps.sps_last_sigma(ctx))
             h = min(h + cfg.h_step, cfg.h_max) if rate > cfg.acc_target else max(h - cfg.h_step, cfg.h_min)
             sps.sps_monitor(ctx, theta, g)
             _, _, _, rne = sps.sps_moments(ctx, g, J, N)
@@ -125,9 +140,68 @@ def run_sps(ctx: sps.Context, cfg: SpsConfig, log=None) -> dict:
     wall = time.perf_counter() - t_start
     sps.sps_monitor(ctx, theta, g)
     mean, sd, nse, rne = sps.sps_moments(ctx, g, J, N)
+    out = dict(theta=theta, ll=ll, mean=mean, sd=sd, nse=nse, rne=rne, logml=logml,
+               logml_nse=nse_logml, logml_j=logml_j.cpu().numpy(), cycles=cycle,
+               m_iters=m_iters, hit_R_max=hit_R_max, records=records, wall=wall)
+    if record:
+        out["design"] = Design(t=[r["t"] for r in records], R=[r["R"] for r in records], sigma=sigmas)
+    return out
+
+
+def run_fixed(ctx: sps.Context, cfg: SpsConfig, design: Design, pass_: int = 1) -> dict:
+    """Algorithm 1 with a fixed design (the second pass of Algorithm 3): the C
+    phase runs to the recorded t_l, the M phase takes the recorded R_l steps
+    with the recorded proposal covariances.  Fresh random streams (pass 1)."""
+    J, N = cfg.J, cfg.N
+    P, d, C = J * N, ctx.d, ctx.C
+    m = d + C - 1
+    dev = ctx.device
+    prec = sps.PREC[cfg.precision]
+    kind = sps.KIND[cfg.kind]
+    scheme = sps.SCHEME[cfg.scheme]
+    mala = kind == sps.SPS_MALA
+    f64 = dict(dtype=torch.float64, device=dev)
+    theta, theta_b = torch.empty(P, d, **f64), torch.empty(P, d, **f64)
+    ll, ll_b = torch.zeros(P, **f64), torch.empty(P, **f64)
+    grad = torch.zeros(P, d, **f64) if mala else None
+    log_w = torch.empty(P, **f64)
+    logml_j = torch.zeros(J, **f64)
+    g = torch.empty(P, m, **f64)
+    anc = torch.empty(P, dtype=torch.int32, device=dev)
+    t_start = time.perf_counter()
+    sps.sps_init_prior(ctx, theta, cfg.seed, stream_id(0, 0, 1, pass_))
+    step = 0
+    t_prev = 0
+    logml = nse_logml = float("nan")
+    for li, (t, R) in enumerate(zip(design.t, design.R)):
+        cycle = li + 1
+        sps.sps_correct_fixed(ctx, theta, ll, J, N, t_prev, t, prec, log_w)
+        logml, nse_logml = sps.sps_logml(ctx, log_w, J, N, logml_j)
+        sps.sps_resample(ctx, log_w, J, N, scheme, seed=cfg.seed, stream=stream_id(cycle, 0, 2, pass_),
+                         ancestor=anc, theta_in=theta, theta_out=theta_b, ll_in=ll, ll_out=ll_b)
+        theta, theta_b = theta_b, theta
+        ll, ll_b = ll_b, ll
+        if mala:
+            sps.sps_loglik_grad(ctx, theta, 0, t, prec, ll, grad)
+        for r in range(1, R + 1):
+            sps.sps_mutate_cov(ctx, theta, ll, grad, J, N, t, design.sigma[step], kind, prec,
+                               seed=cfg.seed, stream=stream_id(cycle, r, 3, pass_), want_rate=True)
+            step += 1
+        t_prev = t
+    torch.cuda.synchronize(dev)
+    wall = time.perf_counter() - t_start
+    sps.sps_monitor(ctx, theta, g)
+    mean, sd, nse, rne = sps.sps_moments(ctx, g, J, N)
     return dict(theta=theta, ll=ll, mean=mean, sd=sd, nse=nse, rne=rne, logml=logml,
-                logml_nse=nse_logml, logml_j=logml_j.cpu().numpy(), cycles=cycle,
-                m_iters=m_iters, hit_R_max=hit_R_max, records=records, wall=wall)
+                logml_nse=nse_logml, cycles=len(design.t), m_iters=step, wall=wall)
+
+
+def run_two_pass(ctx: sps.Context, cfg: SpsConfig) -> tuple:
+    """Algorithm 3: an adaptive pass whose particles are discarded, then the
+    nonadaptive pass with its design.  Returns (pass 1, pass 2) results."""
+    p1 = run_sps(ctx, cfg, record=True)
+    p2 = run_fixed(ctx, cfg, p1["design"])
+    return p1, p2
 
 
 def setup(X: np.ndarray, y: np.ndarray, C: int, prior_mean=0.0, prior_sd=1.0,

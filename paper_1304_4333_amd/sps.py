@@ -57,6 +57,10 @@ _SIGS = {
     "sps_monitor": [_vp, _vp, _i64, _vp],
     "sps_moments": [_vp, _vp, _i32, _i32, _i32, ct.POINTER(_dbl), ct.POINTER(_dbl),
                     ct.POINTER(_dbl), ct.POINTER(_dbl)],
+    "sps_mutate_cov": [_vp, _vp, _vp, _vp, _i32, _i32, _i64, _vp, ct.c_int, ct.c_int, _vp, _vp,
+                       _u64, _u64, ct.POINTER(_dbl)],
+    "sps_last_sigma": [_vp, _vp],
+    "sps_correct_fixed": [_vp, _vp, _vp, _i32, _i32, _i64, _i64, ct.c_int, _vp],
     "sps_timing_enable": [_vp, ct.c_int],
     "sps_timing_read": [_vp, ct.c_int, ct.POINTER(_i64), ct.POINTER(_dbl)],
 }
@@ -276,6 +280,44 @@ def sps_mutate(ctx: Context, theta: torch.Tensor, ll: torch.Tensor, grad: Option
                                prec, _ptr(z), _ptr(u), seed, stream,
                                ct.byref(rate) if want_rate else None))
     return rate.value if want_rate else None
+
+
+def sps_mutate_cov(ctx: Context, theta: torch.Tensor, ll: torch.Tensor, grad: Optional[torch.Tensor],
+                   J: int, N: int, t: int, Sigma: torch.Tensor, kind: int, prec: int,
+                   z: Optional[torch.Tensor] = None, u: Optional[torch.Tensor] = None,
+                   seed: int = 0, stream: int = 0, want_rate: bool = True):
+    P = J * N
+    ctx._t(theta, torch.float64, (P, ctx.d), "theta")
+    ctx._t(ll, torch.float64, (P,), "ll")
+    ctx._t(grad, torch.float64, (P, ctx.d), "grad", allow_none=True)
+    ctx._t(Sigma, torch.float64, (ctx.d, ctx.d), "Sigma")
+    ctx._t(z, torch.float64, (P, ctx.d), "z", allow_none=True)
+    ctx._t(u, torch.float64, (P,), "u", allow_none=True)
+    rate = _dbl(-1.0)
+    ctx.check(lib().sps_mutate_cov(ctx.handle, _ptr(theta), _ptr(ll), _ptr(grad), J, N, t, _ptr(Sigma),
+                                   kind, prec, _ptr(z), _ptr(u), seed, stream,
+                                   ct.byref(rate) if want_rate else None))
+    return rate.value if want_rate else None
+
+
+def sps_last_sigma(ctx: Context, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    if out is None:
+        out = torch.empty(ctx.d, ctx.d, dtype=torch.float64, device=ctx.device)
+    ctx._t(out, torch.float64, (ctx.d, ctx.d), "Sigma")
+    ctx.check(lib().sps_last_sigma(ctx.handle, _ptr(out)))
+    return out
+
+
+def sps_correct_fixed(ctx: Context, theta: torch.Tensor, ll: torch.Tensor, J: int, N: int, s0: int,
+                      s1: int, prec: int, log_w: Optional[torch.Tensor] = None) -> torch.Tensor:
+    P = J * N
+    ctx._t(theta, torch.float64, (P, ctx.d), "theta")
+    ctx._t(ll, torch.float64, (P,), "ll")
+    if log_w is None:
+        log_w = torch.empty(P, dtype=torch.float64, device=ctx.device)
+    ctx._t(log_w, torch.float64, (P,), "log_w")
+    ctx.check(lib().sps_correct_fixed(ctx.handle, _ptr(theta), _ptr(ll), J, N, s0, s1, prec, _ptr(log_w)))
+    return log_w
 
 
 def sps_monitor(ctx: Context, theta: torch.Tensor, g: Optional[torch.Tensor] = None) -> torch.Tensor:

@@ -123,7 +123,11 @@ def test_loglik_rejects_bad_args():
         sps.sps_set_data(ctx2, to_gpu(X), bad_y, 2)
 
 
-@pytest.mark.parametrize("name,prec", [("binary30", 1), ("small", 0)])
+FULL = [("binary30", 1), ("small", 0), ("binary30", 0), ("multi4", 2), ("ar100", 2), ("multi6", 2),
+        ("multi6", 1)]
+
+
+@pytest.mark.parametrize("name,prec", FULL, ids=[f"{n}-{p}" for n, p in FULL])
 def test_loglik_full_size_sampled(orc, name, prec):
     """Full-size workload in the benchmark's launch configuration, checked on
     a sample of particles the oracle evaluates one by one."""
@@ -137,7 +141,8 @@ def test_loglik_full_size_sampled(orc, name, prec):
     ll = sps.sps_loglik(ctx, to_gpu(th), 0, w.T, prec).cpu().numpy()
     ll_g, g = sps.sps_loglik_grad(ctx, to_gpu(th), 0, w.T, prec)
     g = g.cpu().numpy()
-    idx = synth.rng(12).choice(w.P, size=48, replace=False)
+    nsamp = 48 if w.T * w.d <= 10 ** 6 else 14
+    idx = synth.rng(12).choice(w.P, size=nsamp, replace=False)
     idx = np.concatenate([idx, [0, w.P - 1]])
     ref_ll, ref_g = orc.loglik(X, y, w.C, th[idx], 0, w.T, grad=True)
     assert rel_err(ll[idx], ref_ll).max() <= TOL[prec]

@@ -246,3 +246,61 @@ def test_monitor_and_moments_match_oracle(orc):
     assert np.allclose(sd, rs, rtol=1e-9)
     assert np.allclose(nse, rn, rtol=1e-9)
     assert np.allclose(rne, rr, rtol=1e-9)
+
+
+# ------------------------------------------------------------------ two-pass entry points
+@pytest.mark.parametrize("kind", [0, 1])
+def test_mutate_cov_matches_oracle(orc, kind):
+    """Given proposal covariance (Algorithm 3, second pass)."""
+    need_gpu()
+    sps = _sps()
+    T, C, k, J, N, t = 800, 3, 6, 4, 128, 700
+    X, y, B = dataset(T, k, C, seed=30)
+    d = k * (C - 1)
+    P = J * N
+    th = synth.make_particles(P, d, scale=0.05, seed=31, center=B.reshape(-1))
+    ll, gr = orc.loglik(X, y, C, th, 0, t, grad=True)
+    A = synth.rng(32).standard_normal((d, d))
+    Sigma = 0.002 * (A @ A.T + d * np.eye(d))
+    z = synth.make_normals(P, d, seed=33)
+    u = synth.make_uniforms(P, seed=34)
+    ctx = make_ctx(X, y, C)
+    thg, llg = to_gpu(th), to_gpu(ll)
+    grg = to_gpu(gr) if kind == 1 else None
+    sps.sps_mutate_cov(ctx, thg, llg, grg, J, N, t, to_gpu(Sigma), kind, 0, z=to_gpu(z), u=to_gpu(u))
+    th_o, ll_o, _, _, la_o, acc_o = orc.mutate_cov(X, y, C, 0.0, 5.0, th, ll, gr if kind else None,
+                                                   J, N, t, Sigma, kind, z, u)
+    acc_g = np.any(thg.cpu().numpy() != th, axis=1)
+    diff = acc_g != acc_o
+    assert np.all(np.abs(np.log(u) - la_o)[diff] < 1e-6)
+    same = ~diff
+    assert rel_err(thg.cpu().numpy()[same], th_o[same]).max() <= 1e-9
+    assert np.allclose(sps.sps_last_sigma(ctx).cpu().numpy(), Sigma, rtol=0, atol=0)
+
+
+def test_last_sigma_is_h_times_variance(orc):
+    need_gpu()
+    sps = _sps()
+    X, y, _ = dataset(200, 4, 2, seed=35)
+    ctx = make_ctx(X, y, 2)
+    th = synth.make_particles(512, 4, scale=0.3, seed=36)
+    ll = orc.loglik(X, y, 2, th, 0, 200)
+    sps.sps_mutate(ctx, to_gpu(th), to_gpu(ll), None, 4, 128, 200, 0.37, 0, 0, seed=1, stream=8)
+    _, V = orc.cov(th)
+    assert np.allclose(sps.sps_last_sigma(ctx).cpu().numpy(), 0.37 * V, rtol=1e-11, atol=1e-14)
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_correct_fixed_matches_oracle(orc, prec):
+    need_gpu()
+    sps = _sps()
+    X, y, _ = dataset(900, 7, 4, seed=37)
+    th = synth.make_particles(300, 21, scale=0.3, seed=38)
+    ll0 = synth.make_normals(300, 1, seed=39)[:, 0]
+    ctx = make_ctx(X, y, 4)
+    llg = to_gpu(ll0.copy())
+    lw = sps.sps_correct_fixed(ctx, to_gpu(th), llg, 3, 100, 123, 877, prec).cpu().numpy()
+    ref = orc.loglik(X, y, 4, th, 123, 877)
+    tol = 1e-10 if prec == 0 else 1e-4
+    assert rel_err(lw, ref).max() <= tol
+    assert rel_err(llg.cpu().numpy(), ll0 + ref).max() <= tol

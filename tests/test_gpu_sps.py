@@ -70,3 +70,23 @@ def test_sps_single_observation_logml():
     r = driver.run_sps(ctx, driver.SpsConfig(J=16, N=2048, precision="fp32", seed=4))
     assert r["cycles"] == 1
     assert abs(r["logml"] + math.log(2.0)) < 4 * r["logml_nse"] + 1e-12
+
+
+def test_two_pass_vs_oracle_two_pass(orc):
+    """Algorithm 3 on both sides: the second pass replays the first pass's
+    design; moments and logML of the GPU and oracle second passes agree."""
+    need_gpu()
+    from paper_1304_4333_amd import driver
+    w = synth.workload("small", T=200)
+    X, y, _ = synth.make_data(w)
+    J, N = 16, 256
+    ctx = driver.setup(X, y, w.C, 0.0, w.prior_sd)
+    g1, g2 = driver.run_two_pass(ctx, driver.SpsConfig(J=J, N=N, precision="fp64", seed=21))
+    assert g2["cycles"] == g1["cycles"] and g2["m_iters"] == g1["m_iters"]
+    o1, o2 = orc.sps_two_pass(X, y, w.C, 0.0, w.prior_sd, J, N, seed=22)
+    assert o2["cycles"] == o1["cycles"]
+    z = _z(g2["mean"], o2["mean"], g2["nse"], o2["nse"])
+    print("two-pass z-scores:", np.round(z, 2))
+    assert z.max() < 4.0
+    zl = abs(g2["logml"] - o2["logml"]) / math.hypot(g2["logml_nse"], o2["logml_nse"])
+    assert zl < 4.0

@@ -109,3 +109,46 @@ def test_deterministic_given_seed(orc):
     a = orc.sps_run(X, y, 2, 0.0, 5.0, J=4, N=128, seed=9)
     b = orc.sps_run(X, y, 2, 0.0, 5.0, J=4, N=128, seed=9)
     assert np.array_equal(a["theta"], b["theta"]) and a["logml"] == b["logml"]
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_two_pass_against_quadrature(orc, kind):
+    """Algorithm 3: the second pass (fixed design, fresh randomness) agrees
+    with quadrature, and replays the first pass's cycles and M steps."""
+    X, y = _intercept_model(60, 0.75, seed=2)
+    logZ, m1, sd = _intercept_truth(y, 5.0)
+    kw = dict(kind=kind)
+    if kind == 1:
+        kw.update(h_min=0.01, h_max=2.0, acc_target=0.574)
+    p1, p2 = orc.sps_two_pass(X, y, 2, 0.0, 5.0, J=16, N=1024, seed=13, **kw)
+    assert p2["cycles"] == p1["cycles"] and p2["m_iters"] == p1["m_iters"]
+    assert p1["sigma"].shape == (p1["m_iters"], 1, 1)
+    assert abs(p2["mean"][0] - m1) < 4 * p2["nse"][0] + 1e-4
+    assert abs(p2["logml"] - logZ) < 4 * p2["logml_nse"] + 0.01
+    # the second pass draws fresh variates: its particles differ from the first pass's
+    assert not np.allclose(p1["theta"], p2["theta"])
+
+
+def test_mutate_cov_log_alpha_independent(orc):
+    """Given proposal covariance: log alpha rebuilt with scipy."""
+    w = synth.workload("small", T=80)
+    X, y, _ = synth.make_data(w)
+    J, N, d, t = 2, 16, w.d, 60
+    th = synth.make_particles(J * N, d, scale=0.3, seed=11, center=[-0.7, 1, 0.3, -1.4, 0.4])
+    ll, gr = orc.loglik(X, y, 2, th, 0, t, grad=True)
+    A = synth.rng(3).standard_normal((d, d))
+    S = 0.01 * (A @ A.T + d * np.eye(d))
+    z = synth.make_normals(J * N, d, seed=12)
+    u = synth.make_uniforms(J * N, seed=13)
+    _, _, _, _, la, _ = orc.mutate_cov(X, y, 2, 0.0, 5.0, th, ll, gr, J, N, t, S, 1, z, u)
+    L = np.linalg.cholesky(S)
+    prior = lambda a: stats.norm.logpdf(a, 0.0, 5.0).sum(axis=-1)
+    mu0 = th + 0.5 * (gr - th / 25.0) @ S.T
+    prop = mu0 + z @ L.T
+    llp, grp = orc.loglik(X, y, 2, prop, 0, t, grad=True)
+    mu1 = prop + 0.5 * (grp - prop / 25.0) @ S.T
+    ref = llp + prior(prop) - ll - prior(th)
+    for p in range(J * N):
+        ref[p] += (stats.multivariate_normal.logpdf(th[p], mu1[p], S)
+                   - stats.multivariate_normal.logpdf(prop[p], mu0[p], S))
+    assert np.allclose(la, ref, rtol=1e-9, atol=1e-9)
