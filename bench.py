@@ -201,6 +201,46 @@ def cpu_baseline(w, seconds, seed=1):
                        f"(16 groups x 32), {el:.1f} s, OpenMP over particles")
 
 
+def kernel_table(names, reps=5):
+    """Full-data sps_loglik and sps_loglik_grad throughput through the ABI
+    (main kernel + split reduction + sufficient-statistic terms), per
+    workload and precision, with particles at posterior scale."""
+    import torch
+    from paper_1304_4333_amd import driver, sps, synth
+    rows = []
+    for name in names:
+        w = synth.workload(name)
+        X, y, B = synth.make_data(w)
+        ctx = driver.setup(X, y, w.C, 0.0, w.prior_sd)
+        th = torch.from_numpy(synth.make_particles(w.P, w.d, scale=0.02, seed=1, center=B.reshape(-1))).cuda()
+        ll = torch.empty(w.P, dtype=torch.float64, device="cuda")
+        g = torch.empty(w.P, w.d, dtype=torch.float64, device="cuda")
+        for prec_name in ("fp64", "fp32", "bf16x3"):
+            prec = sps.PREC[prec_name]
+            for grad in (False, True):
+                def call():
+                    if grad:
+                        sps.sps_loglik_grad(ctx, th, 0, w.T, prec, ll, g)
+                    else:
+                        sps.sps_loglik(ctx, th, 0, w.T, prec, ll)
+                call()
+                torch.cuda.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for _ in range(reps):
+                    call()
+                e1.record()
+                torch.cuda.synchronize()
+                us = e0.elapsed_time(e1) * 1e3 / reps
+                flops = 2.0 * w.k * (w.C - 1) * (2 if grad else 1) * w.P * w.T
+                rows.append(dict(workload=name, precision=prec_name, call="loglik_grad" if grad else "loglik",
+                                 us=round(us, 1), evals_per_s=float(f"{w.P * w.T / us * 1e6:.4g}"),
+                                 mfma_tflops=round(flops / us * 1e-6, 2)))
+                print(json.dumps(rows[-1]), flush=True)
+        del ctx
+    return rows
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -211,7 +251,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sps", action="store_true", help="skip the fixed-NSE SPS comparison")
     ap.add_argument("--sps-seeds", type=int, default=2)
+    ap.add_argument("--kernel-table", default=None,
+                    help="comma-separated workloads: print full-data loglik/grad rates instead")
     args = ap.parse_args()
+    if args.kernel_table:
+        kernel_table(args.kernel_table.split(","))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); the particle-group "
               "sharding across GPUs is a design note only.", file=sys.stderr)

@@ -57,6 +57,10 @@ constexpr double kLn2 = 0.69314718055994530942;
 
 enum { MODE_FWD = 0, MODE_GRAD = 1 };
 
+#ifndef SPS_PW_BUDGET
+#define SPS_PW_BUDGET 128
+#endif
+
 struct LoglikArgs {
     const void* X;      // row-major kernel copy of X (FP64 / FP32 / BF16 hi)
     const void* Xlo;    // BF16 lo part (BF16X3 only)
@@ -117,31 +121,41 @@ template <> struct Prec<SPS_BF16X3> {
     static constexpr int KPS = 32;
 };
 
-// Particle blocks (of 16) per wave: the largest of 4, 2, 1 whose register
-// estimate fits the budget (the fused adjoint keeps more live state).
+// Register estimates (32-bit registers per lane) behind two compile-time
+// choices: PW, the particle blocks (of 16) per wave, and whether the step loop
+// is software-pipelined (two sets of forward accumulators and A fragments).
+template <int PREC, int NC, int KS, int MODE>
+struct Shape {
+    static constexpr bool BF = PREC == SPS_BF16X3;
+    static constexpr int w = PREC == SPS_FP64 ? 2 : 1;           // registers per element
+    static constexpr int breg = BF ? 8 * KS : w * KS;             // theta fragments per (block, outcome)
+    static constexpr int accr = 2 * 4 * w;                        // one set: two tiles x 4 values
+    static constexpr int kbt = BF ? 2 * KS : KS / 4;              // adjoint k blocks of 16
+    static constexpr int grad = MODE == MODE_GRAD ? (4 * w * kbt + 8 * w) : 0;
+    static constexpr int afrag = 2 * (BF ? 8 * KS : w * KS);      // one set: two tiles
+    static constexpr int per1 = NC * (breg + accr + grad);
+    static constexpr int budget = 96;
+    static constexpr int PW = afrag + 4 * per1 <= budget ? 4 : (afrag + 2 * per1 <= budget ? 2 : 1);
+    // pipelining doubles the accumulators and fragments
+    static constexpr bool PIPE = 2 * afrag + PW * (per1 + NC * accr) <= 128;
+};
+
 template <int PREC, int NC, int KS, int MODE>
 constexpr int pick_pw() {
-    constexpr bool BF = PREC == SPS_BF16X3;
-    constexpr int w = PREC == SPS_FP64 ? 2 : 1;        // registers per element
-    constexpr int breg = BF ? 8 * KS : w * KS;          // theta fragments per (block, outcome)
-    constexpr int accr = 2 * 4 * w;                     // two tiles of 4 accumulators
-    constexpr int kbt = BF ? 2 * KS : KS / 4;           // adjoint k blocks of 16
-    constexpr int grad = MODE == MODE_GRAD ? (4 * w * kbt + 8 * w) : 0;  // G tiles + residuals
-    constexpr int per = NC * (breg + accr + grad) + 2;
-    constexpr int budget = MODE == MODE_GRAD ? 112 : 160;
-    return per * 4 <= budget ? 4 : (per * 2 <= budget ? 2 : 1);
+    return Shape<PREC, NC, KS, MODE>::PW;
 }
 
 template <bool V> using bconst = std::integral_constant<bool, V>;
 
-template <int PREC, int NC, int KS, int MODE>
+// PWO / PIPEO override the register-estimate choices (0 / -1: use Shape).
+template <int PREC, int NC, int KS, int MODE, int PWO = 0, int PIPEO = -1>
 __global__ __launch_bounds__(256) void loglik_kernel(LoglikArgs a) {
     using P_ = Prec<PREC>;
     using E = typename P_::E;
     using Acc = typename P_::Acc;
     constexpr bool BF = (PREC == SPS_BF16X3);
     constexpr bool F64 = (PREC == SPS_FP64);
-    constexpr int PW = pick_pw<PREC, NC, KS, MODE>();
+    constexpr int PW = PWO ? PWO : Shape<PREC, NC, KS, MODE>::PW;
     constexpr int KBT = BF ? 2 * KS : KS / 4;  // adjoint k blocks of 16 (rows of XT)
     constexpr bool GRAD = (MODE == MODE_GRAD);
     // Multinomial FP32/BF16: the eta_{y_t} term of the log-likelihood is
@@ -248,11 +262,18 @@ __global__ __launch_bounds__(256) void loglik_kernel(LoglikArgs a) {
     // D row r = 4g+i (f32/bf16) or r = g+4i (f64) must map to o + 8g + i.
     const int arow = F64 ? 8 * (r16 & 3) + (r16 >> 2) : 8 * (r16 >> 2) + (r16 & 3);
 
-    // A fragments of one step (two 16-row tiles), double-buffered by prefetch.
+    // A fragments and forward accumulators come in two sets: while the
+    // epilogue of step st reads set CUR, the MFMAs of step st+1 fill set
+    // 1 - CUR in the same basic block, so the scheduler can interleave the
+    // matrix-core work of one step with the VALU work of the previous one.
+    constexpr bool PIPE = PIPEO < 0 ? Shape<PREC, NC, KS, MODE>::PIPE : PIPEO != 0;
+    constexpr int NSET = PIPE ? 2 : 1;
     using AReg = typename std::conditional<BF, bf16x8, E>::type;
-    AReg ah[2][KS];
-    AReg al[BF ? 2 : 1][BF ? KS : 1];
-    auto load_a = [&](int64_t o) {
+    AReg ah[NSET][2][KS];                       // [set][tile][k-step]
+    AReg al[NSET][BF ? 2 : 1][BF ? KS : 1];
+    Acc acc[NSET][2][PW][NC];                   // [set][tile][block][outcome]
+    auto load_a = [&](auto set_c, int64_t o) {
+        constexpr int S_ = decltype(set_c)::value;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int64_t row = o + arow + 4 * h;
@@ -261,29 +282,25 @@ __global__ __launch_bounds__(256) void loglik_kernel(LoglikArgs a) {
                 const unsigned short* xl = (const unsigned short*)a.Xlo + row * a.ldx + g * 8 * KS;
 #pragma unroll
                 for (int s = 0; s < KS; ++s) {
-                    ah[h][s] = __builtin_bit_cast(bf16x8, *(const u16x8*)(xh + 8 * s));
-                    al[h][s] = __builtin_bit_cast(bf16x8, *(const u16x8*)(xl + 8 * s));
+                    ah[S_][h][s] = __builtin_bit_cast(bf16x8, *(const u16x8*)(xh + 8 * s));
+                    al[S_][h][s] = __builtin_bit_cast(bf16x8, *(const u16x8*)(xl + 8 * s));
                 }
             } else {
                 const E* xr = (const E*)a.X + row * a.ldx + g * KS;
 #pragma unroll
-                for (int s = 0; s < KS; ++s) ah[h][s] = xr[s];
+                for (int s = 0; s < KS; ++s) ah[S_][h][s] = xr[s];
             }
         }
     };
-    if (st_begin < st_end) load_a(a.t0a + (int64_t)st_begin * 32);
-
-    for (int st = st_begin; st < st_end; ++st) {
-        const int64_t o = a.t0a + (int64_t)st * 32;
-
-        // ---- forward contraction, independent chains interleaved ----
-        Acc acc[2][PW][NC];
+    // forward contraction of one step into set S_, independent chains interleaved
+    auto mfma_fwd = [&](auto set_c) {
+        constexpr int S_ = decltype(set_c)::value;
 #pragma unroll
         for (int h = 0; h < 2; ++h)
 #pragma unroll
             for (int b = 0; b < PW; ++b)
 #pragma unroll
-                for (int c = 0; c < NC; ++c) acc[h][b][c] = Acc{0, 0, 0, 0};
+                for (int c = 0; c < NC; ++c) acc[S_][h][b][c] = Acc{0, 0, 0, 0};
 #pragma unroll
         for (int s = 0; s < KS; ++s)
 #pragma unroll
@@ -293,16 +310,28 @@ __global__ __launch_bounds__(256) void loglik_kernel(LoglikArgs a) {
 #pragma unroll
                     for (int c = 0; c < NC; ++c) {
                         if constexpr (BF) {
-                            acc[h][b][c] = mfma(ah[h][s], bh[b][c][s], acc[h][b][c]);
-                            acc[h][b][c] = mfma(ah[h][s], bl[b][c][s], acc[h][b][c]);
-                            acc[h][b][c] = mfma(al[h][s], bh[b][c][s], acc[h][b][c]);
+                            acc[S_][h][b][c] = mfma(ah[S_][h][s], bh[b][c][s], acc[S_][h][b][c]);
+                            acc[S_][h][b][c] = mfma(ah[S_][h][s], bl[b][c][s], acc[S_][h][b][c]);
+                            acc[S_][h][b][c] = mfma(al[S_][h][s], bh[b][c][s], acc[S_][h][b][c]);
                         } else {
-                            acc[h][b][c] = mfma(ah[h][s], bh[b][c][s], acc[h][b][c]);
+                            acc[S_][h][b][c] = mfma(ah[S_][h][s], bh[b][c][s], acc[S_][h][b][c]);
                         }
                     }
-        if (st + 1 < st_end) load_a(o + 32);
+    };
 
-        // ---- epilogue: per-observation log-probabilities ----
+    // One step: epilogue (and adjoint) of step st from set CUR, overlapped
+    // with the forward MFMAs of step st + 1 into the other set.
+    auto body = [&](auto cur_c, int st, bool has_next) {
+        constexpr int CUR = decltype(cur_c)::value;
+        constexpr int NXT = PIPE ? 1 - CUR : CUR;
+        const int64_t o = a.t0a + (int64_t)st * 32;
+        if constexpr (PIPE) {
+            if (st + 2 < st_end) load_a(cur_c, o + 64);  // set CUR is free again: prefetch step st + 2
+        } else {
+            mfma_fwd(cur_c);
+            if (has_next) load_a(cur_c, o + 32);  // the MFMAs have read this step's fragments
+        }
+
         unsigned ylo = 0, yhi = 0;
         if (NC > 1 && (!SUFF || a.perobs != nullptr)) {
             const uint2 yy = *(const uint2*)(a.y8 + o + 8 * g);
@@ -315,164 +344,192 @@ __global__ __launch_bounds__(256) void loglik_kernel(LoglikArgs a) {
 #pragma unroll
         for (int b = 0; b < PW; ++b) tsum[b] = E(0);
 
-        auto epilogue = [&](auto masked_c, auto perobs_c, auto fast_c) {
-            constexpr bool MASKED = decltype(masked_c)::value;
-            constexpr bool PEROBS = decltype(perobs_c)::value;
-            constexpr bool FAST = decltype(fast_c)::value;  // no max shift (SUFF only)
-            constexpr bool NOY = SUFF && !PEROBS;           // eta_y via sufficient statistics
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int64_t obs = o + 8 * g + 4 * h + i;
-                    const bool ov = !MASKED || (obs >= a.t0 && obs < a.t1);
-                    const int yt = NC > 1 ? (int)(((h ? yhi : ylo) >> (8 * i)) & 0xFFu) : 0;
-#pragma unroll
-                    for (int b = 0; b < PW; ++b) {
-                        E lp;
-                        if constexpr (NC == 1) {
-                            // Binary with sign folding: l = -softplus(z), z = x~' theta.
-                            const E z = acc[h][b][0][i];
-                            if constexpr (F64) {
-                                const double e = exp(-fabs(z));
-                                const double q = 1.0 + e;
-                                lp = -(fmax(z, 0.0) + log1p(e));
-                                if constexpr (GRAD) rres[h][i][b][0] = ov ? -(z > 0.0 ? 1.0 : e) / q : 0.0;
-                            } else {
-                                // base 2: softplus2(z) = max(z, 0) + log2(1 + 2^-|z|);
-                                // max via the signed-integer order of float bits
-                                const float mz = __int_as_float(max(__float_as_int(z), 0));
-                                lp = -(mz + flog2(1.f + fexp2(-fabsf(z))));
-                                // sigmoid(z) = 2^(z - softplus2(z))
-                                if constexpr (GRAD) rres[h][i][b][0] = ov ? -fexp2(z + lp) : 0.f;
-                            }
-                        } else if constexpr (NOY && FAST) {
-                            // base 2 without a shift: exact while the sum stays below 2^126
-                            E ec[NC];
-                            E s = E(1);
-#pragma unroll
-                            for (int c = 0; c < NC; ++c) {
-                                ec[c] = fexp2(acc[h][b][c][i]);
-                                s += ec[c];
-                            }
-                            bad |= !(s < 0x1p126f);
-                            lp = -flog2(s);
-                            if constexpr (GRAD) {
-                                const E inv = frcp(s);
-#pragma unroll
-                                for (int c = 0; c < NC; ++c) rres[h][i][b][c] = ov ? -ec[c] * inv : E(0);
-                            }
-                        } else {
-                            E m = E(0);
-                            E ey = E(0);
-#pragma unroll
-                            for (int c = 0; c < NC; ++c) {
-                                const E v = acc[h][b][c][i];
-                                if constexpr (F64) m = v > m ? v : m;
-                                else m = __int_as_float(max(__float_as_int(v), __float_as_int(m)));  // m >= 0
-                                if constexpr (!NOY) ey = (yt == c + 1) ? v : ey;
-                            }
-                            E ec[NC];
-                            E s;
-                            if constexpr (F64) {
-                                s = exp(-m);
-#pragma unroll
+            auto epilogue = [&](auto set_c, auto masked_c, auto perobs_c, auto fast_c) {
+                constexpr int CS = decltype(set_c)::value;
+                constexpr bool MASKED = decltype(masked_c)::value;
+                constexpr bool PEROBS = decltype(perobs_c)::value;
+                constexpr bool FAST = decltype(fast_c)::value;  // no max shift (SUFF only)
+                constexpr bool NOY = SUFF && !PEROBS;           // eta_y via sufficient statistics
+    #pragma unroll
+                for (int h = 0; h < 2; ++h) {
+    #pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int64_t obs = o + 8 * g + 4 * h + i;
+                        const bool ov = !MASKED || (obs >= a.t0 && obs < a.t1);
+                        const int yt = NC > 1 ? (int)(((h ? yhi : ylo) >> (8 * i)) & 0xFFu) : 0;
+    #pragma unroll
+                        for (int b = 0; b < PW; ++b) {
+                            E lp;
+                            if constexpr (NC == 1) {
+                                // Binary with sign folding: l = -softplus(z), z = x~' theta.
+                                const E z = acc[CS][h][b][0][i];
+                                if constexpr (F64) {
+                                    const double e = exp(-fabs(z));
+                                    const double q = 1.0 + e;
+                                    lp = -(fmax(z, 0.0) + log1p(e));
+                                    if constexpr (GRAD) rres[h][i][b][0] = ov ? -(z > 0.0 ? 1.0 : e) / q : 0.0;
+                                } else {
+                                    // base 2: softplus2(z) = max(z, 0) + log2(1 + 2^-|z|);
+                                    // max via the signed-integer order of float bits
+                                    const float mz = __int_as_float(max(__float_as_int(z), 0));
+                                    lp = -(mz + flog2(1.f + fexp2(-fabsf(z))));
+                                    // sigmoid(z) = 2^(z - softplus2(z))
+                                    if constexpr (GRAD) rres[h][i][b][0] = ov ? -fexp2(z + lp) : 0.f;
+                                }
+                            } else if constexpr (NOY && FAST) {
+                                // base 2 without a shift: exact while the sum stays below 2^126
+                                E ec[NC];
+                                E s = E(1);
+    #pragma unroll
                                 for (int c = 0; c < NC; ++c) {
-                                    ec[c] = exp(acc[h][b][c][i] - m);
+                                    ec[c] = fexp2(acc[CS][h][b][c][i]);
                                     s += ec[c];
                                 }
-                                lp = ey - (m + log(s));
-                            } else {
-                                s = fexp2(-m);
-#pragma unroll
-                                for (int c = 0; c < NC; ++c) {
-                                    ec[c] = fexp2(acc[h][b][c][i] - m);
-                                    s += ec[c];
+                                bad |= !(s < 0x1p126f);
+                                lp = -flog2(s);
+                                if constexpr (GRAD) {
+                                    const E inv = frcp(s);
+    #pragma unroll
+                                    for (int c = 0; c < NC; ++c) rres[h][i][b][c] = ov ? -ec[c] * inv : E(0);
                                 }
-                                lp = ey - (m + flog2(s));
+                            } else {
+                                E m = E(0);
+                                E ey = E(0);
+    #pragma unroll
+                                for (int c = 0; c < NC; ++c) {
+                                    const E v = acc[CS][h][b][c][i];
+                                    if constexpr (F64) m = v > m ? v : m;
+                                    else m = __int_as_float(max(__float_as_int(v), __float_as_int(m)));  // m >= 0
+                                    if constexpr (!NOY) ey = (yt == c + 1) ? v : ey;
+                                }
+                                E ec[NC];
+                                E s;
+                                if constexpr (F64) {
+                                    s = exp(-m);
+    #pragma unroll
+                                    for (int c = 0; c < NC; ++c) {
+                                        ec[c] = exp(acc[CS][h][b][c][i] - m);
+                                        s += ec[c];
+                                    }
+                                    lp = ey - (m + log(s));
+                                } else {
+                                    s = fexp2(-m);
+    #pragma unroll
+                                    for (int c = 0; c < NC; ++c) {
+                                        ec[c] = fexp2(acc[CS][h][b][c][i] - m);
+                                        s += ec[c];
+                                    }
+                                    lp = ey - (m + flog2(s));
+                                }
+                                if constexpr (GRAD) {
+                                    const E inv = F64 ? E(1) / s : frcp(s);
+    #pragma unroll
+                                    for (int c = 0; c < NC; ++c)
+                                        rres[h][i][b][c] =
+                                            ov ? ((!NOY && yt == c + 1 ? E(1) : E(0)) - ec[c] * inv) : E(0);
+                                }
                             }
-                            if constexpr (GRAD) {
-                                const E inv = F64 ? E(1) / s : frcp(s);
-#pragma unroll
-                                for (int c = 0; c < NC; ++c)
-                                    rres[h][i][b][c] =
-                                        ov ? ((!NOY && yt == c + 1 ? E(1) : E(0)) - ec[c] * inv) : E(0);
+                            tsum[b] += MASKED ? (ov ? lp : E(0)) : lp;
+                            if constexpr (PEROBS) {
+                                const int64_t p = pbase + b * 16 + r16;
+                                if (ov && p < a.P)
+                                    a.perobs[(obs - a.t0) * a.P + p] = F64 ? (double)lp : (double)lp * kLn2;
                             }
-                        }
-                        tsum[b] += MASKED ? (ov ? lp : E(0)) : lp;
-                        if constexpr (PEROBS) {
-                            const int64_t p = pbase + b * 16 + r16;
-                            if (ov && p < a.P)
-                                a.perobs[(obs - a.t0) * a.P + p] = F64 ? (double)lp : (double)lp * kLn2;
                         }
                     }
                 }
-            }
-        };
+            };
+
         const bool full = (o >= a.t0) && (o + 32 <= a.t1);
+        const std::integral_constant<int, NXT> nxt_c{};
         if (a.perobs != nullptr) {
-            epilogue(bconst<true>{}, bconst<true>{}, bconst<false>{});
+            if (PIPE && has_next) mfma_fwd(nxt_c);
+            epilogue(cur_c, bconst<true>{}, bconst<true>{}, bconst<false>{});
         } else if constexpr (SUFF) {
-            if (full) epilogue(bconst<false>{}, bconst<false>{}, bconst<true>{});
-            else epilogue(bconst<true>{}, bconst<false>{}, bconst<true>{});
+            if (full && has_next) {
+                if constexpr (PIPE) mfma_fwd(nxt_c);
+                epilogue(cur_c, bconst<false>{}, bconst<false>{}, bconst<true>{});
+            } else {
+                if (PIPE && has_next) mfma_fwd(nxt_c);
+                epilogue(cur_c, bconst<true>{}, bconst<false>{}, bconst<true>{});
+            }
             if (__any(bad)) {  // wave-uniform: redo this step with the max shift
 #pragma unroll
                 for (int b = 0; b < PW; ++b) tsum[b] = E(0);
-                epilogue(bconst<true>{}, bconst<false>{}, bconst<false>{});
+                epilogue(cur_c, bconst<true>{}, bconst<false>{}, bconst<false>{});
             }
-        } else if (full) {
-            epilogue(bconst<false>{}, bconst<false>{}, bconst<false>{});
+        } else if (full && has_next) {
+            if constexpr (PIPE) mfma_fwd(nxt_c);
+            epilogue(cur_c, bconst<false>{}, bconst<false>{}, bconst<false>{});
         } else {
-            epilogue(bconst<true>{}, bconst<false>{}, bconst<false>{});
+            if (PIPE && has_next) mfma_fwd(nxt_c);
+            epilogue(cur_c, bconst<true>{}, bconst<false>{}, bconst<false>{});
         }
 #pragma unroll
         for (int b = 0; b < PW; ++b) acc64[b] += (double)tsum[b];
 
-        // ---- adjoint: G += X~^T R over the 32 rows of this step ----
-        if constexpr (GRAD) {
-            if constexpr (BF) {
-#pragma unroll
-                for (int q = 0; q < KBT; ++q) {
-                    const int64_t xrow = (int64_t)(q * 16 + r16) * a.Tp + o + 8 * g;
-                    const bf16x8 th8 = __builtin_bit_cast(bf16x8, *(const u16x8*)((const unsigned short*)a.XT + xrow));
-                    const bf16x8 tl8 = __builtin_bit_cast(bf16x8, *(const u16x8*)((const unsigned short*)a.XTlo + xrow));
-#pragma unroll
-                    for (int b = 0; b < PW; ++b)
-#pragma unroll
-                        for (int c = 0; c < NC; ++c) {
-                            // hi/lo split with the hardware round-to-nearest-even conversion
-                            bf16x8 Rh, Rl;
-#pragma unroll
-                            for (int j = 0; j < 8; ++j) {
-                                const float v = rres[j >> 2][j & 3][b][c];
-                                const __bf16 hb = (__bf16)v;
-                                Rh[j] = hb;
-                                Rl[j] = (__bf16)(v - (float)hb);
-                            }
-                            gacc[b][c][q] = mfma(th8, Rh, gacc[b][c][q]);
-                            gacc[b][c][q] = mfma(th8, Rl, gacc[b][c][q]);
-                            gacc[b][c][q] = mfma(tl8, Rh, gacc[b][c][q]);
-                        }
-                }
-            } else {
-                E xv[KBT][8];
-#pragma unroll
-                for (int q = 0; q < KBT; ++q) {
-                    const E* xt = (const E*)a.XT + (int64_t)(q * 16 + r16) * a.Tp + o + 8 * g;
-#pragma unroll
-                    for (int j = 0; j < 8; ++j) xv[q][j] = xt[j];
-                }
-#pragma unroll
-                for (int j = 0; j < 8; ++j)
-#pragma unroll
-                    for (int q = 0; q < KBT; ++q)
-#pragma unroll
+            // ---- adjoint: G += X~^T R over the 32 rows of this step ----
+            if constexpr (GRAD) {
+                if constexpr (BF) {
+    #pragma unroll
+                    for (int q = 0; q < KBT; ++q) {
+                        const int64_t xrow = (int64_t)(q * 16 + r16) * a.Tp + o + 8 * g;
+                        const bf16x8 th8 = __builtin_bit_cast(bf16x8, *(const u16x8*)((const unsigned short*)a.XT + xrow));
+                        const bf16x8 tl8 = __builtin_bit_cast(bf16x8, *(const u16x8*)((const unsigned short*)a.XTlo + xrow));
+    #pragma unroll
                         for (int b = 0; b < PW; ++b)
-#pragma unroll
-                            for (int c = 0; c < NC; ++c)
-                                gacc[b][c][q] = mfma(xv[q][j], rres[j >> 2][j & 3][b][c], gacc[b][c][q]);
-            }
+    #pragma unroll
+                            for (int c = 0; c < NC; ++c) {
+                                // hi/lo split with the hardware round-to-nearest-even conversion
+                                bf16x8 Rh, Rl;
+    #pragma unroll
+                                for (int j = 0; j < 8; ++j) {
+                                    const float v = rres[j >> 2][j & 3][b][c];
+                                    const __bf16 hb = (__bf16)v;
+                                    Rh[j] = hb;
+                                    Rl[j] = (__bf16)(v - (float)hb);
+                                }
+                                gacc[b][c][q] = mfma(th8, Rh, gacc[b][c][q]);
+                                gacc[b][c][q] = mfma(th8, Rl, gacc[b][c][q]);
+                                gacc[b][c][q] = mfma(tl8, Rh, gacc[b][c][q]);
+                            }
+                    }
+                } else {
+                    E xv[KBT][8];
+    #pragma unroll
+                    for (int q = 0; q < KBT; ++q) {
+                        const E* xt = (const E*)a.XT + (int64_t)(q * 16 + r16) * a.Tp + o + 8 * g;
+    #pragma unroll
+                        for (int j = 0; j < 8; ++j) xv[q][j] = xt[j];
+                    }
+    #pragma unroll
+                    for (int j = 0; j < 8; ++j)
+    #pragma unroll
+                        for (int q = 0; q < KBT; ++q)
+    #pragma unroll
+                            for (int b = 0; b < PW; ++b)
+    #pragma unroll
+                                for (int c = 0; c < NC; ++c)
+                                    gacc[b][c][q] = mfma(xv[q][j], rres[j >> 2][j & 3][b][c], gacc[b][c][q]);
+                }
             if (((st - st_begin) % kFoldSteps) == kFoldSteps - 1) fold();
+        }
+    };
+
+    if (st_begin < st_end) {
+        const std::integral_constant<int, 0> set0{};
+        load_a(set0, a.t0a + (int64_t)st_begin * 32);
+        if constexpr (PIPE) {
+            const std::integral_constant<int, 1> set1{};
+            if (st_begin + 1 < st_end) load_a(set1, a.t0a + (int64_t)(st_begin + 1) * 32);
+            mfma_fwd(set0);
+            for (int st = st_begin; st < st_end; st += 2) {
+                body(set0, st, st + 1 < st_end);
+                if (st + 1 >= st_end) break;
+                body(set1, st + 1, st + 2 < st_end);
+            }
+        } else {
+            for (int st = st_begin; st < st_end; ++st) body(set0, st, st + 1 < st_end);
         }
     }
     if constexpr (GRAD) {

@@ -74,19 +74,29 @@ __global__ __launch_bounds__(256) void cov_partial_kernel(const double* __restri
     }
 }
 
-// Sigma = h V, V = (S - P m m') / (P - 1) with S, m the shifted sums over all chunks.
-__global__ void cov_final_kernel(const double* __restrict__ part, const double* __restrict__ psum,
-                                 int32_t nchunk, int32_t d, int64_t P, double h, double* __restrict__ V) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// Sigma = h V, V = (S - P m m') / (P - 1) with S, m the shifted sums over all
+// chunks.  One wave per matrix element, lanes over chunks, butterfly sums.
+__global__ __launch_bounds__(256) void cov_final_kernel(const double* __restrict__ part,
+                                                        const double* __restrict__ psum, int32_t nchunk,
+                                                        int32_t d, int64_t P, double h,
+                                                        double* __restrict__ V) {
+    const int lane = threadIdx.x & 63;
+    const int64_t e = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (e >= (int64_t)d * d) return;
     const int32_t a = (int32_t)(e / d), b = (int32_t)(e % d);
     double s = 0.0, sa = 0.0, sb = 0.0;
-    for (int32_t q = 0; q < nchunk; ++q) {
+    for (int32_t q = lane; q < nchunk; q += 64) {
         s += part[(int64_t)q * d * d + e];
         sa += psum[(int64_t)q * d + a];
         sb += psum[(int64_t)q * d + b];
     }
-    V[e] = h * ((s - sa * sb / (double)P) / (double)(P - 1));
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) {
+        s += __shfl_xor(s, m, 64);
+        sa += __shfl_xor(sa, m, 64);
+        sb += __shfl_xor(sb, m, 64);
+    }
+    if (lane == 0) V[e] = h * ((s - sa * sb / (double)P) / (double)(P - 1));
 }
 
 // Cholesky V = L L' in one workgroup (left-looking, one column per step).
@@ -218,59 +228,71 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-// One wave per particle (four per block):
+// One wave per particle, kAccPerWave particles per wave in turn:
 // log alpha = [ll' + log p(theta')] - [ll + log p(theta)]
 //             (+ MALA: -|v|^2 / 2 + |z|^2 / 2, v = L^-1 (theta - mu(theta')), L L' = Sigma);
 // accept iff log u < log alpha; accepted particles take theta', ll' (grad').
+// Accepted particles are counted per block and added with one atomic.
+constexpr int kAccPerWave = 16;
 __global__ __launch_bounds__(256) void accept_kernel(
     double* __restrict__ theta, double* __restrict__ ll, double* __restrict__ grad,
     const double* __restrict__ theta2, const double* __restrict__ ll2,
     const double* __restrict__ grad2, const double* __restrict__ z, const double* __restrict__ v,
     const double* __restrict__ u, const double* __restrict__ mu, const double* __restrict__ isd,
     int64_t P, int32_t d, int mala, const unsigned* flags, unsigned long long* count) {
+    __shared__ unsigned nacc[4];
     const int lane = threadIdx.x & 63;
-    const int64_t p = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (p >= P || (*flags & kFlagNotPD)) return;
-    const double* a = theta + p * d;
-    const double* b = theta2 + p * d;
-    double q0 = 0.0, q1 = 0.0, vv = 0.0, zz = 0.0;
-    for (int32_t i = lane; i < d; i += 64) {
-        const double za = (a[i] - mu[i]) * isd[i];
-        const double zb = (b[i] - mu[i]) * isd[i];
-        q0 += za * za;
-        q1 += zb * zb;
-        if (mala) {
-            vv += v[p * d + i] * v[p * d + i];
-            zz += z[p * d + i] * z[p * d + i];
+    const int wave = threadIdx.x >> 6;
+    const bool ok = !(*flags & kFlagNotPD);
+    unsigned taken = 0;
+    for (int q = 0; q < kAccPerWave && ok; ++q) {
+        const int64_t p = ((int64_t)blockIdx.x * 4 + wave) * kAccPerWave + q;
+        if (p >= P) break;
+        const double* a = theta + p * d;
+        const double* b = theta2 + p * d;
+        double q0 = 0.0, q1 = 0.0, vv = 0.0, zz = 0.0;
+        for (int32_t i = lane; i < d; i += 64) {
+            const double za = (a[i] - mu[i]) * isd[i];
+            const double zb = (b[i] - mu[i]) * isd[i];
+            q0 += za * za;
+            q1 += zb * zb;
+            if (mala) {
+                vv += v[p * d + i] * v[p * d + i];
+                zz += z[p * d + i] * z[p * d + i];
+            }
+        }
+        q0 = wave_sum(q0);
+        q1 = wave_sum(q1);
+        double la = (ll2[p] - 0.5 * q1) - (ll[p] - 0.5 * q0);
+        if (mala) la += -0.5 * wave_sum(vv) + 0.5 * wave_sum(zz);
+        if (isnan(la)) la = -INFINITY;
+        if (log(u[p]) < la) {
+            for (int32_t i = lane; i < d; i += 64) {
+                theta[p * d + i] = b[i];
+                if (mala) grad[p * d + i] = grad2[p * d + i];
+            }
+            if (lane == 0) ll[p] = ll2[p];
+            ++taken;
         }
     }
-    q0 = wave_sum(q0);
-    q1 = wave_sum(q1);
-    double la = (ll2[p] - 0.5 * q1) - (ll[p] - 0.5 * q0);
-    if (mala) la += -0.5 * wave_sum(vv) + 0.5 * wave_sum(zz);
-    if (isnan(la)) la = -INFINITY;
-    if (log(u[p]) < la) {
-        for (int32_t i = lane; i < d; i += 64) {
-            theta[p * d + i] = b[i];
-            if (mala) grad[p * d + i] = grad2[p * d + i];
-        }
-        if (lane == 0) {
-            ll[p] = ll2[p];
-            atomicAdd(count, 1ull);
-        }
+    if (lane == 0) nacc[wave] = taken;
+    __syncthreads();
+    if (threadIdx.x == 0 && ok) {
+        const unsigned tot = nacc[0] + nacc[1] + nacc[2] + nacc[3];
+        if (tot) atomicAdd(count, (unsigned long long)tot);
     }
 }
 
 // Cholesky and triangular inverse with the matrix held in LDS (d <= 64).
 constexpr int kSmallD = 64;
-__global__ __launch_bounds__(256) void cholesky_small_kernel(const double* __restrict__ V, int32_t d,
-                                                             double* __restrict__ L, unsigned* flags) {
+__global__ __launch_bounds__(64) void cholesky_small_kernel(const double* __restrict__ V, int32_t d,
+                                                            double* __restrict__ L, unsigned* flags) {
     __shared__ double Ls[kSmallD][kSmallD + 1];
     __shared__ double col[kSmallD];
     __shared__ int fail_s;
     const int t = threadIdx.x;
     if (t == 0) fail_s = 0;
-    for (int e = t; e < d * d; e += 256) Ls[e / d][e % d] = (e % d <= e / d) ? V[e] : 0.0;
+    for (int e = t; e < d * d; e += 64) Ls[e / d][e % d] = (e % d <= e / d) ? V[e] : 0.0;
     __syncthreads();
     for (int j = 0; j < d; ++j) {
         if (t >= j && t < d) {
@@ -292,16 +314,16 @@ __global__ __launch_bounds__(256) void cholesky_small_kernel(const double* __res
         if (t >= j && t < d) Ls[t][j] = (t == j) ? ljj : col[t] / ljj;
         __syncthreads();
     }
-    for (int e = t; e < d * d; e += 256) L[e] = Ls[e / d][e % d];
+    for (int e = t; e < d * d; e += 64) L[e] = Ls[e / d][e % d];
 }
 
-__global__ __launch_bounds__(256) void trinv_small_kernel(const double* __restrict__ L, int32_t d,
-                                                          double* __restrict__ W, const unsigned* flags) {
+__global__ __launch_bounds__(64) void trinv_small_kernel(const double* __restrict__ L, int32_t d,
+                                                         double* __restrict__ W, const unsigned* flags) {
     __shared__ double Ls[kSmallD][kSmallD + 1];
     __shared__ double Ws[kSmallD][kSmallD + 1];
     if (*flags & kFlagNotPD) return;
     const int t = threadIdx.x;
-    for (int e = t; e < d * d; e += 256) {
+    for (int e = t; e < d * d; e += 64) {
         Ls[e / d][e % d] = L[e];
         Ws[e / d][e % d] = 0.0;
     }
@@ -314,7 +336,7 @@ __global__ __launch_bounds__(256) void trinv_small_kernel(const double* __restri
         }
         __syncthreads();
     }
-    for (int e = t; e < d * d; e += 256) W[e] = Ws[e / d][e % d];
+    for (int e = t; e < d * d; e += 64) W[e] = Ws[e / d][e % d];
 }
 
 static inline unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
@@ -388,10 +410,11 @@ static int mutate_impl(sps_ctx* c, const char* who, double* theta, double* ll, d
         cov_partial_kernel<<<dim3((d + 63) / 64, (d + 63) / 64, nchunk), 256, 0, c->stream>>>(
             theta, P, d, chunk, part, psum);
         SPS_CHECK(launched(c, "cov_partial_kernel"));
-        cov_final_kernel<<<nblk((int64_t)d * d), 256, 0, c->stream>>>(part, psum, nchunk, d, P, h, Sg);
+        cov_final_kernel<<<(unsigned)(((int64_t)d * d + 3) / 4), 256, 0, c->stream>>>(part, psum, nchunk, d, P,
+                                                                                      h, Sg);
         SPS_CHECK(launched(c, "cov_final_kernel"));
     }
-    if (d <= kSmallD) cholesky_small_kernel<<<1, 256, 0, c->stream>>>(Sg, d, L, flags);
+    if (d <= kSmallD) cholesky_small_kernel<<<1, 64, 0, c->stream>>>(Sg, d, L, flags);
     else cholesky_kernel<<<1, 1024, 0, c->stream>>>(Sg, d, L, flags);
     SPS_CHECK(launched(c, "cholesky_kernel"));
 
@@ -405,7 +428,7 @@ static int mutate_impl(sps_ctx* c, const char* who, double* theta, double* ll, d
         double* gpi = (double*)c->pstat.p;
         double* work = gpi + Pd;
         double* g2 = (double*)c->grad2.p;
-        if (d <= kSmallD) trinv_small_kernel<<<1, 256, 0, c->stream>>>(L, d, W, flags);
+        if (d <= kSmallD) trinv_small_kernel<<<1, 64, 0, c->stream>>>(L, d, W, flags);
         else trinv_kernel<<<1, 1024, 0, c->stream>>>(L, d, W, flags);
         SPS_CHECK(launched(c, "trinv_kernel"));
         // mu(theta) = theta + (1/2) Sigma grad log pi(theta); theta' = mu + L z
@@ -426,7 +449,7 @@ static int mutate_impl(sps_ctx* c, const char* who, double* theta, double* ll, d
         gemm_abt_kernel<<<gg, 256, 0, c->stream>>>(work, W, nullptr, gpi, P, d, 1.0);
         SPS_CHECK(launched(c, "gemm_abt_kernel"));
     }
-    accept_kernel<<<(unsigned)((P + 3) / 4), 256, 0, c->stream>>>(
+    accept_kernel<<<(unsigned)((P + 4 * kAccPerWave - 1) / (4 * kAccPerWave)), 256, 0, c->stream>>>(
         theta, ll, grad, th2, ll2, mala ? (const double*)c->grad2.p : nullptr, z,
         mala ? (const double*)c->pstat.p : nullptr, u, c->prior_mean, c->prior_isd, P, d, mala ? 1 : 0,
         flags, count);

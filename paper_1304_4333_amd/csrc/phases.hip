@@ -83,46 +83,95 @@ __global__ void correct_chunk_sum_kernel(const double* __restrict__ lw, int64_t 
     tot[(int64_t)ch * P + p] = s;
 }
 
-__global__ void correct_prefix_kernel(double* __restrict__ lw, const double* __restrict__ carry,
-                                      const double* __restrict__ tot, int64_t P, int32_t nb) {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// Pass 2 of the scan fused with the ESS statistics.  Thread (p, chunk)
+// turns its per-observation terms into running log-weights (written back in
+// place); for every observation u of the chunk each block reduces, over its
+// 256 particles, m = max lw, s1 = sum exp(lw - m), s2 = sum exp(2 (lw - m))
+// into part[(u * npb + block) * 3 + {0, 1, 2}].  flags |= 1 on NaN or +inf.
+__global__ __launch_bounds__(256) void correct_scan_ess_kernel(double* __restrict__ lw,
+                                                               const double* __restrict__ carry,
+                                                               const double* __restrict__ tot, int64_t P,
+                                                               int32_t nb, double* __restrict__ part,
+                                                               unsigned* flags) {
+    __shared__ double wm[4][kScanChunk], ws1[4][kScanChunk], ws2[4][kScanChunk];
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const int32_t ch = blockIdx.y;
-    if (p >= P) return;
-    double acc = carry[p];
-    for (int32_t q = 0; q < ch; ++q) acc += tot[(int64_t)q * P + p];
-    const int32_t u1 = min(nb, (ch + 1) * kScanChunk);
-    for (int32_t u = ch * kScanChunk; u < u1; ++u) {
-        acc += lw[(int64_t)u * P + p];
-        lw[(int64_t)u * P + p] = acc;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int32_t npb = gridDim.x;
+    const bool pv = p < P;
+    double acc = 0.0;
+    if (pv) {
+        acc = carry[p];
+        for (int32_t q = 0; q < ch; ++q) acc += tot[(int64_t)q * P + p];
+    }
+    const int32_t u0 = ch * kScanChunk;
+    const int32_t u1 = min(nb, u0 + kScanChunk);
+    bool bad = false;
+    for (int32_t u = u0; u < u1; ++u) {
+        double v = -INFINITY;
+        if (pv) {
+            acc += lw[(int64_t)u * P + p];
+            lw[(int64_t)u * P + p] = acc;
+            v = acc;
+            bad |= isnan(acc) || acc == INFINITY;
+        }
+        double m = v;
+#pragma unroll
+        for (int sh = 32; sh > 0; sh >>= 1) m = fmax(m, __shfl_xor(m, sh, 64));
+        const double w = (m > -INFINITY && v > -INFINITY) ? exp(v - m) : 0.0;
+        double s1 = w, s2 = w * w;
+#pragma unroll
+        for (int sh = 32; sh > 0; sh >>= 1) {
+            s1 += __shfl_xor(s1, sh, 64);
+            s2 += __shfl_xor(s2, sh, 64);
+        }
+        if (lane == 0) {
+            wm[wave][u - u0] = m;
+            ws1[wave][u - u0] = s1;
+            ws2[wave][u - u0] = s2;
+        }
+    }
+    if (bad) atomicOr(flags, 1u);
+    __syncthreads();
+    const int uu = threadIdx.x;
+    if (uu < u1 - u0) {
+        double M = fmax(fmax(wm[0][uu], wm[1][uu]), fmax(wm[2][uu], wm[3][uu]));
+        double S1 = 0.0, S2 = 0.0;
+        if (M > -INFINITY) {
+            for (int w = 0; w < 4; ++w) {
+                if (wm[w][uu] > -INFINITY) {
+                    const double f = exp(wm[w][uu] - M);
+                    S1 += ws1[w][uu] * f;
+                    S2 += ws2[w][uu] * f * f;
+                }
+            }
+        }
+        double* o = part + ((int64_t)(u0 + uu) * npb + blockIdx.x) * 3;
+        o[0] = M;
+        o[1] = S1;
+        o[2] = S2;
     }
 }
 
-// ESS(u) = (sum_p w)^2 / sum_p w^2 with w = exp(lw - max_p lw), one block per
-// observation u.  flags |= 1 if a log-weight is NaN or +inf.
-__global__ void correct_ess_kernel(const double* __restrict__ lw, int64_t P, double* __restrict__ ess,
-                                   unsigned* flags) {
-    __shared__ double red[256];
-    const double* col = lw + (int64_t)blockIdx.x * P;
-    double m = -INFINITY;
-    bool bad = false;
-    for (int64_t p = threadIdx.x; p < P; p += 256) {
-        const double v = col[p];
-        bad |= isnan(v) || v == INFINITY;
-        m = fmax(m, v);
-    }
-    if (bad) atomicOr(flags, 1u);
-    m = block_max256(m, red);
-    double s1 = 0.0, s2 = 0.0;
-    if (m > -INFINITY) {
-        for (int64_t p = threadIdx.x; p < P; p += 256) {
-            const double w = exp(col[p] - m);
-            s1 += w;
-            s2 += w * w;
+// ESS(u) = S1^2 / S2 from the per-block partials, combined in block order.
+__global__ void correct_ess_combine_kernel(const double* __restrict__ part, int32_t npb, int32_t nb,
+                                           double* __restrict__ ess) {
+    const int32_t u = blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= nb) return;
+    const double* q = part + (int64_t)u * npb * 3;
+    double M = -INFINITY;
+    for (int32_t b = 0; b < npb; ++b) M = fmax(M, q[3 * b]);
+    double S1 = 0.0, S2 = 0.0;
+    if (M > -INFINITY) {
+        for (int32_t b = 0; b < npb; ++b) {
+            if (q[3 * b] > -INFINITY) {
+                const double f = exp(q[3 * b] - M);
+                S1 += q[3 * b + 1] * f;
+                S2 += q[3 * b + 2] * f * f;
+            }
         }
     }
-    s1 = block_sum256(s1, red);
-    s2 = block_sum256(s2, red);
-    if (threadIdx.x == 0) ess[blockIdx.x] = (m > -INFINITY) ? s1 * s1 / s2 : 0.0;
+    ess[u] = (M > -INFINITY) ? S1 * S1 / S2 : 0.0;
 }
 
 // First u in [0, nb) with ESS(u) < thr, or the last observation of the data.
@@ -511,12 +560,16 @@ extern "C" int sps_correct(sps_ctx* c, const double* theta, double* ll, int32_t 
     const int32_t kMaxBlock =
         (int32_t)std::max<int64_t>(kScanChunk, std::min<int64_t>(2048, (int64_t(32) << 20) / P / kScanChunk * kScanChunk));
     const int32_t nchmax = (kMaxBlock + kScanChunk - 1) / kScanChunk;
+    const int64_t npb = (P + 255) / 256;
     SPS_CHECK(ensure(c, c->corr_lw, sizeof(double) * P * kMaxBlock, "C-phase block"));
-    SPS_CHECK(ensure(c, c->corr_red, sizeof(double) * (kMaxBlock + (size_t)nchmax * P), "C-phase ESS"));
+    SPS_CHECK(ensure(c, c->corr_red,
+                     sizeof(double) * (kMaxBlock + (size_t)nchmax * P + (size_t)kMaxBlock * npb * 3),
+                     "C-phase ESS"));
     SPS_CHECK(zero_flags(c));
     double* lwblk = (double*)c->corr_lw.p;
     double* ess = (double*)c->corr_red.p;
     double* tot = ess + kMaxBlock;
+    double* epart = tot + (size_t)nchmax * P;
     double* res = (double*)c->small.p + 2;  // [2], [3]: index, ESS
     unsigned* flags = (unsigned*)c->small.p;
     const unsigned pg = (unsigned)((P + 255) / 256);
@@ -531,10 +584,10 @@ extern "C" int sps_correct(sps_ctx* c, const double* theta, double* ll, int32_t 
         SPS_CHECK(loglik_perobs(c, theta, P, s, s + nb, prec, lwblk));
         correct_chunk_sum_kernel<<<dim3(pg, nch), 256, 0, c->stream>>>(lwblk, P, nb, tot);
         SPS_CHECK(launched(c, "correct_chunk_sum_kernel"));
-        correct_prefix_kernel<<<dim3(pg, nch), 256, 0, c->stream>>>(lwblk, log_w, tot, P, nb);
-        SPS_CHECK(launched(c, "correct_prefix_kernel"));
-        correct_ess_kernel<<<nb, 256, 0, c->stream>>>(lwblk, P, ess, flags);
-        SPS_CHECK(launched(c, "correct_ess_kernel"));
+        correct_scan_ess_kernel<<<dim3(pg, nch), 256, 0, c->stream>>>(lwblk, log_w, tot, P, nb, epart, flags);
+        SPS_CHECK(launched(c, "correct_scan_ess_kernel"));
+        correct_ess_combine_kernel<<<(unsigned)((nb + 255) / 256), 256, 0, c->stream>>>(epart, (int32_t)npb, nb, ess);
+        SPS_CHECK(launched(c, "correct_ess_combine_kernel"));
         correct_find_kernel<<<1, 64, 0, c->stream>>>(ess, nb, thr, s, c->T, res);
         SPS_CHECK(launched(c, "correct_find_kernel"));
         SPS_HIP(c, hipMemcpyAsync(c->hostbuf.p, c->small.p, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
