@@ -142,6 +142,47 @@ def sps_fixed_nse(w, seeds):
             "max_mean_z_A_vs_B": round(float(z.max()), 2), "seeds": list(seeds)}
 
 
+PREC_SOURCES = {"fp64": ("loglik_fp64.hip",), "fp32": ("loglik_fp32.hip",),
+                "bf16x3": ("loglik_bf16.hip", "loglik_bf16_wide.hip")}
+
+
+def kernel_digest(precision):
+    """Digest of the likelihood kernel sources and compile flags of one
+    precision: HBM traffic counters taken on other sources do not describe
+    the current kernel."""
+    import hashlib
+    from paper_1304_4333_amd import build
+    root = os.path.dirname(os.path.abspath(__file__))
+    h = hashlib.sha256()
+    for f in ("loglik_kernel.h", "loglik.hip", "sps_internal.h") + PREC_SOURCES[precision]:
+        with open(os.path.join(root, "paper_1304_4333_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+        h.update(" ".join(build.CFLAGS[:-2] + build.FILE_FLAGS.get(f, [])).encode())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload, kernel, precision):
+    """HBM bytes per launch of `kernel` on `workload` from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE summary, if it was taken on the current
+    kernel sources; otherwise None."""
+    root = os.path.dirname(os.path.abspath(__file__))
+    path = os.path.join(root, "profiles", f"{kernel}_{workload}_traffic.md")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and line.startswith("- "):
+                k, v = line[2:].split(":", 1)
+                fields[k.strip()] = v.strip().strip("`")
+    if fields.get("kernel_digest") != kernel_digest(precision):
+        return None
+    try:
+        return int(fields["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def roofline(w, res):
     """Dominant likelihood kernel: algorithmic MFMA flops per launch over its
     average HIP-event duration.  Forward: 2 k (C-1) flops per particle x
@@ -159,7 +200,7 @@ def roofline(w, res):
     dt = DTYPE[w.precision]
     peak = PEAK_TFLOPS[dt]
     return dict(bound="mfma", achieved=round(achieved, 3), peak=peak, unit="TFLOP/s",
-                frac=round(achieved / peak, 4), traffic=None), \
+                frac=round(achieved / peak, 4), traffic=measured_traffic(w.name, name, w.precision)), \
         dict(kernel=name, launches=n, avg_us=round(ms / n * 1e3, 2), flops_per_launch=flops)
 
 
@@ -241,6 +282,19 @@ def kernel_table(names, reps=5):
     return rows
 
 
+def copy_calibration(mib=1024, reps=3):
+    """A plain device-to-device copy of known size (reads and writes `mib`
+    MiB per launch): the reference that scales the FETCH_SIZE / WRITE_SIZE
+    counters of the likelihood kernel to bytes."""
+    import torch
+    src = torch.ones(mib << 18, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_per_launch": src.numel() * 4, "launches": reps}))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -253,7 +307,12 @@ def main():
     ap.add_argument("--sps-seeds", type=int, default=2)
     ap.add_argument("--kernel-table", default=None,
                     help="comma-separated workloads: print full-data loglik/grad rates instead")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run only a device copy of 1 GiB (counter calibration)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.kernel_table:
         kernel_table(args.kernel_table.split(","))
         return

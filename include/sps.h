@@ -94,6 +94,28 @@ int sps_set_data(sps_ctx* ctx, const double* X, const int32_t* y, int64_t T,
  * Requires sps_set_data first (d is taken from it). */
 int sps_set_prior(sps_ctx* ctx, const double* mean, const double* sd);
 
+/* Prior of the free parameters: N(mean, cov) with a full covariance, e.g.
+ * the normalised prior of eq. (prior_norm).  mean: host, d FP64 (NULL:
+ * zero); cov: host, d x d FP64 row-major, symmetric (to 1e-12 relative)
+ * and positive definite.  The library keeps its own copy (Cholesky factor
+ * and inverse on the device).  SPS_ERR_NOT_PD if cov is not positive
+ * definite, SPS_ERR_ARG if not symmetric or not finite.  Requires
+ * sps_set_data first.  Synchronises the stream. */
+int sps_set_prior_cov(sps_ctx* ctx, const double* mean, const double* cov);
+
+/* The normalised g-prior: theta_c ~ iid N(0, Sigma) for all C outcomes
+ * before normalisation on outcome 0, Sigma = g T (X'X)^-1 (eq.
+ * (g-prior_def)); the free vectors theta_c - theta_0 then have variance
+ * 2 Sigma and pairwise covariance Sigma (eq. (prior_norm)).  X'X is formed
+ * on the device in FP64 from the data of sps_set_data.  g > 0; mean: host,
+ * d FP64 or NULL (zero).  SPS_ERR_NOT_PD if X'X is singular.
+ * Synchronises the stream. */
+int sps_set_prior_g(sps_ctx* ctx, double g, const double* mean);
+
+/* Copy the d x d prior covariance in use (diagonal after sps_set_prior)
+ * into cov (host, row-major). */
+int sps_get_prior_cov(sps_ctx* ctx, double* cov);
+
 /* ------------------------------------------------------- random numbers */
 
 /* Philox4x32-10 variates of a stream (the same definitions as used inside

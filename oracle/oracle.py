@@ -66,6 +66,7 @@ def lib():
         L.orc_logprior.restype = None
         L.orc_init_prior.argtypes = [_d, _d, ct.c_int32, ct.c_int64, ct.c_uint64, ct.c_uint64, _d]
         L.orc_init_prior.restype = None
+        L.orc_gprior_cov.argtypes = [_d, ct.c_int64, ct.c_int32, ct.c_int32, ct.c_double, _d]
         L.orc_correct.argtypes = [_d, _i32, ct.c_int64, ct.c_int32, ct.c_int32, _d, _d,
                                   ct.c_int32, ct.c_int32, ct.c_int64, ct.c_double, _d, _i64, _d]
         L.orc_ess.argtypes = [_d, ct.c_int64]
@@ -157,24 +158,42 @@ def loglik(X, y, C, theta, t0=0, t1=None, grad=False):
     return ll
 
 
-def logprior(theta, mean, sd):
+def prior_factor(d, sd=1.0, cov=None):
+    """Lower Cholesky factor L (d x d) of the prior covariance: diag(sd) for
+    independent components, else the oracle's own Cholesky of cov."""
+    if cov is None:
+        return np.diag(_f64(np.broadcast_to(sd, (d,))).copy())
+    return cholesky(cov)
+
+
+def logprior(theta, mean, sd=1.0, cov=None):
     theta = _f64(theta)
     P, d = theta.shape
     mean = _f64(np.broadcast_to(mean, (d,)))
-    sd = _f64(np.broadcast_to(sd, (d,)))
+    L = prior_factor(d, sd, cov)
     lp = np.zeros(P)
     g = np.zeros_like(theta)
-    lib().orc_logprior(_p(theta, _d), P, d, _p(mean, _d), _p(sd, _d), _p(lp, _d), _p(g, _d))
+    lib().orc_logprior(_p(theta, _d), P, d, _p(mean, _d), _p(L, _d), _p(lp, _d), _p(g, _d))
     return lp, g
 
 
-def init_prior(mean, sd, P, seed, stream):
+def init_prior(mean, sd, P, seed, stream, cov=None):
     mean = _f64(mean)
-    sd = _f64(sd)
     d = mean.shape[0]
+    L = prior_factor(d, sd, cov)
     th = np.zeros((P, d))
-    lib().orc_init_prior(_p(mean, _d), _p(sd, _d), d, P, seed, stream, _p(th, _d))
+    lib().orc_init_prior(_p(mean, _d), _p(L, _d), d, P, seed, stream, _p(th, _d))
     return th
+
+
+def gprior_cov(X, C, g):
+    """Covariance of the free parameters under the normalised g-prior."""
+    X = _f64(X)
+    T, k = X.shape
+    d = k * (C - 1)
+    cov = np.zeros((d, d))
+    _check(lib().orc_gprior_cov(_p(X, _d), T, k, C, float(g), _p(cov, _d)), "gprior_cov")
+    return cov
 
 
 # ---------------------------------------------------------------- C phase
@@ -252,7 +271,8 @@ def cholesky(V):
     return L
 
 
-def mutate_cov(X, y, C, prior_mean, prior_sd, theta, ll, grad, J, N, t, Sigma, kind, z, u):
+def mutate_cov(X, y, C, prior_mean, prior_sd, theta, ll, grad, J, N, t, Sigma, kind, z, u,
+               prior_cov=None):
     """One M step with proposal covariance Sigma (d x d).  Returns
     (theta, ll, grad, rate, log_alpha, accepted); inputs untouched."""
     X = _f64(X)
@@ -263,7 +283,7 @@ def mutate_cov(X, y, C, prior_mean, prior_sd, theta, ll, grad, J, N, t, Sigma, k
     ll = _f64(ll).copy()
     grad = None if grad is None else _f64(grad).copy()
     pm = _f64(np.broadcast_to(prior_mean, (d,)))
-    ps = _f64(np.broadcast_to(prior_sd, (d,)))
+    ps = prior_factor(d, prior_sd, prior_cov)
     S = _f64(Sigma)
     z = _f64(z)
     u = _f64(u)
@@ -278,7 +298,7 @@ def mutate_cov(X, y, C, prior_mean, prior_sd, theta, ll, grad, J, N, t, Sigma, k
     return theta, ll, grad, rate.value, la, acc.astype(bool)
 
 
-def mutate(X, y, C, prior_mean, prior_sd, theta, ll, grad, J, N, t, h, kind, z, u):
+def mutate(X, y, C, prior_mean, prior_sd, theta, ll, grad, J, N, t, h, kind, z, u, prior_cov=None):
     """One M step.  Returns (theta, ll, grad, rate, log_alpha, accepted); inputs untouched."""
     X = _f64(X)
     y = np.ascontiguousarray(y, dtype=np.int32)
@@ -288,7 +308,7 @@ def mutate(X, y, C, prior_mean, prior_sd, theta, ll, grad, J, N, t, h, kind, z, 
     ll = _f64(ll).copy()
     grad = None if grad is None else _f64(grad).copy()
     pm = _f64(np.broadcast_to(prior_mean, (d,)))
-    ps = _f64(np.broadcast_to(prior_sd, (d,)))
+    ps = prior_factor(d, prior_sd, prior_cov)
     z = _f64(z)
     u = _f64(u)
     P = J * N
@@ -315,7 +335,8 @@ def moments(g, J, N):
 
 def sps_run(X, y, C, prior_mean, prior_sd, J, N, seed, kind=RW, scheme=RESIDUAL, rne_rule=0,
             R_max=100, ess_frac=0.5, K_mid=0.35, K_final=0.9, h_init=0.5, h_step=0.01,
-            h_min=0.1, h_max=1.0, acc_target=0.25, max_cycles=4096, record_sigma=0):
+            h_min=0.1, h_max=1.0, acc_target=0.25, max_cycles=4096, record_sigma=0,
+            prior_cov=None):
     """Full adaptive SPS (Algorithm 2).  Returns a dict of results; with
     record_sigma = n > 0 the proposal covariances of the first n M steps are
     returned too (the design of Algorithm 3's first pass)."""
@@ -326,7 +347,7 @@ def sps_run(X, y, C, prior_mean, prior_sd, J, N, seed, kind=RW, scheme=RESIDUAL,
     m = d + C - 1
     P = J * N
     pm = _f64(np.broadcast_to(prior_mean, (d,)))
-    ps = _f64(np.broadcast_to(prior_sd, (d,)))
+    ps = prior_factor(d, prior_sd, prior_cov)
     cfg = Config(J=J, N=N, kind=kind, scheme=scheme, rne_rule=rne_rule, R_max=R_max,
                  max_cycles=max_cycles, pad_=0, ess_frac=ess_frac, K_mid=K_mid,
                  K_final=K_final, h_init=h_init, h_step=h_step, h_min=h_min, h_max=h_max,
@@ -358,7 +379,7 @@ def sps_run(X, y, C, prior_mean, prior_sd, J, N, seed, kind=RW, scheme=RESIDUAL,
 
 
 def sps_run_fixed(X, y, C, prior_mean, prior_sd, J, N, seed, t, R, sigma, kind=RW,
-                  scheme=RESIDUAL):
+                  scheme=RESIDUAL, prior_cov=None):
     """Algorithm 1 with a fixed design (the second pass of Algorithm 3)."""
     X = _f64(X)
     y = np.ascontiguousarray(y, dtype=np.int32)
@@ -367,7 +388,7 @@ def sps_run_fixed(X, y, C, prior_mean, prior_sd, J, N, seed, t, R, sigma, kind=R
     m = d + C - 1
     P = J * N
     pm = _f64(np.broadcast_to(prior_mean, (d,)))
-    ps = _f64(np.broadcast_to(prior_sd, (d,)))
+    ps = prior_factor(d, prior_sd, prior_cov)
     cfg = Config(J=J, N=N, kind=kind, scheme=scheme, seed=seed)
     tt = np.ascontiguousarray(t, dtype=np.int64)
     RR = np.ascontiguousarray(R, dtype=np.int32)
@@ -389,5 +410,5 @@ def sps_two_pass(X, y, C, prior_mean, prior_sd, J, N, seed, kind=RW, **kw):
     particles are discarded and a second, nonadaptive pass reruns with it."""
     p1 = sps_run(X, y, C, prior_mean, prior_sd, J, N, seed, kind=kind, record_sigma=20000, **kw)
     p2 = sps_run_fixed(X, y, C, prior_mean, prior_sd, J, N, seed, p1["t"], p1["R"], p1["sigma"],
-                       kind=kind, scheme=kw.get("scheme", RESIDUAL))
+                       kind=kind, scheme=kw.get("scheme", RESIDUAL), prior_cov=kw.get("prior_cov"))
     return p1, p2

@@ -173,30 +173,106 @@ int orc_loglik_grad(const double* X, const int32_t* y, int64_t T, int32_t k, int
     return ORC_OK;
 }
 
-/* Independent Gaussian prior on the free parameters, a special case of
- * eq. (prior_Gauss): theta_i ~ N(mean_i, sd_i^2).  glp may be NULL. */
+static void lower_solve(const double* L, int32_t d, const double* r, double* v);
+
+/* Gaussian prior on the free parameters, theta ~ N(mean, S) with S = L L'
+ * (L lower triangular, row-major d x d).  Eq. (prior_Gauss) with independent
+ * components gives a diagonal L; the normalised form of eq. (prior_norm),
+ * e.g. with the g-prior of eq. (g-prior_def), gives a full one.
+ *   log p = -d/2 log(2 pi) - sum_i log L_ii - |r|^2 / 2,  L r = theta - mean,
+ *   grad log p = -S^-1 (theta - mean) = -L'^-1 r.
+ * glp may be NULL. */
 void orc_logprior(const double* theta, int64_t P, int32_t d, const double* mean,
-                  const double* sd, double* lp, double* glp)
+                  const double* L, double* lp, double* glp)
 {
+    double logdet = 0.0;
+    for (int32_t i = 0; i < d; ++i) logdet += log(L[i * d + i]);
+    double* r = (double*)malloc(sizeof(double) * (d > 0 ? d : 1));
     for (int64_t p = 0; p < P; ++p) {
-        double acc = 0.0;
+        const double* th = theta + p * d;
+        /* forward substitution L r = theta - mean */
+        double q = 0.0;
         for (int32_t i = 0; i < d; ++i) {
-            double z = (theta[p * d + i] - mean[i]) / sd[i];
-            acc += -0.5 * log(2.0 * M_PI) - log(sd[i]) - 0.5 * z * z;
-            if (glp) glp[p * d + i] = -(theta[p * d + i] - mean[i]) / (sd[i] * sd[i]);
+            double s = th[i] - mean[i];
+            for (int32_t j = 0; j < i; ++j) s -= L[i * d + j] * r[j];
+            r[i] = s / L[i * d + i];
+            q += r[i] * r[i];
         }
-        lp[p] = acc;
+        lp[p] = -0.5 * d * log(2.0 * M_PI) - logdet - 0.5 * q;
+        if (glp) {
+            /* back substitution L' w = r, grad = -w */
+            double* g = glp + p * d;
+            for (int32_t i = d - 1; i >= 0; --i) {
+                double s = r[i];
+                for (int32_t j = i + 1; j < d; ++j) s -= L[j * d + i] * g[j];
+                g[i] = s / L[i * d + i];
+            }
+            for (int32_t i = 0; i < d; ++i) g[i] = -g[i];
+        }
     }
+    free(r);
 }
 
-/* Algorithm 1 step 1: particles iid from the prior. */
-void orc_init_prior(const double* mean, const double* sd, int32_t d, int64_t P,
+/* Algorithm 1 step 1: particles iid from the prior, theta = mean + L z. */
+void orc_init_prior(const double* mean, const double* L, int32_t d, int64_t P,
                     uint64_t seed, uint64_t stream, double* theta)
 {
-    orc_normals(seed, stream, P, d, theta);
+    double* z = (double*)malloc(sizeof(double) * (size_t)(P > 0 ? P : 1) * (d > 0 ? d : 1));
+    orc_normals(seed, stream, P, d, z);
     for (int64_t p = 0; p < P; ++p)
-        for (int32_t i = 0; i < d; ++i)
-            theta[p * d + i] = mean[i] + sd[i] * theta[p * d + i];
+        for (int32_t i = 0; i < d; ++i) {
+            double s = mean[i];
+            for (int32_t j = 0; j <= i; ++j) s += L[i * d + j] * z[p * d + j];
+            theta[p * d + i] = s;
+        }
+    free(z);
+}
+
+/* The prior covariance of eq. (prior_norm) for the model normalised on
+ * outcome 0, when theta_c ~ iid N(0, Sigma) for all C outcomes before
+ * normalisation and Sigma = g T (X'X)^-1 (eq. (g-prior_def)): the free
+ * vectors beta_c = theta_c - theta_0 (c = 1..C-1) have var 2 Sigma and
+ * pairwise covariance Sigma, i.e. block (i, j) of the d x d covariance is
+ * (1 + [i == j]) Sigma.  X'X is inverted through its Cholesky factor. */
+int orc_gprior_cov(const double* X, int64_t T, int32_t k, int32_t C, double g, double* cov)
+{
+    if (!data_ok(T, k, C, 0, 0) || T < 1 || !(g > 0.0)) return ORC_ERR_ARG;
+    int32_t d = k * (C - 1);
+    double* S = (double*)malloc(sizeof(double) * (size_t)k * k);
+    double* Ls = (double*)malloc(sizeof(double) * (size_t)k * k);
+    double* Sig = (double*)malloc(sizeof(double) * (size_t)k * k);
+    double* e = (double*)malloc(sizeof(double) * k);
+    double* v = (double*)malloc(sizeof(double) * k);
+    int status = ORC_OK;
+    if (!S || !Ls || !Sig || !e || !v) { status = ORC_ERR_NOMEM; goto done; }
+    for (int32_t a = 0; a < k; ++a)
+        for (int32_t b = 0; b < k; ++b) {
+            double s = 0.0;
+            for (int64_t t = 0; t < T; ++t) s += X[t * k + a] * X[t * k + b];
+            S[a * k + b] = s;
+        }
+    status = orc_cholesky(S, k, Ls);
+    if (status != ORC_OK) goto done;
+    /* column b of S^-1: solve Ls Ls' x = e_b */
+    for (int32_t b = 0; b < k; ++b) {
+        for (int32_t i = 0; i < k; ++i) e[i] = (i == b) ? 1.0 : 0.0;
+        lower_solve(Ls, k, e, v);
+        for (int32_t i = k - 1; i >= 0; --i) {
+            double s = v[i];
+            for (int32_t j = i + 1; j < k; ++j) s -= Ls[j * k + i] * e[j];
+            e[i] = s / Ls[i * k + i];
+        }
+        for (int32_t i = 0; i < k; ++i) Sig[i * k + b] = g * (double)T * e[i];
+    }
+    for (int32_t ci = 0; ci < C - 1; ++ci)
+        for (int32_t cj = 0; cj < C - 1; ++cj)
+            for (int32_t a = 0; a < k; ++a)
+                for (int32_t b = 0; b < k; ++b)
+                    cov[((int64_t)ci * k + a) * d + (int64_t)cj * k + b] =
+                        (ci == cj ? 2.0 : 1.0) * Sig[a * k + b];
+done:
+    free(S); free(Ls); free(Sig); free(e); free(v);
+    return status;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -476,7 +552,7 @@ static void mala_mean(const double* th, const double* glp, const double* Sigma, 
  * of the log-likelihood over the same observations) are cached per particle
  * and updated on acceptance.  Observations 1..t are used. */
 int orc_mutate_cov(const double* X, const int32_t* y, int64_t T, int32_t k, int32_t C,
-                   const double* prior_mean, const double* prior_sd,
+                   const double* prior_mean, const double* prior_L,
                    double* theta, double* ll, double* grad, int32_t J, int32_t N,
                    int64_t t, const double* Sigma, int32_t kind, const double* z, const double* u,
                    double* accept_rate, double* log_alpha_out, int8_t* accepted_out)
@@ -501,7 +577,7 @@ int orc_mutate_cov(const double* X, const int32_t* y, int64_t T, int32_t k, int3
     }
     status = orc_cholesky(Sigma, d, L);
     if (status != ORC_OK) goto done;
-    orc_logprior(theta, P, d, prior_mean, prior_sd, lp0, glp0);
+    orc_logprior(theta, P, d, prior_mean, prior_L, lp0, glp0);
     for (int64_t p = 0; p < P; ++p) {
         const double* th = theta + p * d;
         double* q = prop + p * d;
@@ -524,7 +600,7 @@ int orc_mutate_cov(const double* X, const int32_t* y, int64_t T, int32_t k, int3
     else
         status = orc_loglik(X, y, T, k, C, prop, P, 0, t, llp);
     if (status != ORC_OK) goto done;
-    orc_logprior(prop, P, d, prior_mean, prior_sd, lp1, glp1);
+    orc_logprior(prop, P, d, prior_mean, prior_L, lp1, glp1);
     int64_t acc = 0;
     for (int64_t p = 0; p < P; ++p) {
         double la = (llp[p] + lp1[p]) - (ll[p] + lp0[p]);
@@ -573,7 +649,7 @@ done:
  * sample variance of all particles, then one Metropolis step.  The Sigma
  * used is returned in sigma_out (d x d, may be NULL). */
 int orc_mutate(const double* X, const int32_t* y, int64_t T, int32_t k, int32_t C,
-               const double* prior_mean, const double* prior_sd,
+               const double* prior_mean, const double* prior_L,
                double* theta, double* ll, double* grad, int32_t J, int32_t N,
                int64_t t, double h, int32_t kind, const double* z, const double* u,
                double* accept_rate, double* log_alpha_out, int8_t* accepted_out,
@@ -589,7 +665,7 @@ int orc_mutate(const double* X, const int32_t* y, int64_t T, int32_t k, int32_t 
         orc_cov(theta, P, d, mean, V);
         for (int64_t i = 0; i < (int64_t)d * d; ++i) V[i] *= h;
         if (sigma_out) memcpy(sigma_out, V, sizeof(double) * (size_t)d * d);
-        status = orc_mutate_cov(X, y, T, k, C, prior_mean, prior_sd, theta, ll, grad, J, N, t, V,
+        status = orc_mutate_cov(X, y, T, k, C, prior_mean, prior_L, theta, ll, grad, J, N, t, V,
                                 kind, z, u, accept_rate, log_alpha_out, accepted_out);
     }
     free(mean);
@@ -660,7 +736,7 @@ static void monitored(const double* theta, int64_t P, int32_t k, int32_t C,
 }
 
 int orc_sps_run(const double* X, const int32_t* y, int64_t T, int32_t k, int32_t C,
-                const double* prior_mean, const double* prior_sd, const orc_config* cfg,
+                const double* prior_mean, const double* prior_L, const orc_config* cfg,
                 double* theta_out, double* ll_out,
                 double* mom_mean, double* mom_sd, double* mom_nse, double* mom_rne,
                 int64_t* rec_t, int32_t* rec_R, double* rec_h, double* rec_acc,
@@ -696,7 +772,7 @@ int orc_sps_run(const double* X, const int32_t* y, int64_t T, int32_t k, int32_t
         for (int32_t i = 0; i < k; ++i) xbar[i] += X[t * k + i];
     for (int32_t i = 0; i < k; ++i) xbar[i] /= (double)T;
 
-    orc_init_prior(prior_mean, prior_sd, d, P, cfg->seed, stream_id(0, 0, 0, 1), theta);
+    orc_init_prior(prior_mean, prior_L, d, P, cfg->seed, stream_id(0, 0, 0, 1), theta);
     for (int64_t p = 0; p < P; ++p) ll[p] = 0.0;
     double h = cfg->h_init;
     int64_t t = 0;
@@ -731,7 +807,7 @@ int orc_sps_run(const double* X, const int32_t* y, int64_t T, int32_t k, int32_t
             double* sig = NULL;
             if (rec_sigma && summary->m_iters + r <= sigma_cap)
                 sig = rec_sigma + (size_t)(summary->m_iters + r - 1) * d * d;
-            status = orc_mutate(X, y, T, k, C, prior_mean, prior_sd, theta, ll,
+            status = orc_mutate(X, y, T, k, C, prior_mean, prior_L, theta, ll,
                                 cfg->kind == ORC_MALA ? grad : NULL, J, N, t, h, cfg->kind,
                                 z, u, &rate, NULL, NULL, sig);
             if (status != ORC_OK) goto out;
@@ -772,7 +848,7 @@ out:
 /* pass.  Random streams carry pass = 1.                                     */
 /* ------------------------------------------------------------------------ */
 int orc_sps_run_fixed(const double* X, const int32_t* y, int64_t T, int32_t k, int32_t C,
-                      const double* prior_mean, const double* prior_sd, const orc_config* cfg,
+                      const double* prior_mean, const double* prior_L, const orc_config* cfg,
                       int32_t L, const int64_t* t_l, const int32_t* R_l, const double* Sigma,
                       double* theta_out, double* ll_out,
                       double* mom_mean, double* mom_sd, double* mom_nse, double* mom_rne,
@@ -807,7 +883,7 @@ int orc_sps_run_fixed(const double* X, const int32_t* y, int64_t T, int32_t k, i
         for (int32_t i = 0; i < k; ++i) xbar[i] += X[t * k + i];
     for (int32_t i = 0; i < k; ++i) xbar[i] /= (double)T;
 
-    orc_init_prior(prior_mean, prior_sd, d, P, cfg->seed, stream_id(1, 0, 0, 1), theta);
+    orc_init_prior(prior_mean, prior_L, d, P, cfg->seed, stream_id(1, 0, 0, 1), theta);
     for (int64_t p = 0; p < P; ++p) ll[p] = 0.0;
     int64_t step = 0;
     for (int32_t l = 0; l < L; ++l) {
@@ -834,7 +910,7 @@ int orc_sps_run_fixed(const double* X, const int32_t* y, int64_t T, int32_t k, i
             double rate = 0.0;
             orc_normals(cfg->seed, stream_id(1, cycle, r, 3), P, d, z);
             orc_uniforms(cfg->seed, stream_id(1, cycle, r, 4), P, u);
-            status = orc_mutate_cov(X, y, T, k, C, prior_mean, prior_sd, theta, ll,
+            status = orc_mutate_cov(X, y, T, k, C, prior_mean, prior_L, theta, ll,
                                     cfg->kind == ORC_MALA ? grad : NULL, J, N, t1,
                                     Sigma + (size_t)step * d * d, cfg->kind, z, u, &rate, NULL, NULL);
             if (status != ORC_OK) goto out;

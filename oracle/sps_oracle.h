@@ -40,10 +40,14 @@ int orc_loglik(const double* X, const int32_t* y, int64_t T, int32_t k, int32_t 
 int orc_loglik_grad(const double* X, const int32_t* y, int64_t T, int32_t k, int32_t C,
                     const double* theta, int64_t P, int64_t t0, int64_t t1,
                     double* ll, double* grad);
+/* Gaussian prior N(mean, L L'), L lower triangular d x d (diagonal for
+ * independent components, eq. (prior_Gauss); full for eq. (prior_norm)). */
 void orc_logprior(const double* theta, int64_t P, int32_t d, const double* mean,
-                  const double* sd, double* lp, double* glp);
-void orc_init_prior(const double* mean, const double* sd, int32_t d, int64_t P,
+                  const double* L, double* lp, double* glp);
+void orc_init_prior(const double* mean, const double* L, int32_t d, int64_t P,
                     uint64_t seed, uint64_t stream, double* theta);
+/* Normalised g-prior covariance, eqs. (g-prior_def) and (prior_norm). */
+int orc_gprior_cov(const double* X, int64_t T, int32_t k, int32_t C, double g, double* cov);
 
 /* C phase, Algorithm 1 step 2(a) with the ESS stopping rule of Algorithm 2. */
 int orc_correct(const double* X, const int32_t* y, int64_t T, int32_t k, int32_t C,
@@ -68,12 +72,12 @@ void orc_gather(const int32_t* ancestor, int64_t P, int32_t m, const double* src
 void orc_cov(const double* theta, int64_t P, int32_t d, double* mean, double* V);
 int orc_cholesky(const double* V, int32_t d, double* L);
 int orc_mutate_cov(const double* X, const int32_t* y, int64_t T, int32_t k, int32_t C,
-                   const double* prior_mean, const double* prior_sd,
+                   const double* prior_mean, const double* prior_L,
                    double* theta, double* ll, double* grad, int32_t J, int32_t N,
                    int64_t t, const double* Sigma, int32_t kind, const double* z, const double* u,
                    double* accept_rate, double* log_alpha_out, int8_t* accepted_out);
 int orc_mutate(const double* X, const int32_t* y, int64_t T, int32_t k, int32_t C,
-               const double* prior_mean, const double* prior_sd,
+               const double* prior_mean, const double* prior_L,
                double* theta, double* ll, double* grad, int32_t J, int32_t N,
                int64_t t, double h, int32_t kind, const double* z, const double* u,
                double* accept_rate, double* log_alpha_out, int8_t* accepted_out,
@@ -102,7 +106,7 @@ typedef struct {
 } orc_summary;
 
 int orc_sps_run(const double* X, const int32_t* y, int64_t T, int32_t k, int32_t C,
-                const double* prior_mean, const double* prior_sd, const orc_config* cfg,
+                const double* prior_mean, const double* prior_L, const orc_config* cfg,
                 double* theta_out, double* ll_out,
                 double* mom_mean, double* mom_sd, double* mom_nse, double* mom_rne,
                 int64_t* rec_t, int32_t* rec_R, double* rec_h, double* rec_acc,
@@ -110,7 +114,7 @@ int orc_sps_run(const double* X, const int32_t* y, int64_t T, int32_t k, int32_t
 
 /* Algorithm 1 with the design recorded by a first adaptive pass (Algorithm 3). */
 int orc_sps_run_fixed(const double* X, const int32_t* y, int64_t T, int32_t k, int32_t C,
-                      const double* prior_mean, const double* prior_sd, const orc_config* cfg,
+                      const double* prior_mean, const double* prior_L, const orc_config* cfg,
                       int32_t L, const int64_t* t_l, const int32_t* R_l, const double* Sigma,
                       double* theta_out, double* ll_out,
                       double* mom_mean, double* mom_sd, double* mom_nse, double* mom_rne,

@@ -1,4 +1,6 @@
-// loglik_bf16.hip -- instantiations of the likelihood kernel for SPS_BF16X3.
+// loglik_bf16.hip -- instantiations of the likelihood kernel for SPS_BF16X3,
+// C <= 5 outcomes (C >= 6 live in loglik_bf16_wide.hip, a separate unit so
+// the two compile in parallel).
 #include "loglik_kernel.h"
 
 namespace sps {
@@ -19,17 +21,8 @@ LoglikEntry lookup_bf16(int nc, int ks, int mode) {
     SPS_E(4, 1)
     SPS_E(4, 2)
     SPS_E(4, 4)
-    SPS_E(5, 1)
-    SPS_E(5, 2)
-    SPS_E(5, 4)
-    SPS_E(6, 1)
-    SPS_E(6, 2)
-    SPS_E(6, 4)
-    SPS_E(7, 1)
-    SPS_E(7, 2)
-    SPS_E(7, 4)
 #undef SPS_E
-    return LoglikEntry{};
+    return lookup_bf16_wide(nc, ks, mode);
 }
 
 }  // namespace sps

@@ -1,0 +1,24 @@
+// loglik_bf16_wide.hip -- instantiations of the likelihood kernel for
+// SPS_BF16X3 with C >= 6 outcomes (five or more outcome chains per wave).
+#include "loglik_kernel.h"
+
+namespace sps {
+
+LoglikEntry lookup_bf16_wide(int nc, int ks, int mode) {
+#define SPS_E(NC, KS) \
+    if (nc == NC && ks == KS) return mode == MODE_GRAD ? loglik_entry<SPS_BF16X3, NC, KS, MODE_GRAD>() \
+                                                      : loglik_entry<SPS_BF16X3, NC, KS, MODE_FWD>();
+    SPS_E(5, 1)
+    SPS_E(5, 2)
+    SPS_E(5, 4)
+    SPS_E(6, 1)
+    SPS_E(6, 2)
+    SPS_E(6, 4)
+    SPS_E(7, 1)
+    SPS_E(7, 2)
+    SPS_E(7, 4)
+#undef SPS_E
+    return LoglikEntry{};
+}
+
+}  // namespace sps

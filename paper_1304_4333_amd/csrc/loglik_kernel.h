@@ -57,10 +57,6 @@ constexpr double kLn2 = 0.69314718055994530942;
 
 enum { MODE_FWD = 0, MODE_GRAD = 1 };
 
-#ifndef SPS_PW_BUDGET
-#define SPS_PW_BUDGET 128
-#endif
-
 struct LoglikArgs {
     const void* X;      // row-major kernel copy of X (FP64 / FP32 / BF16 hi)
     const void* Xlo;    // BF16 lo part (BF16X3 only)
@@ -121,9 +117,10 @@ template <> struct Prec<SPS_BF16X3> {
     static constexpr int KPS = 32;
 };
 
-// Register estimates (32-bit registers per lane) behind two compile-time
-// choices: PW, the particle blocks (of 16) per wave, and whether the step loop
-// is software-pipelined (two sets of forward accumulators and A fragments).
+// Two compile-time choices: PW, the particle blocks (of 16) per wave, and
+// whether the step loop is software-pipelined (two sets of forward
+// accumulators and A fragments).  The register counts (32-bit registers per
+// lane) bound PW.
 template <int PREC, int NC, int KS, int MODE>
 struct Shape {
     static constexpr bool BF = PREC == SPS_BF16X3;
@@ -134,10 +131,17 @@ struct Shape {
     static constexpr int grad = MODE == MODE_GRAD ? (4 * w * kbt + 8 * w) : 0;
     static constexpr int afrag = 2 * (BF ? 8 * KS : w * KS);      // one set: two tiles
     static constexpr int per1 = NC * (breg + accr + grad);
-    static constexpr int budget = 96;
-    static constexpr int PW = afrag + 4 * per1 <= budget ? 4 : (afrag + 2 * per1 <= budget ? 2 : 1);
-    // pipelining doubles the accumulators and fragments
-    static constexpr bool PIPE = 2 * afrag + PW * (per1 + NC * accr) <= 128;
+    // Measured on gfx950 (binary k=30 in all three precisions, BF16 with
+    // k = 20/50/100 and C = 4/6): two particle blocks per wave pay off when a
+    // wave has a single outcome column, i.e. each X fragment feeds NC*PW = 2
+    // MFMA chains; with C > 2 the outcome columns already give that reuse and
+    // the extra registers cost occupancy.  The FP64 adjoint (64 registers per
+    // block) is the exception.  Over 256 live registers per lane, use one.
+    static constexpr int PW =
+        (NC == 1 && !(PREC == SPS_FP64 && MODE == MODE_GRAD) && afrag + 2 * per1 <= 256) ? 2 : 1;
+    // Double-buffering the X fragments measured slower or equal everywhere
+    // (it doubles the live fragments and accumulators): off by default.
+    static constexpr bool PIPE = false;
 };
 
 template <int PREC, int NC, int KS, int MODE>
@@ -164,6 +168,9 @@ __global__ __launch_bounds__(256) void loglik_kernel(LoglikArgs a) {
     // the adjoint; both are added outside this kernel, which then evaluates
     // only -log sum_c exp(eta_c) and -pi_c (no outcome needed).
     constexpr bool SUFF = (NC > 1) && !F64;
+    // Steps take an unshifted fast form of the epilogue first and are redone
+    // with the max-shifted form when a lane leaves its safe range (see body).
+    constexpr bool FASTOK = SUFF || (NC == 1 && !F64);
     // The FP32 adjoint accumulators are added into the wave's FP64 output
     // slice every kFoldSteps steps (4096 observations), bounding the length
     // of any FP32 running sum; FP64 accumulates in registers throughout.
@@ -229,6 +236,9 @@ __global__ __launch_bounds__(256) void loglik_kernel(LoglikArgs a) {
 #pragma unroll
                 for (int q = 0; q < KBT; ++q) gacc[b][c][q] = Acc{0, 0, 0, 0};
     }
+    // The binary FP32/BF16 epilogue hands the adjoint +sigmoid instead of the
+    // residual -sigmoid (saves a sign flip per element); the sign is applied here.
+    constexpr bool kNegRes = (NC == 1) && !F64;
     double* const g_out = GRAD ? a.out_g + (int64_t)split * a.P * a.d : nullptr;
     bool g_first = true;
     // Add the FP32/FP64 adjoint tiles into the wave's slice of the output.
@@ -246,7 +256,8 @@ __global__ __launch_bounds__(256) void loglik_kernel(LoglikArgs a) {
                             const int kk = q * 16 + (F64 ? g + 4 * i : 4 * g + i);
                             if (p < a.P && kk < a.k) {
                                 double* dst = g_out + p * a.d + c * a.k + kk;
-                                *dst = (g_first ? 0.0 : *dst) + (double)gacc[b][c][q][i];
+                                const double gv = (double)gacc[b][c][q][i];
+                                *dst = (g_first ? 0.0 : *dst) + (kNegRes ? -gv : gv);
                             }
                         }
                         gacc[b][c][q] = Acc{0, 0, 0, 0};
@@ -331,6 +342,25 @@ __global__ __launch_bounds__(256) void loglik_kernel(LoglikArgs a) {
             mfma_fwd(cur_c);
             if (has_next) load_a(cur_c, o + 32);  // the MFMAs have read this step's fragments
         }
+        // A operand of the adjoint (rows of the transposed X for this step),
+        // requested before the epilogue so the load latency hides behind it.
+        using XtReg = typename std::conditional<BF, bf16x8, E>::type;
+        XtReg xth[GRAD ? KBT : 1][BF ? 1 : 8];
+        XtReg xtl[GRAD && BF ? KBT : 1];
+        if constexpr (GRAD) {
+#pragma unroll
+            for (int q = 0; q < KBT; ++q) {
+                const int64_t xrow = (int64_t)(q * 16 + r16) * a.Tp + o + 8 * g;
+                if constexpr (BF) {
+                    xth[q][0] = __builtin_bit_cast(bf16x8, *(const u16x8*)((const unsigned short*)a.XT + xrow));
+                    xtl[q] = __builtin_bit_cast(bf16x8, *(const u16x8*)((const unsigned short*)a.XTlo + xrow));
+                } else {
+                    const E* xt = (const E*)a.XT + xrow;
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) xth[q][j] = xt[j];
+                }
+            }
+        }
 
         unsigned ylo = 0, yhi = 0;
         if (NC > 1 && (!SUFF || a.perobs != nullptr)) {
@@ -338,7 +368,7 @@ __global__ __launch_bounds__(256) void loglik_kernel(LoglikArgs a) {
             ylo = yy.x;
             yhi = yy.y;
         }
-        bool bad = false;  // fast multinomial path left its safe range
+        bool bad = false;  // the unshifted fast epilogue left its safe range
         E rres[GRAD ? 2 : 1][GRAD ? 4 : 1][GRAD ? PW : 1][GRAD ? NC : 1];
         E tsum[PW];
 #pragma unroll
@@ -360,7 +390,15 @@ __global__ __launch_bounds__(256) void loglik_kernel(LoglikArgs a) {
     #pragma unroll
                         for (int b = 0; b < PW; ++b) {
                             E lp;
-                            if constexpr (NC == 1) {
+                            if constexpr (NC == 1 && FAST) {
+                                // base 2, unshifted: l2 = -log2(1 + 2^z).  Exact in range while
+                                // 2^z is finite (z < 128); otherwise tsum turns -inf or NaN and
+                                // the step is redone below with the shifted form.
+                                const E z = acc[CS][h][b][0][i];
+                                const float lg = flog2(1.f + fexp2(z));
+                                lp = -lg;
+                                if constexpr (GRAD) rres[h][i][b][0] = ov ? fexp2(z - lg) : 0.f;
+                            } else if constexpr (NC == 1) {
                                 // Binary with sign folding: l = -softplus(z), z = x~' theta.
                                 const E z = acc[CS][h][b][0][i];
                                 if constexpr (F64) {
@@ -373,8 +411,8 @@ __global__ __launch_bounds__(256) void loglik_kernel(LoglikArgs a) {
                                     // max via the signed-integer order of float bits
                                     const float mz = __int_as_float(max(__float_as_int(z), 0));
                                     lp = -(mz + flog2(1.f + fexp2(-fabsf(z))));
-                                    // sigmoid(z) = 2^(z - softplus2(z))
-                                    if constexpr (GRAD) rres[h][i][b][0] = ov ? -fexp2(z + lp) : 0.f;
+                                    // sigmoid(z) = 2^(z - softplus2(z)); the residual is its negative
+                                    if constexpr (GRAD) rres[h][i][b][0] = ov ? fexp2(z + lp) : 0.f;
                                 }
                             } else if constexpr (NOY && FAST) {
                                 // base 2 without a shift: exact while the sum stays below 2^126
@@ -445,13 +483,17 @@ __global__ __launch_bounds__(256) void loglik_kernel(LoglikArgs a) {
         if (a.perobs != nullptr) {
             if (PIPE && has_next) mfma_fwd(nxt_c);
             epilogue(cur_c, bconst<true>{}, bconst<true>{}, bconst<false>{});
-        } else if constexpr (SUFF) {
+        } else if constexpr (FASTOK) {
             if (full && has_next) {
                 if constexpr (PIPE) mfma_fwd(nxt_c);
                 epilogue(cur_c, bconst<false>{}, bconst<false>{}, bconst<true>{});
             } else {
                 if (PIPE && has_next) mfma_fwd(nxt_c);
                 epilogue(cur_c, bconst<true>{}, bconst<false>{}, bconst<true>{});
+            }
+            if constexpr (NC == 1) {
+#pragma unroll
+                for (int b = 0; b < PW; ++b) bad |= !(tsum[b] > -INFINITY);  // -inf or NaN
             }
             if (__any(bad)) {  // wave-uniform: redo this step with the max shift
 #pragma unroll
@@ -473,9 +515,8 @@ __global__ __launch_bounds__(256) void loglik_kernel(LoglikArgs a) {
                 if constexpr (BF) {
     #pragma unroll
                     for (int q = 0; q < KBT; ++q) {
-                        const int64_t xrow = (int64_t)(q * 16 + r16) * a.Tp + o + 8 * g;
-                        const bf16x8 th8 = __builtin_bit_cast(bf16x8, *(const u16x8*)((const unsigned short*)a.XT + xrow));
-                        const bf16x8 tl8 = __builtin_bit_cast(bf16x8, *(const u16x8*)((const unsigned short*)a.XTlo + xrow));
+                        const bf16x8 th8 = xth[q][0];
+                        const bf16x8 tl8 = xtl[q];
     #pragma unroll
                         for (int b = 0; b < PW; ++b)
     #pragma unroll
@@ -495,13 +536,6 @@ __global__ __launch_bounds__(256) void loglik_kernel(LoglikArgs a) {
                             }
                     }
                 } else {
-                    E xv[KBT][8];
-    #pragma unroll
-                    for (int q = 0; q < KBT; ++q) {
-                        const E* xt = (const E*)a.XT + (int64_t)(q * 16 + r16) * a.Tp + o + 8 * g;
-    #pragma unroll
-                        for (int j = 0; j < 8; ++j) xv[q][j] = xt[j];
-                    }
     #pragma unroll
                     for (int j = 0; j < 8; ++j)
     #pragma unroll
@@ -510,7 +544,7 @@ __global__ __launch_bounds__(256) void loglik_kernel(LoglikArgs a) {
                             for (int b = 0; b < PW; ++b)
     #pragma unroll
                                 for (int c = 0; c < NC; ++c)
-                                    gacc[b][c][q] = mfma(xv[q][j], rres[j >> 2][j & 3][b][c], gacc[b][c][q]);
+                                    gacc[b][c][q] = mfma(xth[q][j], rres[j >> 2][j & 3][b][c], gacc[b][c][q]);
                 }
             if (((st - st_begin) % kFoldSteps) == kFoldSteps - 1) fold();
         }
@@ -585,5 +619,6 @@ LoglikEntry loglik_entry() {
 LoglikEntry lookup_fp64(int nc, int ks, int mode);
 LoglikEntry lookup_fp32(int nc, int ks, int mode);
 LoglikEntry lookup_bf16(int nc, int ks, int mode);
+LoglikEntry lookup_bf16_wide(int nc, int ks, int mode);  // C >= 6
 
 }  // namespace sps

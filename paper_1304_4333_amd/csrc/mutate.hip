@@ -11,9 +11,6 @@
 
 namespace sps {
 
-int random_fill(sps_ctx* c, int kind, uint64_t seed, uint64_t stream, int64_t count, int32_t d,
-                void* out);
-
 constexpr unsigned kFlagNotPD = 1u;
 
 // Sample variance in one pass, shifted by the first particle c = theta[0]
@@ -204,6 +201,31 @@ __global__ __launch_bounds__(256) void gemm_abt_kernel(const double* __restrict_
     }
 }
 
+int gemm_abt(sps_ctx* c, const double* A, const double* B, const double* Base, double* Out,
+             int64_t P, int32_t d, double alpha) {
+    if (P <= 0 || d <= 0) return SPS_OK;
+    const dim3 gg((unsigned)((P + 63) / 64), (unsigned)((d + 63) / 64));
+    gemm_abt_kernel<<<gg, 256, 0, c->stream>>>(A, B, Base, Out, P, d, alpha);
+    return launched(c, "gemm_abt_kernel");
+}
+
+// out[p][i] = theta[p][i] - mu[i]
+__global__ void center_kernel(const double* __restrict__ theta, const double* __restrict__ mu,
+                              int64_t P, int32_t d, double* __restrict__ out) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= P * d) return;
+    out[e] = theta[e] - mu[(int32_t)(e % d)];
+}
+
+int prior_whiten(sps_ctx* c, const double* theta, int64_t P, double* tmp, double* R) {
+    const int32_t d = c->d;
+    const int64_t n = P * d;
+    if (n <= 0) return SPS_OK;
+    center_kernel<<<(unsigned)((n + 255) / 256), 256, 0, c->stream>>>(theta, c->prior_mean, P, d, tmp);
+    SPS_CHECK(launched(c, "center_kernel"));
+    return gemm_abt(c, tmp, c->prior_Li, nullptr, R, P, d, 1.0);
+}
+
 // gpi = grad + gradient of the log prior, -(theta - mu) / sd^2.
 __global__ void grad_logpost_kernel(const double* __restrict__ grad, const double* __restrict__ theta,
                                     const double* __restrict__ mu, const double* __restrict__ isd,
@@ -239,6 +261,7 @@ __global__ __launch_bounds__(256) void accept_kernel(
     const double* __restrict__ theta2, const double* __restrict__ ll2,
     const double* __restrict__ grad2, const double* __restrict__ z, const double* __restrict__ v,
     const double* __restrict__ u, const double* __restrict__ mu, const double* __restrict__ isd,
+    const double* __restrict__ w0, const double* __restrict__ w1,
     int64_t P, int32_t d, int mala, const unsigned* flags, unsigned long long* count) {
     __shared__ unsigned nacc[4];
     const int lane = threadIdx.x & 63;
@@ -252,8 +275,9 @@ __global__ __launch_bounds__(256) void accept_kernel(
         const double* b = theta2 + p * d;
         double q0 = 0.0, q1 = 0.0, vv = 0.0, zz = 0.0;
         for (int32_t i = lane; i < d; i += 64) {
-            const double za = (a[i] - mu[i]) * isd[i];
-            const double zb = (b[i] - mu[i]) * isd[i];
+            // whitened distance to the prior mean: given (full prior) or (theta - mu) / sd
+            const double za = w0 ? w0[p * d + i] : (a[i] - mu[i]) * isd[i];
+            const double zb = w0 ? w1[p * d + i] : (b[i] - mu[i]) * isd[i];
             q0 += za * za;
             q1 += zb * zb;
             if (mala) {
@@ -419,11 +443,29 @@ static int mutate_impl(sps_ctx* c, const char* who, double* theta, double* ll, d
     SPS_CHECK(launched(c, "cholesky_kernel"));
 
     const dim3 gg((unsigned)((P + 63) / 64), (unsigned)((d + 63) / 64));
+    // Full prior: whitened particles r = L^-1 (theta - mean) for the prior
+    // terms of log alpha and, for MALA, its gradient -L^-T r.
+    double* wtmp = nullptr;
+    double* R0 = nullptr;
+    double* R1 = nullptr;
+    if (c->prior_full) {
+        SPS_CHECK(ensure(c, c->pw, sizeof(double) * 3 * Pd, "whitened particles"));
+        wtmp = (double*)c->pw.p;
+        R0 = wtmp + Pd;
+        R1 = R0 + Pd;
+        SPS_CHECK(prior_whiten(c, theta, P, wtmp, R0));
+    }
+    auto grad_logpost = [&](const double* gl, const double* th, const double* R, double* out) -> int {
+        if (c->prior_full) return gemm_abt(c, R, c->prior_LiT, gl, out, P, d, -1.0);
+        grad_logpost_kernel<<<nblk(Pd), 256, 0, c->stream>>>(gl, th, c->prior_mean, c->prior_isd, P, d, out);
+        return launched(c, "grad_logpost_kernel");
+    };
     if (!mala) {
         // theta' = theta + L z
         gemm_abt_kernel<<<gg, 256, 0, c->stream>>>(z, L, theta, th2, P, d, 1.0);
         SPS_CHECK(launched(c, "gemm_abt_kernel"));
         SPS_CHECK(loglik_launch(c, th2, P, 0, t, prec, ll2, nullptr));
+        if (c->prior_full) SPS_CHECK(prior_whiten(c, th2, P, wtmp, R1));
     } else {
         double* gpi = (double*)c->pstat.p;
         double* work = gpi + Pd;
@@ -432,16 +474,15 @@ static int mutate_impl(sps_ctx* c, const char* who, double* theta, double* ll, d
         else trinv_kernel<<<1, 1024, 0, c->stream>>>(L, d, W, flags);
         SPS_CHECK(launched(c, "trinv_kernel"));
         // mu(theta) = theta + (1/2) Sigma grad log pi(theta); theta' = mu + L z
-        grad_logpost_kernel<<<nblk(Pd), 256, 0, c->stream>>>(grad, theta, c->prior_mean, c->prior_isd, P, d, gpi);
-        SPS_CHECK(launched(c, "grad_logpost_kernel"));
+        SPS_CHECK(grad_logpost(grad, theta, R0, gpi));
         gemm_abt_kernel<<<gg, 256, 0, c->stream>>>(gpi, Sg, theta, work, P, d, 0.5);
         SPS_CHECK(launched(c, "gemm_abt_kernel"));
         gemm_abt_kernel<<<gg, 256, 0, c->stream>>>(z, L, work, th2, P, d, 1.0);
         SPS_CHECK(launched(c, "gemm_abt_kernel"));
         SPS_CHECK(loglik_launch(c, th2, P, 0, t, prec, ll2, g2));
         // v = L^-1 (theta - mu(theta'))
-        grad_logpost_kernel<<<nblk(Pd), 256, 0, c->stream>>>(g2, th2, c->prior_mean, c->prior_isd, P, d, gpi);
-        SPS_CHECK(launched(c, "grad_logpost_kernel"));
+        if (c->prior_full) SPS_CHECK(prior_whiten(c, th2, P, wtmp, R1));
+        SPS_CHECK(grad_logpost(g2, th2, R1, gpi));
         sub_kernel<<<nblk(Pd), 256, 0, c->stream>>>(theta, th2, work, Pd);
         SPS_CHECK(launched(c, "sub_kernel"));
         gemm_abt_kernel<<<gg, 256, 0, c->stream>>>(gpi, Sg, work, work, P, d, -0.5);
@@ -451,8 +492,8 @@ static int mutate_impl(sps_ctx* c, const char* who, double* theta, double* ll, d
     }
     accept_kernel<<<(unsigned)((P + 4 * kAccPerWave - 1) / (4 * kAccPerWave)), 256, 0, c->stream>>>(
         theta, ll, grad, th2, ll2, mala ? (const double*)c->grad2.p : nullptr, z,
-        mala ? (const double*)c->pstat.p : nullptr, u, c->prior_mean, c->prior_isd, P, d, mala ? 1 : 0,
-        flags, count);
+        mala ? (const double*)c->pstat.p : nullptr, u, c->prior_mean, c->prior_isd, R0, R1, P, d,
+        mala ? 1 : 0, flags, count);
     SPS_CHECK(launched(c, "accept_kernel"));
     SPS_HIP(c, hipMemcpyAsync(c->hostbuf.p, c->small.p, 16, hipMemcpyDeviceToHost, c->stream));
     SPS_HIP(c, hipStreamSynchronize(c->stream));

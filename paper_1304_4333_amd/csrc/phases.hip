@@ -530,6 +530,13 @@ extern "C" int sps_random(sps_ctx* c, int kind, uint64_t seed, uint64_t stream, 
     return random_fill(c, kind, seed, stream, count, d, out);
 }
 
+// theta[p][i] = mean[i]
+__global__ void rows_kernel(double* __restrict__ theta, const double* __restrict__ mean, int64_t P, int32_t d) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= P * d) return;
+    theta[e] = mean[(int32_t)(e % d)];
+}
+
 extern "C" int sps_init_prior(sps_ctx* c, double* theta, int64_t P, uint64_t seed, uint64_t stream) {
     if (!c) return SPS_ERR_ARG;
     c->err.clear();
@@ -537,11 +544,18 @@ extern "C" int sps_init_prior(sps_ctx* c, double* theta, int64_t P, uint64_t see
     if (P < 0 || (!theta && P > 0)) return fail(c, SPS_ERR_ARG, "sps_init_prior: bad arguments");
     const int64_t n = P * c->d;
     if (n == 0) return SPS_OK;
+    if (c->prior_full) {
+        // theta = mean + L z, z the same Philox normals as in the independent case
+        SPS_CHECK(ensure(c, c->z, sizeof(double) * n, "normals"));
+        SPS_CHECK(random_fill(c, 2, seed, stream, P, c->d, c->z.p));
+        rows_kernel<<<(unsigned)((n + 255) / 256), 256, 0, c->stream>>>(theta, c->prior_mean, P, c->d);
+        SPS_CHECK(launched(c, "rows_kernel"));
+        return gemm_abt(c, (const double*)c->z.p, c->prior_L, theta, theta, P, c->d, 1.0);
+    }
     init_prior_kernel<<<(unsigned)((n + 255) / 256), 256, 0, c->stream>>>(
         theta, P, c->d, c->prior_mean, c->prior_isd, seed, stream);
     return launched(c, "init_prior_kernel");
 }
-
 extern "C" int sps_correct(sps_ctx* c, const double* theta, double* ll, int32_t J, int32_t N,
                            int64_t s0, double ess_frac, int prec, double* log_w, int64_t* t_end,
                            double* ess_end) {

@@ -159,10 +159,16 @@ static void free_data(sps_ctx* c) {
 }
 
 static void free_prior(sps_ctx* c) {
-    if (c->prior_mean) (void)hipFree(c->prior_mean);
-    if (c->prior_isd) (void)hipFree(c->prior_isd);
+    double* ps[] = {c->prior_mean, c->prior_isd, c->prior_L, c->prior_Li, c->prior_LiT};
+    for (double* p : ps)
+        if (p) (void)hipFree(p);
     c->prior_mean = nullptr;
     c->prior_isd = nullptr;
+    c->prior_L = nullptr;
+    c->prior_Li = nullptr;
+    c->prior_LiT = nullptr;
+    c->prior_full = false;
+    c->prior_cov_host.clear();
     c->has_prior = false;
 }
 
@@ -372,14 +378,12 @@ extern "C" int sps_set_prior(sps_ctx* c, const double* mean, const double* sd) {
     int d = c->d;
     double* isd = (double*)malloc(sizeof(double) * d);
     if (!isd) return fail(c, SPS_ERR_NOMEM, "sps_set_prior: host allocation");
-    double cst = 0.0;
     for (int i = 0; i < d; ++i) {
         if (!(sd[i] > 0.0) || !std::isfinite(sd[i]) || !std::isfinite(mean[i])) {
             free(isd);
             return fail(c, SPS_ERR_ARG, "sps_set_prior: sd[%d] must be positive and finite", i);
         }
         isd[i] = 1.0 / sd[i];
-        cst -= std::log(sd[i]) + 0.5 * std::log(2.0 * M_PI);
     }
     SPS_HIP(c, hipSetDevice(c->device));
     SPS_HIP(c, hipStreamSynchronize(c->stream));
@@ -396,7 +400,166 @@ extern "C" int sps_set_prior(sps_ctx* c, const double* mean, const double* sd) {
     free(isd);
     if (e3 != hipSuccess) return hip_fail(c, e3, "sps_set_prior: copy");
     if (e4 != hipSuccess) return hip_fail(c, e4, "sps_set_prior: copy");
-    c->prior_const = cst;
+    c->prior_cov_host.assign((size_t)d * d, 0.0);
+    for (int i = 0; i < d; ++i) c->prior_cov_host[(size_t)i * d + i] = sd[i] * sd[i];
     c->has_prior = true;
+    return SPS_OK;
+}
+
+// ---- full prior covariance ------------------------------------------------
+
+// Lower Cholesky factor of the symmetric n x n matrix A (row-major, lower
+// triangle read).  False when A is not numerically positive definite.
+static bool host_cholesky(const double* A, int n, double* L) {
+    for (int i = 0; i < n * n; ++i) L[i] = 0.0;
+    for (int j = 0; j < n; ++j) {
+        double s = A[j * n + j];
+        for (int q = 0; q < j; ++q) s -= L[j * n + q] * L[j * n + q];
+        if (!(s > 0.0) || !std::isfinite(s)) return false;
+        const double ljj = std::sqrt(s);
+        L[j * n + j] = ljj;
+        for (int i = j + 1; i < n; ++i) {
+            double t = A[i * n + j];
+            for (int q = 0; q < j; ++q) t -= L[i * n + q] * L[j * n + q];
+            L[i * n + j] = t / ljj;
+        }
+    }
+    return true;
+}
+
+// Inverse of a lower-triangular n x n matrix (column by column forward substitution).
+static void host_trinv(const double* L, int n, double* Li) {
+    for (int i = 0; i < n * n; ++i) Li[i] = 0.0;
+    for (int col = 0; col < n; ++col)
+        for (int i = col; i < n; ++i) {
+            double s = (i == col) ? 1.0 : 0.0;
+            for (int q = col; q < i; ++q) s -= L[i * n + q] * Li[q * n + col];
+            Li[i * n + col] = s / L[i * n + i];
+        }
+}
+
+// Install N(mean, cov) on the free parameters (mean null: zero).
+static int set_prior_full(sps_ctx* c, const double* mean, const std::vector<double>& cov, const char* who) {
+    const int d = c->d;
+    const size_t dd = (size_t)d * d;
+    std::vector<double> L(dd), Li(dd), LiT(dd), mu(d, 0.0);
+    if (mean)
+        for (int i = 0; i < d; ++i) {
+            if (!std::isfinite(mean[i])) return fail(c, SPS_ERR_ARG, "%s: mean[%d] is not finite", who, i);
+            mu[i] = mean[i];
+        }
+    if (!host_cholesky(cov.data(), d, L.data()))
+        return fail(c, SPS_ERR_NOT_PD, "%s: the prior covariance is not positive definite", who);
+    host_trinv(L.data(), d, Li.data());
+    for (int i = 0; i < d; ++i)
+        for (int j = 0; j < d; ++j) LiT[(size_t)j * d + i] = Li[(size_t)i * d + j];
+    SPS_HIP(c, hipSetDevice(c->device));
+    SPS_HIP(c, hipStreamSynchronize(c->stream));
+    free_prior(c);
+    double** dst[] = {&c->prior_mean, &c->prior_L, &c->prior_Li, &c->prior_LiT};
+    const double* src[] = {mu.data(), L.data(), Li.data(), LiT.data()};
+    const size_t n[] = {(size_t)d, dd, dd, dd};
+    for (int q = 0; q < 4; ++q) {
+        if (hipMalloc((void**)dst[q], sizeof(double) * n[q]) != hipSuccess) {
+            free_prior(c);
+            return fail(c, SPS_ERR_NOMEM, "%s: device allocation", who);
+        }
+        hipError_t e = hipMemcpy(*dst[q], src[q], sizeof(double) * n[q], hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            free_prior(c);
+            return hip_fail(c, e, who);
+        }
+    }
+    c->prior_cov_host = cov;
+    c->prior_full = true;
+    c->has_prior = true;
+    return SPS_OK;
+}
+
+extern "C" int sps_set_prior_cov(sps_ctx* c, const double* mean, const double* cov) {
+    if (!c) return SPS_ERR_ARG;
+    c->err.clear();
+    if (!c->has_data) return fail(c, SPS_ERR_STATE, "sps_set_prior_cov: call sps_set_data first");
+    if (!cov) return fail(c, SPS_ERR_ARG, "sps_set_prior_cov: null covariance");
+    const int d = c->d;
+    std::vector<double> S(cov, cov + (size_t)d * d);
+    for (int i = 0; i < d; ++i)
+        for (int j = 0; j < i; ++j) {
+            const double a = S[(size_t)i * d + j], b = S[(size_t)j * d + i];
+            if (!std::isfinite(a) || !std::isfinite(b) ||
+                std::fabs(a - b) > 1e-12 * std::max(1.0, std::max(std::fabs(a), std::fabs(b))))
+                return fail(c, SPS_ERR_ARG, "sps_set_prior_cov: covariance not symmetric at (%d, %d)", i, j);
+        }
+    return set_prior_full(c, mean, S, "sps_set_prior_cov");
+}
+
+// X'X over all observations, one workgroup per entry (a <= b), fixed order.
+// The sign folding of binary rows cancels in the products.
+__global__ __launch_bounds__(256) void xtx_kernel(const double* __restrict__ XT, int64_t Tp, int64_t T,
+                                                   int32_t k, double* __restrict__ out) {
+    __shared__ double red[256];
+    int32_t e = blockIdx.x, a = 0;
+    while (e >= k - a) {  // blockIdx -> (a, b), b >= a
+        e -= k - a;
+        ++a;
+    }
+    const int32_t b = a + e;
+    const double* xa = XT + (int64_t)a * Tp;
+    const double* xb = XT + (int64_t)b * Tp;
+    double s = 0.0;
+    for (int64_t t = threadIdx.x; t < T; t += 256) s += xa[t] * xb[t];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[(int64_t)a * k + b] = red[0];
+        out[(int64_t)b * k + a] = red[0];
+    }
+}
+
+extern "C" int sps_set_prior_g(sps_ctx* c, double g, const double* mean) {
+    if (!c) return SPS_ERR_ARG;
+    c->err.clear();
+    if (!c->has_data) return fail(c, SPS_ERR_STATE, "sps_set_prior_g: call sps_set_data first");
+    if (!(g > 0.0) || !std::isfinite(g)) return fail(c, SPS_ERR_ARG, "sps_set_prior_g: g must be positive");
+    const int k = c->k, d = c->d, m = c->C - 1;
+    SPS_HIP(c, hipSetDevice(c->device));
+    SPS_CHECK(ensure(c, c->small, std::max<size_t>(4096, sizeof(double) * (size_t)k * k), "small"));
+    const unsigned nblk = (unsigned)((int64_t)k * (k + 1) / 2);
+    xtx_kernel<<<nblk, 256, 0, c->stream>>>(c->XTd, c->Tp, c->T, k, (double*)c->small.p);
+    SPS_CHECK(launched(c, "xtx_kernel"));
+    std::vector<double> XtX((size_t)k * k), Ls((size_t)k * k), Lsi((size_t)k * k);
+    SPS_HIP(c, hipMemcpyAsync(XtX.data(), c->small.p, sizeof(double) * k * k, hipMemcpyDeviceToHost, c->stream));
+    SPS_HIP(c, hipStreamSynchronize(c->stream));
+    if (!host_cholesky(XtX.data(), k, Ls.data()))
+        return fail(c, SPS_ERR_NOT_PD, "sps_set_prior_g: X'X is singular");
+    // Sigma = g T (X'X)^-1 = g T Ls^-T Ls^-1
+    host_trinv(Ls.data(), k, Lsi.data());
+    std::vector<double> Sig((size_t)k * k);
+    for (int i = 0; i < k; ++i)
+        for (int j = 0; j < k; ++j) {
+            double s = 0.0;
+            for (int q = std::max(i, j); q < k; ++q) s += Lsi[(size_t)q * k + i] * Lsi[(size_t)q * k + j];
+            Sig[(size_t)i * k + j] = g * (double)c->T * s;
+        }
+    // normalised on outcome 0: block (ci, cj) = (1 + [ci == cj]) Sigma
+    std::vector<double> S((size_t)d * d);
+    for (int ci = 0; ci < m; ++ci)
+        for (int cj = 0; cj < m; ++cj)
+            for (int a = 0; a < k; ++a)
+                for (int b = 0; b < k; ++b)
+                    S[((size_t)ci * k + a) * d + (size_t)cj * k + b] = (ci == cj ? 2.0 : 1.0) * Sig[(size_t)a * k + b];
+    return set_prior_full(c, mean, S, "sps_set_prior_g");
+}
+
+extern "C" int sps_get_prior_cov(sps_ctx* c, double* cov) {
+    if (!c) return SPS_ERR_ARG;
+    c->err.clear();
+    if (!c->has_prior) return fail(c, SPS_ERR_STATE, "sps_get_prior_cov: no prior set");
+    if (!cov) return fail(c, SPS_ERR_ARG, "sps_get_prior_cov: null output");
+    std::copy(c->prior_cov_host.begin(), c->prior_cov_host.end(), cov);
     return SPS_OK;
 }

@@ -56,8 +56,13 @@ struct sps_ctx {
     int8_t* y8 = nullptr;      // Tp outcomes as bytes (padding 0)
     double* xbar = nullptr;    // k column means of X
     double* prior_mean = nullptr;  // d
-    double* prior_isd = nullptr;   // d  1 / sd
-    double prior_const = 0.0;      // -sum_i (log sd_i + log(2 pi)/2)
+    double* prior_isd = nullptr;   // d  1 / sd (independent components only)
+    // Full prior covariance S = L L' (sps_set_prior_cov, sps_set_prior_g).
+    bool prior_full = false;
+    double* prior_L = nullptr;     // d x d lower Cholesky factor of S
+    double* prior_Li = nullptr;    // d x d, L^-1 (lower)
+    double* prior_LiT = nullptr;   // d x d, (L^-1)'
+    std::vector<double> prior_cov_host;  // the prior covariance as set, d x d (either kind)
 
     // ---- scratch (grow-only; allocated on first use at a given size) ----
     sps::Buf part_ll;    // obs-split partial log-likelihoods
@@ -77,6 +82,7 @@ struct sps_ctx {
     sps::Buf W;          // resampling integer weights
     sps::Buf gstat;      // moments partials
     sps::Buf suff;       // multinomial sufficient statistics for one observation range
+    sps::Buf pw;         // full prior: centred and whitened particles (3 P d)
     bool suff_valid = false;
     int64_t suff_t0 = 0, suff_t1 = 0;
 
@@ -132,5 +138,14 @@ int timing_end(sps_ctx* c, int slot);
 void timing_release(sps_ctx* c);
 // p[0..n) = v on the context stream (a kernel, safe under graph capture).
 int fill(sps_ctx* c, double* p, int64_t n, double v);
+// Philox draws into out (kind 0: 53-bit integers, 1: uniforms, 2: normals).
+int random_fill(sps_ctx* c, int kind, uint64_t seed, uint64_t stream, int64_t count, int32_t d,
+                void* out);
+// Out = Base + alpha A B' with A (P x d), B (d x d), all row-major FP64;
+// Base may be null or alias Out.
+int gemm_abt(sps_ctx* c, const double* A, const double* B, const double* Base, double* Out,
+             int64_t P, int32_t d, double alpha);
+// Full prior: R = rows L^-1 (theta_p - mean); tmp (P x d) is scratch.
+int prior_whiten(sps_ctx* c, const double* theta, int64_t P, double* tmp, double* R);
 
 }  // namespace sps

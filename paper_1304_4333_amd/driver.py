@@ -205,11 +205,20 @@ def run_two_pass(ctx: sps.Context, cfg: SpsConfig) -> tuple:
 
 
 def setup(X: np.ndarray, y: np.ndarray, C: int, prior_mean=0.0, prior_sd=1.0,
-          device: int = 0, stream: Optional[torch.cuda.Stream] = None) -> sps.Context:
-    """A context with the data set and the iid N(prior_mean, prior_sd^2) prior."""
+          device: int = 0, stream: Optional[torch.cuda.Stream] = None,
+          prior_cov: Optional[np.ndarray] = None, g: Optional[float] = None) -> sps.Context:
+    """A context with the data set and its prior: the iid
+    N(prior_mean, prior_sd^2) prior by default, N(prior_mean, prior_cov) when
+    prior_cov is given, or the normalised g-prior (eqs. (g-prior_def),
+    (prior_norm)) when g is given."""
     ctx = sps.Context(device, stream)
     Xg = torch.from_numpy(np.ascontiguousarray(X, dtype=np.float64)).to(ctx.device)
     yg = torch.from_numpy(np.ascontiguousarray(y, dtype=np.int32)).to(ctx.device)
     sps.sps_set_data(ctx, Xg, yg, C)
-    sps.sps_set_prior(ctx, prior_mean, prior_sd)
+    if g is not None:
+        sps.sps_set_prior_g(ctx, g, prior_mean)
+    elif prior_cov is not None:
+        sps.sps_set_prior_cov(ctx, prior_mean, prior_cov)
+    else:
+        sps.sps_set_prior(ctx, prior_mean, prior_sd)
     return ctx

@@ -42,6 +42,9 @@ _SIGS = {
     "sps_set_stream": [_vp, _vp],
     "sps_set_data": [_vp, _vp, _vp, _i64, _i32, _i32],
     "sps_set_prior": [_vp, _vp, _vp],
+    "sps_set_prior_cov": [_vp, _vp, _vp],
+    "sps_set_prior_g": [_vp, _dbl, _vp],
+    "sps_get_prior_cov": [_vp, _vp],
     "sps_random": [_vp, ct.c_int, _u64, _u64, _i64, _i32, _vp],
     "sps_init_prior": [_vp, _vp, _i64, _u64, _u64],
     "sps_loglik": [_vp, _vp, _i64, _i64, _i64, ct.c_int, _vp],
@@ -157,6 +160,32 @@ def sps_set_prior(ctx: Context, mean, sd):
     m = np.ascontiguousarray(np.broadcast_to(np.asarray(mean, dtype=np.float64), (ctx.d,)))
     s = np.ascontiguousarray(np.broadcast_to(np.asarray(sd, dtype=np.float64), (ctx.d,)))
     ctx.check(lib().sps_set_prior(ctx.handle, m.ctypes.data_as(_vp), s.ctypes.data_as(_vp)))
+
+
+def sps_set_prior_cov(ctx: Context, mean, cov):
+    """Full-covariance Gaussian prior N(mean, cov) on the free parameters."""
+    import numpy as np
+    m = np.ascontiguousarray(np.broadcast_to(np.asarray(mean, dtype=np.float64), (ctx.d,)))
+    S = np.ascontiguousarray(np.asarray(cov, dtype=np.float64))
+    if S.shape != (ctx.d, ctx.d):
+        raise ValueError(f"cov must be {ctx.d} x {ctx.d}")
+    ctx.check(lib().sps_set_prior_cov(ctx.handle, m.ctypes.data_as(_vp), S.ctypes.data_as(_vp)))
+
+
+def sps_set_prior_g(ctx: Context, g: float, mean=None):
+    """The normalised g-prior (covariance built from the data on the device)."""
+    import numpy as np
+    m = None
+    if mean is not None:
+        m = np.ascontiguousarray(np.broadcast_to(np.asarray(mean, dtype=np.float64), (ctx.d,)))
+    ctx.check(lib().sps_set_prior_g(ctx.handle, float(g), None if m is None else m.ctypes.data_as(_vp)))
+
+
+def sps_get_prior_cov(ctx: Context):
+    import numpy as np
+    out = np.zeros((ctx.d, ctx.d))
+    ctx.check(lib().sps_get_prior_cov(ctx.handle, out.ctypes.data_as(_vp)))
+    return out
 
 
 def sps_random(ctx: Context, kind: int, seed: int, stream: int, count: int, d: int = 1,
