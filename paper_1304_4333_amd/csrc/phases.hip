@@ -84,11 +84,13 @@ __global__ void correct_chunk_sum_kernel(const double* __restrict__ lw, int64_t 
 }
 
 // Pass 2 of the scan fused with the ESS statistics.  Thread (p, chunk)
-// turns its per-observation terms into running log-weights (written back in
-// place); for every observation u of the chunk each block reduces, over its
-// 256 particles, m = max lw, s1 = sum exp(lw - m), s2 = sum exp(2 (lw - m))
-// into part[(u * npb + block) * 3 + {0, 1, 2}].  flags |= 1 on NaN or +inf.
-__global__ __launch_bounds__(256) void correct_scan_ess_kernel(double* __restrict__ lw,
+// forms the running log-weights of its chunk from the carried value and the
+// chunk totals (nothing is written back: correct_column_kernel rebuilds the
+// one column that is needed, in the same order); for every observation u of
+// the chunk each block reduces, over its 256 particles, m = max lw,
+// s1 = sum exp(lw - m), s2 = sum exp(2 (lw - m)) into
+// part[(u * npb + block) * 3 + {0, 1, 2}].  flags |= 1 on NaN or +inf.
+__global__ __launch_bounds__(256) void correct_scan_ess_kernel(const double* __restrict__ lw,
                                                                const double* __restrict__ carry,
                                                                const double* __restrict__ tot, int64_t P,
                                                                int32_t nb, double* __restrict__ part,
@@ -111,7 +113,6 @@ __global__ __launch_bounds__(256) void correct_scan_ess_kernel(double* __restric
         double v = -INFINITY;
         if (pv) {
             acc += lw[(int64_t)u * P + p];
-            lw[(int64_t)u * P + p] = acc;
             v = acc;
             bad |= isnan(acc) || acc == INFINITY;
         }
@@ -153,61 +154,87 @@ __global__ __launch_bounds__(256) void correct_scan_ess_kernel(double* __restric
     }
 }
 
-// ESS(u) = S1^2 / S2 from the per-block partials, combined in block order.
-__global__ void correct_ess_combine_kernel(const double* __restrict__ part, int32_t npb, int32_t nb,
-                                           double* __restrict__ ess) {
-    const int32_t u = blockIdx.x * blockDim.x + threadIdx.x;
+// ESS(u) = S1^2 / S2 from the per-block partials.  One wave per
+// observation: lane l merges blocks l, l + 64, ... in order, then the lanes
+// merge in a fixed butterfly (the same result on every run).
+__device__ __forceinline__ void merge_ms(double& m, double& s1, double& s2, double m2, double t1, double t2) {
+    const double M = fmax(m, m2);
+    if (M == -INFINITY) return;
+    const double fa = m > -INFINITY ? exp(m - M) : 0.0;
+    const double fb = m2 > -INFINITY ? exp(m2 - M) : 0.0;
+    s1 = s1 * fa + t1 * fb;
+    s2 = s2 * fa * fa + t2 * fb * fb;
+    m = M;
+}
+
+__global__ __launch_bounds__(256) void correct_ess_combine_kernel(const double* __restrict__ part, int32_t npb,
+                                                                  int32_t nb, double* __restrict__ ess) {
+    const int32_t u = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
     if (u >= nb) return;
     const double* q = part + (int64_t)u * npb * 3;
-    double M = -INFINITY;
-    for (int32_t b = 0; b < npb; ++b) M = fmax(M, q[3 * b]);
-    double S1 = 0.0, S2 = 0.0;
-    if (M > -INFINITY) {
-        for (int32_t b = 0; b < npb; ++b) {
-            if (q[3 * b] > -INFINITY) {
-                const double f = exp(q[3 * b] - M);
-                S1 += q[3 * b + 1] * f;
-                S2 += q[3 * b + 2] * f * f;
-            }
+    double m = -INFINITY, s1 = 0.0, s2 = 0.0;
+    for (int32_t b = lane; b < npb; b += 64) merge_ms(m, s1, s2, q[3 * b], q[3 * b + 1], q[3 * b + 2]);
+#pragma unroll
+    for (int sh = 1; sh < 64; sh <<= 1) {
+        const double m2 = __shfl_xor(m, sh, 64);
+        const double t1 = __shfl_xor(s1, sh, 64);
+        const double t2 = __shfl_xor(s2, sh, 64);
+        // merge in lane order so both partners compute the same value
+        if (lane & sh) {
+            double mm = m2, a1 = t1, a2 = t2;
+            merge_ms(mm, a1, a2, m, s1, s2);
+            m = mm; s1 = a1; s2 = a2;
+        } else {
+            merge_ms(m, s1, s2, m2, t1, t2);
         }
     }
-    ess[u] = (M > -INFINITY) ? S1 * S1 / S2 : 0.0;
+    if (lane == 0) ess[u] = (m > -INFINITY) ? s1 * s1 / s2 : 0.0;
 }
 
 // First u in [0, nb) with ESS(u) < thr, or the last observation of the data.
-// out[0] = index (-1 if none), out[1] = ESS there.
-__global__ void correct_find_kernel(const double* __restrict__ ess, int32_t nb, double thr,
-                                    int64_t s, int64_t T, double* out) {
-    if (threadIdx.x != 0) return;
-    double idx = -1.0, val = 0.0;
-    for (int32_t u = 0; u < nb; ++u) {
+// out[0] = index (-1 if none), out[1] = ESS there.  One block of 256.
+__global__ __launch_bounds__(256) void correct_find_kernel(const double* __restrict__ ess, int32_t nb, double thr,
+                                                           int64_t s, int64_t T, double* out) {
+    __shared__ int32_t red[256];
+    int32_t first = INT32_MAX;
+    for (int32_t u = threadIdx.x; u < nb; u += 256)
         if (ess[u] < thr || s + u + 1 == T) {
-            idx = (double)u;
-            val = ess[u];
+            first = u;
             break;
         }
+    red[threadIdx.x] = first;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] = min(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
     }
-    out[0] = idx;
-    out[1] = val;
+    if (threadIdx.x == 0) {
+        const int32_t f = red[0];
+        out[0] = f == INT32_MAX ? -1.0 : (double)f;
+        out[1] = f == INT32_MAX ? 0.0 : ess[f];
+    }
 }
 
-__global__ void correct_final_kernel(const double* __restrict__ lwcol, double* __restrict__ log_w,
-                                     double* __restrict__ ll, int64_t P) {
+// Running log-weight of observation u of the block for every particle, in the
+// order of correct_scan_ess_kernel: carry + chunk totals before u's chunk +
+// the terms of u's chunk up to u.  Writes log_w (and adds it to ll if add_ll).
+__global__ void correct_column_kernel(const double* __restrict__ lw, const double* __restrict__ tot,
+                                      int64_t P, int32_t u, double* __restrict__ log_w,
+                                      double* __restrict__ ll, int add_ll) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= P) return;
-    const double v = lwcol[p];
-    log_w[p] = v;
-    ll[p] += v;
+    const int32_t ch = u / kScanChunk;
+    double acc = log_w[p];
+    for (int32_t q = 0; q < ch; ++q) acc += tot[(int64_t)q * P + p];
+    for (int32_t v = ch * kScanChunk; v <= u; ++v) acc += lw[(int64_t)v * P + p];
+    log_w[p] = acc;
+    if (add_ll) ll[p] += acc;
 }
 
 __global__ void add_kernel(double* __restrict__ a, const double* __restrict__ b, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) a[i] += b[i];
-}
-
-__global__ void copy_kernel(const double* __restrict__ src, double* __restrict__ dst, int64_t n) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) dst[i] = src[i];
 }
 
 // ------------------------------------------------------------------ logML
@@ -600,9 +627,9 @@ extern "C" int sps_correct(sps_ctx* c, const double* theta, double* ll, int32_t 
         SPS_CHECK(launched(c, "correct_chunk_sum_kernel"));
         correct_scan_ess_kernel<<<dim3(pg, nch), 256, 0, c->stream>>>(lwblk, log_w, tot, P, nb, epart, flags);
         SPS_CHECK(launched(c, "correct_scan_ess_kernel"));
-        correct_ess_combine_kernel<<<(unsigned)((nb + 255) / 256), 256, 0, c->stream>>>(epart, (int32_t)npb, nb, ess);
+        correct_ess_combine_kernel<<<(unsigned)((nb + 3) / 4), 256, 0, c->stream>>>(epart, (int32_t)npb, nb, ess);
         SPS_CHECK(launched(c, "correct_ess_combine_kernel"));
-        correct_find_kernel<<<1, 64, 0, c->stream>>>(ess, nb, thr, s, c->T, res);
+        correct_find_kernel<<<1, 256, 0, c->stream>>>(ess, nb, thr, s, c->T, res);
         SPS_CHECK(launched(c, "correct_find_kernel"));
         SPS_HIP(c, hipMemcpyAsync(c->hostbuf.p, c->small.p, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
         SPS_HIP(c, hipStreamSynchronize(c->stream));
@@ -612,14 +639,14 @@ extern "C" int sps_correct(sps_ctx* c, const double* theta, double* ll, int32_t 
                         (long long)(s + nb));
         const int64_t idx = (int64_t)h[2];
         if (idx >= 0) {
-            correct_final_kernel<<<pg, 256, 0, c->stream>>>(lwblk + idx * P, log_w, ll, P);
-            SPS_CHECK(launched(c, "correct_final_kernel"));
+            correct_column_kernel<<<pg, 256, 0, c->stream>>>(lwblk, tot, P, (int32_t)idx, log_w, ll, 1);
+            SPS_CHECK(launched(c, "correct_column_kernel"));
             *t_end = s + idx + 1;
             if (ess_end) *ess_end = h[3];
             return SPS_OK;
         }
-        copy_kernel<<<pg, 256, 0, c->stream>>>(lwblk + (int64_t)(nb - 1) * P, log_w, P);
-        SPS_CHECK(launched(c, "copy_kernel"));
+        correct_column_kernel<<<pg, 256, 0, c->stream>>>(lwblk, tot, P, nb - 1, log_w, ll, 0);
+        SPS_CHECK(launched(c, "correct_column_kernel"));
         s += nb;
         B = std::min(2 * B, kMaxBlock);
     }
