@@ -136,10 +136,41 @@ def sps_fixed_nse(w, seeds):
     sa = np.sqrt(np.mean([r["nse"] ** 2 for r in out["A"]], axis=0) / len(seeds))
     sb = np.sqrt(np.mean([r["nse"] ** 2 for r in out["B"]], axis=0) / len(seeds))
     z = np.abs(za - zb) / np.sqrt(sa ** 2 + sb ** 2)
+    # mixing gain per likelihood call: (M steps of RW / M steps of MALA) over
+    # the cost of a gradient call relative to a plain call, both at full data
+    # in the precision of run B
+    t_ll, t_gr = _call_times(ctx, w, fast)
+    steps_ratio = float(np.mean([r["m_iters"] for r in out["A"]]) / np.mean([r["m_iters"] for r in out["B"]]))
     return {"A": dict(summary(out["A"]), precision="fp64", kernel="rw"),
             "B": dict(summary(out["B"]), precision=fast, kernel="mala"),
             "efficiency_ratio_A_over_B": round(float(np.mean(ratios)), 3),
-            "max_mean_z_A_vs_B": round(float(z.max()), 2), "seeds": list(seeds)}
+            "max_mean_z_A_vs_B": round(float(z.max()), 2), "seeds": list(seeds),
+            "m_steps_ratio_rw_over_mala": round(steps_ratio, 3),
+            "grad_over_loglik_time": round(t_gr / t_ll, 3),
+            "mixing_gain_per_call": round(steps_ratio / (t_gr / t_ll), 3)}
+
+
+def _call_times(ctx, w, precision, reps=5):
+    """Mean seconds of one full-data sps_loglik and sps_loglik_grad call."""
+    import torch
+    from paper_1304_4333_amd import sps, synth
+    _, _, B = synth.make_data(w)
+    th = torch.from_numpy(synth.make_particles(w.P, w.d, scale=0.02, seed=3, center=B.reshape(-1))).cuda()
+    ll = torch.empty(w.P, dtype=torch.float64, device="cuda")
+    g = torch.empty(w.P, w.d, dtype=torch.float64, device="cuda")
+    prec = sps.PREC[precision]
+    out = []
+    for grad in (False, True):
+        call = (lambda: sps.sps_loglik_grad(ctx, th, 0, w.T, prec, ll, g)) if grad else \
+            (lambda: sps.sps_loglik(ctx, th, 0, w.T, prec, ll))
+        call()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            call()
+        torch.cuda.synchronize()
+        out.append((time.perf_counter() - t0) / reps)
+    return out[0], out[1]
 
 
 PREC_SOURCES = {"fp64": ("loglik_fp64.hip",), "fp32": ("loglik_fp32.hip",),

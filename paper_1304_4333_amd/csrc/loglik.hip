@@ -25,18 +25,22 @@ __global__ void loglik_reduce_kernel(const double* __restrict__ part_ll,
 
 // Sufficient statistics of the multinomial likelihood over rows [t0, t1):
 // S[(c - 1) k + i] = sum_{t0 <= t < t1, y_t = c} x_{t,i}, c = 1..C-1 (same
-// layout as theta).  One block per covariate, reading the transposed FP64
-// copy; fixed-order reduction.
-__global__ void suffstat_kernel(const double* __restrict__ XT, const int8_t* __restrict__ y8,
+// layout as theta), with x as the likelihood kernel of precision prec sees it
+// (the FP32 copy, or hi + lo of the BF16 pair), so that the eta_{y_t} term
+// carries the same rounding as the normaliser the kernel computes.  One block
+// per covariate, reading the transposed copy; fixed-order reduction.
+__global__ void suffstat_kernel(const float* __restrict__ XTf, const uint16_t* __restrict__ XTh,
+                                const uint16_t* __restrict__ XTl, int prec, const int8_t* __restrict__ y8,
                                 int64_t Tp, int64_t t0, int64_t t1, int32_t k, int32_t C,
                                 double* __restrict__ S) {
     __shared__ double red[8][256];
     const int32_t i = blockIdx.x;
     double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    const double* row = XT + (int64_t)i * Tp;
+    const int64_t row = (int64_t)i * Tp;
     for (int64_t t = t0 + threadIdx.x; t < t1; t += 256) {
         const int yt = y8[t];
-        const double x = row[t];
+        const double x = prec == SPS_FP32 ? (double)XTf[row + t]
+                                          : (double)from_bf16(XTh[row + t]) + (double)from_bf16(XTl[row + t]);
 #pragma unroll
         for (int c = 1; c < 8; ++c) acc[c] += (yt == c) ? x : 0.0;
     }
@@ -51,22 +55,33 @@ __global__ void suffstat_kernel(const double* __restrict__ XT, const int8_t* __r
         for (int c = 1; c < C; ++c) S[(int64_t)(c - 1) * k + i] = red[c][0];
 }
 
-// ll[p] += theta_p . S (the sum of eta_{y_t}); grad[p] += S.  Wave per particle.
+// ll[p] += ln 2 * theta~_p . S, the sum of eta_{y_t} with theta rounded exactly
+// as the kernel's B operand (log2(e) theta in FP32, or its BF16 hi + lo);
+// grad[p] += S.  Wave per particle.
 __global__ __launch_bounds__(256) void suffstat_apply_kernel(const double* __restrict__ theta,
                                                              const double* __restrict__ S, int64_t P,
-                                                             int32_t d, double* __restrict__ ll,
+                                                             int32_t d, int prec, double* __restrict__ ll,
                                                              double* __restrict__ grad) {
     const int lane = threadIdx.x & 63;
     const int64_t p = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (p >= P) return;
     double v = 0.0;
     for (int32_t e = lane; e < d; e += 64) {
-        v += theta[p * d + e] * S[e];
+        const double vd = theta[p * d + e] * kLog2e;
+        double t2;
+        if (prec == SPS_FP32) {
+            t2 = (double)(float)vd;
+        } else {
+            const unsigned short h = to_bf16((float)vd);
+            const unsigned short l = to_bf16((float)(vd - (double)from_bf16(h)));
+            t2 = (double)from_bf16(h) + (double)from_bf16(l);
+        }
+        v += t2 * S[e];
         if (grad) grad[p * d + e] += S[e];
     }
 #pragma unroll
     for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m, 64);
-    if (lane == 0) ll[p] += v;
+    if (lane == 0) ll[p] += v * kLn2;
 }
 
 __global__ void fill_kernel(double* __restrict__ p, int64_t n, double v) {
@@ -161,16 +176,17 @@ static int run_loglik(sps_ctx* c, const double* theta, int64_t P, int64_t t0, in
     if (ll && c->C > 2 && prec != SPS_FP64) {
         // the eta_{y_t} / 1{y_t = c} terms the kernel leaves out
         SPS_CHECK(ensure(c, c->suff, sizeof(double) * c->d, "sufficient statistics"));
-        if (!(c->suff_valid && c->suff_t0 == t0 && c->suff_t1 == t1)) {
-            suffstat_kernel<<<c->k, 256, 0, c->stream>>>(c->XTd, c->y8, c->Tp, t0, t1, c->k, c->C,
-                                                          (double*)c->suff.p);
+        if (!(c->suff_valid && c->suff_t0 == t0 && c->suff_t1 == t1 && c->suff_prec == prec)) {
+            suffstat_kernel<<<c->k, 256, 0, c->stream>>>(c->XTf, c->XTh, c->XTl, prec, c->y8, c->Tp, t0, t1,
+                                                          c->k, c->C, (double*)c->suff.p);
             SPS_CHECK(launched(c, "suffstat_kernel"));
             c->suff_valid = true;
             c->suff_t0 = t0;
             c->suff_t1 = t1;
+            c->suff_prec = prec;
         }
         suffstat_apply_kernel<<<(unsigned)((P + 3) / 4), 256, 0, c->stream>>>(theta, (const double*)c->suff.p,
-                                                                              P, c->d, ll, grad);
+                                                                              P, c->d, prec, ll, grad);
         SPS_CHECK(launched(c, "suffstat_apply_kernel"));
     }
     return SPS_OK;

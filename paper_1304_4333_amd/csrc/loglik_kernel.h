@@ -166,7 +166,10 @@ __global__ __launch_bounds__(256) void loglik_kernel(LoglikArgs a) {
     // linear in theta (sum_t eta_{y_t} = sum_c theta_c' S_c, S_c the sum of
     // the x_t with y_t = c over the range), and so is the 1{y_t = c} term of
     // the adjoint; both are added outside this kernel, which then evaluates
-    // only -log sum_c exp(eta_c) and -pi_c (no outcome needed).
+    // only -log sum_c exp(eta_c) and -pi_c (no outcome needed).  The outside
+    // term uses x and theta rounded exactly as here, so the rounding errors of
+    // the two parts cancel as they would in eta_y - LSE (otherwise the error
+    // would grow with sum_t pi_t x_t, i.e. with T, instead of with the gradient).
     constexpr bool SUFF = (NC > 1) && !F64;
     // Steps take an unshifted fast form of the epilogue first and are redone
     // with the max-shifted form when a lane leaves its safe range (see body).

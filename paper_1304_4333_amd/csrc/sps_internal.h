@@ -85,6 +85,7 @@ struct sps_ctx {
     sps::Buf pw;         // full prior: centred and whitened particles (3 P d)
     bool suff_valid = false;
     int64_t suff_t0 = 0, suff_t1 = 0;
+    int suff_prec = -1;
 
     // ---- optional kernel timing (sps_timing_enable) ----
     struct Timed {

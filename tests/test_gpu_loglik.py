@@ -145,6 +145,7 @@ def test_loglik_full_size_sampled(orc, name, prec):
     idx = synth.rng(12).choice(w.P, size=nsamp, replace=False)
     idx = np.concatenate([idx, [0, w.P - 1]])
     ref_ll, ref_g = orc.loglik(X, y, w.C, th[idx], 0, w.T, grad=True)
+    print(f"  max abs error {np.abs(ll[idx] - ref_ll).max():.3g} nats at |LL| ~ {np.abs(ref_ll).mean():.3g}")
     assert rel_err(ll[idx], ref_ll).max() <= TOL[prec]
     nrm = np.linalg.norm(g[idx] - ref_g, axis=1) / np.maximum(1.0, np.linalg.norm(ref_g, axis=1))
     assert nrm.max() <= GTOL[prec]
@@ -169,3 +170,31 @@ def test_autograd_function(orc):
     fp = sps.sps_loglik(ctx, to_gpu(th + e), 0, 400, 0).cpu().numpy()[3]
     fm = sps.sps_loglik(ctx, to_gpu(th - e), 0, 400, 0).cpu().numpy()[3]
     assert abs((fp - fm) / 2e-5 - ref_g[3, 5]) < 1e-5 * max(1, abs(ref_g[3, 5]))
+
+
+DIFF = [("binary30", 1), ("multi4", 2), ("ar100", 2), ("multi6", 2)]
+
+
+@pytest.mark.parametrize("name,prec", DIFF, ids=[f"{n}-{p}" for n, p in DIFF])
+def test_loglik_difference_error_full_size(orc, name, prec):
+    """What the MH test consumes is LL(theta') - LL(theta) for a nearby
+    proposal.  At full size and posterior scale, its error in nats must stay
+    far below the O(1) differences that decide acceptance."""
+    need_gpu()
+    from paper_1304_4333_amd import sps
+    w = synth.workload(name)
+    X, y, B = synth.make_data(w)
+    th = synth.make_particles(w.P, w.d, scale=0.02, seed=13, center=B.reshape(-1))
+    th2 = th + 0.005 * synth.make_normals(w.P, w.d, seed=14)
+    print(f"difference error {name}: P={w.P} T={w.T} d={w.d} prec={prec}", flush=True)
+    ctx = make_ctx(X, y, w.C, w.prior_sd)
+    a = sps.sps_loglik(ctx, to_gpu(th), 0, w.T, prec).cpu().numpy()
+    b = sps.sps_loglik(ctx, to_gpu(th2), 0, w.T, prec).cpu().numpy()
+    idx = synth.rng(15).choice(w.P, size=12, replace=False)
+    ra = orc.loglik(X, y, w.C, th[idx], 0, w.T)
+    rb = orc.loglik(X, y, w.C, th2[idx], 0, w.T)
+    err_abs = np.abs(a[idx] - ra).max()
+    err_diff = np.abs((b[idx] - a[idx]) - (rb - ra)).max()
+    print(f"  |LL| ~ {np.abs(ra).mean():.4g}, |dLL| ~ {np.abs(rb - ra).mean():.3g}; "
+          f"max error LL {err_abs:.3g} nats, dLL {err_diff:.3g} nats")
+    assert err_diff <= 0.05
