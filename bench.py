@@ -338,6 +338,8 @@ def main():
     ap.add_argument("--sps-seeds", type=int, default=2)
     ap.add_argument("--kernel-table", default=None,
                     help="comma-separated workloads: print full-data loglik/grad rates instead")
+    ap.add_argument("--sps-only", action="store_true",
+                    help="run only the fixed-NSE SPS comparison and print it")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a device copy of 1 GiB (counter calibration)")
     args = ap.parse_args()
@@ -346,6 +348,10 @@ def main():
         return
     if args.kernel_table:
         kernel_table(args.kernel_table.split(","))
+        return
+    if args.sps_only:
+        from paper_1304_4333_amd import synth
+        print(json.dumps(sps_fixed_nse(synth.workload(args.workload), list(range(1, 1 + args.sps_seeds)))))
         return
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); the particle-group "

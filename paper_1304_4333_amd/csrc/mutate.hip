@@ -242,20 +242,20 @@ __global__ void sub_kernel(const double* __restrict__ a, const double* __restric
     if (e < n) out[e] = a[e] - b[e];
 }
 
-// Butterfly sum over the 64 lanes of a wave; every lane ends with the same
-// bits (each stage adds the same two operands in both partner lanes).
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m, 64);
-    return v;
-}
-
-// One wave per particle, kAccPerWave particles per wave in turn:
+// 16 lanes per particle (4 particles per wave, 16 per workgroup):
 // log alpha = [ll' + log p(theta')] - [ll + log p(theta)]
 //             (+ MALA: -|v|^2 / 2 + |z|^2 / 2, v = L^-1 (theta - mu(theta')), L L' = Sigma);
 // accept iff log u < log alpha; accepted particles take theta', ll' (grad').
-// Accepted particles are counted per block and added with one atomic.
-constexpr int kAccPerWave = 16;
+// The prior terms use the whitened particles w0, w1 when given (full prior),
+// else (theta - mu) / sd.  Sums over the 16 lanes are fixed butterflies.
+// Accepted particles are counted per workgroup and added with one atomic.
+constexpr int kAccLanes = 16;
+constexpr int kAccPerBlock = 256 / kAccLanes;
+__device__ __forceinline__ double sum16(double v) {
+#pragma unroll
+    for (int m = kAccLanes / 2; m > 0; m >>= 1) v += __shfl_xor(v, m, 64);
+    return v;
+}
 __global__ __launch_bounds__(256) void accept_kernel(
     double* __restrict__ theta, double* __restrict__ ll, double* __restrict__ grad,
     const double* __restrict__ theta2, const double* __restrict__ ll2,
@@ -263,19 +263,17 @@ __global__ __launch_bounds__(256) void accept_kernel(
     const double* __restrict__ u, const double* __restrict__ mu, const double* __restrict__ isd,
     const double* __restrict__ w0, const double* __restrict__ w1,
     int64_t P, int32_t d, int mala, const unsigned* flags, unsigned long long* count) {
-    __shared__ unsigned nacc[4];
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    __shared__ unsigned nacc[256 / kAccLanes];
+    const int sub = threadIdx.x & (kAccLanes - 1);
+    const int slot = threadIdx.x / kAccLanes;
+    const int64_t p = (int64_t)blockIdx.x * kAccPerBlock + slot;
     const bool ok = !(*flags & kFlagNotPD);
     unsigned taken = 0;
-    for (int q = 0; q < kAccPerWave && ok; ++q) {
-        const int64_t p = ((int64_t)blockIdx.x * 4 + wave) * kAccPerWave + q;
-        if (p >= P) break;
+    if (ok && p < P) {  // the 16 lanes of a particle share p: no divergence inside a group
         const double* a = theta + p * d;
         const double* b = theta2 + p * d;
         double q0 = 0.0, q1 = 0.0, vv = 0.0, zz = 0.0;
-        for (int32_t i = lane; i < d; i += 64) {
-            // whitened distance to the prior mean: given (full prior) or (theta - mu) / sd
+        for (int32_t i = sub; i < d; i += kAccLanes) {
             const double za = w0 ? w0[p * d + i] : (a[i] - mu[i]) * isd[i];
             const double zb = w0 ? w1[p * d + i] : (b[i] - mu[i]) * isd[i];
             q0 += za * za;
@@ -285,84 +283,92 @@ __global__ __launch_bounds__(256) void accept_kernel(
                 zz += z[p * d + i] * z[p * d + i];
             }
         }
-        q0 = wave_sum(q0);
-        q1 = wave_sum(q1);
+        q0 = sum16(q0);
+        q1 = sum16(q1);
         double la = (ll2[p] - 0.5 * q1) - (ll[p] - 0.5 * q0);
-        if (mala) la += -0.5 * wave_sum(vv) + 0.5 * wave_sum(zz);
+        if (mala) la += -0.5 * sum16(vv) + 0.5 * sum16(zz);
         if (isnan(la)) la = -INFINITY;
         if (log(u[p]) < la) {
-            for (int32_t i = lane; i < d; i += 64) {
+            for (int32_t i = sub; i < d; i += kAccLanes) {
                 theta[p * d + i] = b[i];
                 if (mala) grad[p * d + i] = grad2[p * d + i];
             }
-            if (lane == 0) ll[p] = ll2[p];
-            ++taken;
+            if (sub == 0) ll[p] = ll2[p];
+            taken = 1;
         }
     }
-    if (lane == 0) nacc[wave] = taken;
+    if (sub == 0) nacc[slot] = taken;
     __syncthreads();
     if (threadIdx.x == 0 && ok) {
-        const unsigned tot = nacc[0] + nacc[1] + nacc[2] + nacc[3];
+        unsigned tot = 0;
+        for (int q = 0; q < kAccPerBlock; ++q) tot += nacc[q];
         if (tot) atomicAdd(count, (unsigned long long)tot);
     }
 }
 
 // Cholesky and triangular inverse with the matrix held in LDS (d <= 64).
 constexpr int kSmallD = 64;
-__global__ __launch_bounds__(64) void cholesky_small_kernel(const double* __restrict__ V, int32_t d,
-                                                            double* __restrict__ L, unsigned* flags) {
-    __shared__ double Ls[kSmallD][kSmallD + 1];
-    __shared__ double col[kSmallD];
-    __shared__ int fail_s;
-    const int t = threadIdx.x;
-    if (t == 0) fail_s = 0;
-    for (int e = t; e < d * d; e += 64) Ls[e / d][e % d] = (e % d <= e / d) ? V[e] : 0.0;
+// d <= 64: right-looking Cholesky in LDS with 256 threads.  Per column j the
+// pivot's square root and reciprocal are formed by every thread (same value),
+// the column is scaled, and thread (ty, tx) of a 16 x 16 grid updates the
+// trailing entries (j + 1 + ty + 16 a, j + 1 + tx + 16 b) on or below the
+// diagonal.  A non-positive or non-finite pivot sets kFlagNotPD.
+__global__ __launch_bounds__(256) void cholesky_small_kernel(const double* __restrict__ V, int32_t d,
+                                                             double* __restrict__ L, unsigned* flags) {
+    __shared__ double A[kSmallD][kSmallD + 1];
+    const int t = threadIdx.x, tx = t & 15, ty = t >> 4;
+    for (int r = ty; r < d; r += 16)
+        for (int q = tx; q < d; q += 16) A[r][q] = (q <= r) ? V[r * d + q] : 0.0;
     __syncthreads();
     for (int j = 0; j < d; ++j) {
-        if (t >= j && t < d) {
-            double s = Ls[t][j];
-            for (int q = 0; q < j; ++q) s -= Ls[t][q] * Ls[j][q];
-            col[t] = s;
+        const double piv = A[j][j];
+        if (!(piv > 0.0) || !isfinite(piv)) {  // same value in every thread: uniform exit
+            if (t == 0) atomicOr(flags, kFlagNotPD);
+            return;
         }
-        __syncthreads();
-        const double piv = col[j];
-        if (!(piv > 0.0) || !isfinite(piv)) {
-            if (t == 0) {
-                fail_s = 1;
-                atomicOr(flags, kFlagNotPD);
-            }
-        }
-        __syncthreads();
-        if (fail_s) return;
         const double ljj = sqrt(piv);
-        if (t >= j && t < d) Ls[t][j] = (t == j) ? ljj : col[t] / ljj;
+        const double inv = 1.0 / ljj;
+        __syncthreads();  // every thread has read the pivot
+        if (t == j) A[j][j] = ljj;
+        else if (t > j && t < d) A[t][j] *= inv;
+        __syncthreads();
+        for (int r = j + 1 + ty; r < d; r += 16) {
+            const double lr = A[r][j];
+            for (int q = j + 1 + tx; q <= r; q += 16) A[r][q] -= lr * A[q][j];
+        }
         __syncthreads();
     }
-    for (int e = t; e < d * d; e += 64) L[e] = Ls[e / d][e % d];
+    for (int r = ty; r < d; r += 16)
+        for (int q = tx; q < d; q += 16) L[r * d + q] = A[r][q];
 }
 
+// d <= 64: W = L^-1 by forward substitution, one column per thread (the
+// columns are independent), reciprocals of the diagonal formed once.
 __global__ __launch_bounds__(64) void trinv_small_kernel(const double* __restrict__ L, int32_t d,
                                                          double* __restrict__ W, const unsigned* flags) {
     __shared__ double Ls[kSmallD][kSmallD + 1];
     __shared__ double Ws[kSmallD][kSmallD + 1];
+    __shared__ double rd[kSmallD];
     if (*flags & kFlagNotPD) return;
     const int t = threadIdx.x;
-    for (int e = t; e < d * d; e += 64) {
-        Ls[e / d][e % d] = L[e];
-        Ws[e / d][e % d] = 0.0;
+    for (int r = 0; r < d; ++r)
+        if (t < d) {
+            Ls[r][t] = L[r * d + t];
+            Ws[r][t] = 0.0;
+        }
+    if (t < d) rd[t] = 1.0 / L[t * d + t];
+    __syncthreads();
+    if (t < d) {
+        for (int r = t; r < d; ++r) {
+            double s = (r == t) ? 1.0 : 0.0;
+            for (int q = t; q < r; ++q) s -= Ls[r][q] * Ws[q][t];
+            Ws[r][t] = s * rd[r];
+        }
     }
     __syncthreads();
-    for (int i = 0; i < d; ++i) {
-        if (t <= i) {
-            double s = (t == i) ? 1.0 : 0.0;
-            for (int q = t; q < i; ++q) s -= Ls[i][q] * Ws[q][t];
-            Ws[i][t] = s / Ls[i][i];
-        }
-        __syncthreads();
-    }
-    for (int e = t; e < d * d; e += 64) W[e] = Ws[e / d][e % d];
+    for (int r = 0; r < d; ++r)
+        if (t < d) W[r * d + t] = Ws[r][t];
 }
-
 static inline unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 // One M step for every particle.  Sigma_in == nullptr: proposal covariance
@@ -438,7 +444,7 @@ static int mutate_impl(sps_ctx* c, const char* who, double* theta, double* ll, d
                                                                                       h, Sg);
         SPS_CHECK(launched(c, "cov_final_kernel"));
     }
-    if (d <= kSmallD) cholesky_small_kernel<<<1, 64, 0, c->stream>>>(Sg, d, L, flags);
+    if (d <= kSmallD) cholesky_small_kernel<<<1, 256, 0, c->stream>>>(Sg, d, L, flags);
     else cholesky_kernel<<<1, 1024, 0, c->stream>>>(Sg, d, L, flags);
     SPS_CHECK(launched(c, "cholesky_kernel"));
 
@@ -490,7 +496,7 @@ static int mutate_impl(sps_ctx* c, const char* who, double* theta, double* ll, d
         gemm_abt_kernel<<<gg, 256, 0, c->stream>>>(work, W, nullptr, gpi, P, d, 1.0);
         SPS_CHECK(launched(c, "gemm_abt_kernel"));
     }
-    accept_kernel<<<(unsigned)((P + 4 * kAccPerWave - 1) / (4 * kAccPerWave)), 256, 0, c->stream>>>(
+    accept_kernel<<<(unsigned)((P + kAccPerBlock - 1) / kAccPerBlock), 256, 0, c->stream>>>(
         theta, ll, grad, th2, ll2, mala ? (const double*)c->grad2.p : nullptr, z,
         mala ? (const double*)c->pstat.p : nullptr, u, c->prior_mean, c->prior_isd, R0, R1, P, d,
         mala ? 1 : 0, flags, count);

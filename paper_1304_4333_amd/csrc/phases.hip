@@ -486,40 +486,71 @@ __global__ void monitor_kernel(const double* __restrict__ theta, int64_t P, int3
     }
 }
 
-// Group sums of (g - g_0f) and its square, shifted by the first particle's
-// value for stability: part[(j * m + f) * 2 + {0, 1}].  Block per
-// (group, 256 functions).
-__global__ void moments_group_kernel(const double* __restrict__ g, int32_t N, int32_t m,
-                                     double* __restrict__ part) {
-    const int32_t j = blockIdx.y;
-    const int32_t f = blockIdx.x * 256 + threadIdx.x;
-    if (f >= m) return;
-    const double c = g[f];
+// Sums of (g - g_0f) and its square over sub-blocks of kMomSub particles of
+// a group, shifted by the first particle's value for stability:
+// part[((j * nsub + s) * m + f) * 2 + {0, 1}].  Block (function tile of 64,
+// group j, sub-block s); thread (f, lane q of 4) adds particles
+// s kMomSub + q, + 4, ... in order, then the 4 lanes combine in order.
+constexpr int kMomSub = 64;
+__global__ __launch_bounds__(256) void moments_group_kernel(const double* __restrict__ g, int32_t N, int32_t m,
+                                                            int32_t nsub, double* __restrict__ part) {
+    __shared__ double r1[4][64], r2[4][64];
+    const int fl = threadIdx.x & 63, q = threadIdx.x >> 6;
+    const int32_t f = blockIdx.x * 64 + fl;
+    const int32_t j = blockIdx.y, sb = blockIdx.z;
     double s1 = 0.0, s2 = 0.0;
-    for (int32_t n = 0; n < N; ++n) {
-        const double v = g[((int64_t)j * N + n) * m + f] - c;
-        s1 += v;
-        s2 += v * v;
+    if (f < m) {
+        const double c = g[f];
+        const int32_t n1 = min(N, (sb + 1) * kMomSub);
+        for (int32_t n = sb * kMomSub + q; n < n1; n += 4) {
+            const double v = g[((int64_t)j * N + n) * m + f] - c;
+            s1 += v;
+            s2 += v * v;
+        }
     }
-    part[((int64_t)j * m + f) * 2 + 0] = s1;
-    part[((int64_t)j * m + f) * 2 + 1] = s2;
+    r1[q][fl] = s1;
+    r2[q][fl] = s2;
+    __syncthreads();
+    if (q == 0 && f < m) {
+        const double a = ((r1[0][fl] + r1[1][fl]) + r1[2][fl]) + r1[3][fl];
+        const double b = ((r2[0][fl] + r2[1][fl]) + r2[2][fl]) + r2[3][fl];
+        part[(((int64_t)j * nsub + sb) * m + f) * 2 + 0] = a;
+        part[(((int64_t)j * nsub + sb) * m + f) * 2 + 1] = b;
+    }
 }
 
-// out[f] = mean, out[m+f] = sd, out[2m+f] = NSE, out[3m+f] = RNE.
-__global__ void moments_final_kernel(const double* __restrict__ g, const double* __restrict__ part,
-                                     int32_t J, int32_t N, int32_t m, double* __restrict__ out) {
-    const int32_t f = blockIdx.x * blockDim.x + threadIdx.x;
-    if (f >= m) return;
+// out[f] = mean, out[m+f] = sd, out[2m+f] = NSE, out[3m+f] = RNE.  One wave
+// per function: lane l takes groups l, l + 64, ... (each group's sub-block
+// sums added in order), then fixed butterflies combine the lanes.
+__device__ __forceinline__ double wave_sum64(double v) {
+#pragma unroll
+    for (int sh = 32; sh > 0; sh >>= 1) v += __shfl_xor(v, sh, 64);
+    return v;
+}
+__global__ __launch_bounds__(64) void moments_final_kernel(const double* __restrict__ g,
+                                                           const double* __restrict__ part, int32_t J,
+                                                           int32_t N, int32_t m, int32_t nsub,
+                                                           double* __restrict__ out) {
+    const int32_t f = blockIdx.x;
+    const int lane = threadIdx.x;
     const double c = g[f];
-    double gb = 0.0;
-    for (int32_t j = 0; j < J; ++j) gb += part[((int64_t)j * m + f) * 2] / (double)N;
-    gb /= (double)J;  // grand mean minus c
+    auto gsum = [&](int32_t j, int e) {  // group j's sum over its sub-blocks, in order
+        double a = 0.0;
+        for (int32_t sb = 0; sb < nsub; ++sb) a += part[(((int64_t)j * nsub + sb) * m + f) * 2 + e];
+        return a;
+    };
+    double sg = 0.0;
+    for (int32_t j = lane; j < J; j += 64) sg += gsum(j, 0) / (double)N;
+    const double gb = wave_sum64(sg) / (double)J;  // grand mean minus c
     double vb = 0.0, ss = 0.0;
-    for (int32_t j = 0; j < J; ++j) {
-        const double gj = part[((int64_t)j * m + f) * 2] / (double)N;
+    for (int32_t j = lane; j < J; j += 64) {
+        const double gj = gsum(j, 0) / (double)N;
         vb += (gj - gb) * (gj - gb);
-        ss += part[((int64_t)j * m + f) * 2 + 1];
+        ss += gsum(j, 1);
     }
+    vb = wave_sum64(vb);
+    ss = wave_sum64(ss);
+    if (lane != 0) return;
     const double P = (double)J * (double)N;
     const double vhat = J > 1 ? (double)N / (double)(J - 1) * vb : 0.0;
     double var = ss / P - gb * gb;
@@ -764,13 +795,14 @@ extern "C" int sps_moments(sps_ctx* c, const double* g, int32_t J, int32_t N, in
     if (!c) return SPS_ERR_ARG;
     c->err.clear();
     if (J < 1 || N < 1 || m < 1 || !g) return fail(c, SPS_ERR_ARG, "sps_moments: bad arguments");
-    SPS_CHECK(ensure(c, c->gstat, sizeof(double) * ((size_t)J * m * 2 + 4 * (size_t)m), "moments"));
+    const int32_t nsub = (N + kMomSub - 1) / kMomSub;
+    SPS_CHECK(ensure(c, c->gstat, sizeof(double) * ((size_t)J * nsub * m * 2 + 4 * (size_t)m), "moments"));
     SPS_CHECK(ensure_host(c, c->hostbuf, sizeof(double) * 4 * (size_t)m + 64));
     double* part = (double*)c->gstat.p;
-    double* out = part + (size_t)J * m * 2;
-    moments_group_kernel<<<dim3((m + 255) / 256, J), 256, 0, c->stream>>>(g, N, m, part);
+    double* out = part + (size_t)J * nsub * m * 2;
+    moments_group_kernel<<<dim3((m + 63) / 64, J, nsub), 256, 0, c->stream>>>(g, N, m, nsub, part);
     SPS_CHECK(launched(c, "moments_group_kernel"));
-    moments_final_kernel<<<(m + 255) / 256, 256, 0, c->stream>>>(g, part, J, N, m, out);
+    moments_final_kernel<<<m, 64, 0, c->stream>>>(g, part, J, N, m, nsub, out);
     SPS_CHECK(launched(c, "moments_final_kernel"));
     SPS_HIP(c, hipMemcpyAsync(c->hostbuf.p, out, sizeof(double) * 4 * m, hipMemcpyDeviceToHost, c->stream));
     SPS_HIP(c, hipStreamSynchronize(c->stream));
