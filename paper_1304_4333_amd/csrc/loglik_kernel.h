@@ -132,13 +132,16 @@ struct Shape {
     static constexpr int afrag = 2 * (BF ? 8 * KS : w * KS);      // one set: two tiles
     static constexpr int per1 = NC * (breg + accr + grad);
     // Measured on gfx950 (binary k=30 in all three precisions, BF16 with
-    // k = 20/50/100 and C = 4/6): two particle blocks per wave pay off when a
-    // wave has a single outcome column, i.e. each X fragment feeds NC*PW = 2
-    // MFMA chains; with C > 2 the outcome columns already give that reuse and
-    // the extra registers cost occupancy.  The FP64 adjoint (64 registers per
-    // block) is the exception.  Over 256 live registers per lane, use one.
+    // k = 20/50/100 and C = 4/6): several particle blocks per wave pay off when
+    // a wave has a single outcome column (each X fragment then feeds NC*PW
+    // MFMA chains): four for the FP32/BF16 forward kernel, two with the
+    // adjoint and for FP64; with C > 2 the outcome columns already give that
+    // reuse and the extra registers cost occupancy.  The FP64 adjoint (64
+    // registers per block) is the exception.  Over 256 live registers per lane,
+    // use one.
     static constexpr int PW =
-        (NC == 1 && !(PREC == SPS_FP64 && MODE == MODE_GRAD) && afrag + 2 * per1 <= 256) ? 2 : 1;
+        (NC == 1 && MODE == MODE_FWD && PREC != SPS_FP64 && afrag + 4 * per1 <= 256) ? 4
+        : (NC == 1 && !(PREC == SPS_FP64 && MODE == MODE_GRAD) && afrag + 2 * per1 <= 256) ? 2 : 1;
     // Double-buffering the X fragments measured slower or equal everywhere
     // (it doubles the live fragments and accumulators): off by default.
     static constexpr bool PIPE = false;
@@ -381,8 +384,15 @@ __global__ __launch_bounds__(256) void loglik_kernel(LoglikArgs a) {
                 constexpr int CS = decltype(set_c)::value;
                 constexpr bool MASKED = decltype(masked_c)::value;
                 constexpr bool PEROBS = decltype(perobs_c)::value;
-                constexpr bool FAST = decltype(fast_c)::value;  // no max shift (SUFF only)
+                constexpr bool FAST = decltype(fast_c)::value;  // unshifted form, checked after the step
                 constexpr bool NOY = SUFF && !PEROBS;           // eta_y via sufficient statistics
+                // binary fast form: the 8 factors 1 + 2^z of a lane and particle block are
+                // multiplied and their log2 taken once (one log instead of eight)
+                [[maybe_unused]] E prod[(NC == 1 && FAST) ? PW : 1];
+                if constexpr (NC == 1 && FAST) {
+#pragma unroll
+                    for (int b = 0; b < PW; ++b) prod[b] = E(1);
+                }
     #pragma unroll
                 for (int h = 0; h < 2; ++h) {
     #pragma unroll
@@ -394,13 +404,17 @@ __global__ __launch_bounds__(256) void loglik_kernel(LoglikArgs a) {
                         for (int b = 0; b < PW; ++b) {
                             E lp;
                             if constexpr (NC == 1 && FAST) {
-                                // base 2, unshifted: l2 = -log2(1 + 2^z).  Exact in range while
-                                // 2^z is finite (z < 128); otherwise tsum turns -inf or NaN and
-                                // the step is redone below with the shifted form.
+                                // base 2, unshifted: l2 = -log2(1 + 2^z), summed as
+                                // -log2 of the product of the factors (below).  Exact in
+                                // range while the product is finite; otherwise tsum turns
+                                // -inf or NaN and the step is redone with the shifted form.
                                 const E z = acc[CS][h][b][0][i];
-                                const float lg = flog2(1.f + fexp2(z));
-                                lp = -lg;
-                                if constexpr (GRAD) rres[h][i][b][0] = ov ? fexp2(z - lg) : 0.f;
+                                const float e = fexp2(z);
+                                const float sfac = 1.f + e;
+                                prod[b] *= (MASKED && !ov) ? 1.f : sfac;
+                                lp = E(0);
+                                // sigmoid(z) = 2^z / (1 + 2^z)
+                                if constexpr (GRAD) rres[h][i][b][0] = ov ? e * frcp(sfac) : 0.f;
                             } else if constexpr (NC == 1) {
                                 // Binary with sign folding: l = -softplus(z), z = x~' theta.
                                 const E z = acc[CS][h][b][0][i];
@@ -470,7 +484,7 @@ __global__ __launch_bounds__(256) void loglik_kernel(LoglikArgs a) {
                                             ov ? ((!NOY && yt == c + 1 ? E(1) : E(0)) - ec[c] * inv) : E(0);
                                 }
                             }
-                            tsum[b] += MASKED ? (ov ? lp : E(0)) : lp;
+                            if constexpr (!(NC == 1 && FAST)) tsum[b] += MASKED ? (ov ? lp : E(0)) : lp;
                             if constexpr (PEROBS) {
                                 const int64_t p = pbase + b * 16 + r16;
                                 if (ov && p < a.P)
@@ -478,6 +492,10 @@ __global__ __launch_bounds__(256) void loglik_kernel(LoglikArgs a) {
                             }
                         }
                     }
+                }
+                if constexpr (NC == 1 && FAST) {
+#pragma unroll
+                    for (int b = 0; b < PW; ++b) tsum[b] -= flog2(prod[b]);
                 }
             };
 
