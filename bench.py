@@ -97,7 +97,15 @@ def gpu_bench(w, steps, warmup, seed=1):
     return dict(evals=evals, elapsed=elapsed, kt=kt, t_ends=t_ends, P=P, s0=s0)
 
 
-def sps_fixed_nse(w, seeds):
+def _progress(tag):
+    def log(rec):
+        if rec["cycle"] % 25 == 0:
+            print(f"{tag} cycle {rec['cycle']} t={rec['t']} R={rec['R']} h={rec['h']:.3f}",
+                  file=sys.stderr, flush=True)
+    return log
+
+
+def sps_fixed_nse(w, seeds, rw_hmin=0.1):
     """Whole adaptive SPS runs on the workload: (A) the paper's Gaussian
     random walk with the FP64 likelihood, (B) the split-precision likelihood
     with the MALA M phase.  Efficiency per monitored moment e = wall * NSE^2
@@ -112,8 +120,10 @@ def sps_fixed_nse(w, seeds):
     fast = "bf16x3" if w.precision != "fp64" else "fp64"
     out = {"A": [], "B": []}
     for seed in seeds:
-        ra = driver.run_sps(ctx, driver.SpsConfig(J=w.J, N=w.N, precision="fp64", kind="rw", seed=seed))
-        rb = driver.run_sps(ctx, driver.SpsConfig.mala_defaults(J=w.J, N=w.N, precision=fast, seed=seed))
+        ra = driver.run_sps(ctx, driver.SpsConfig(J=w.J, N=w.N, precision="fp64", kind="rw", seed=seed,
+                                                  h_min=rw_hmin), log=_progress(f"A seed {seed}"))
+        rb = driver.run_sps(ctx, driver.SpsConfig.mala_defaults(J=w.J, N=w.N, precision=fast, seed=seed),
+                            log=_progress(f"B seed {seed}"))
         out["A"].append(ra)
         out["B"].append(rb)
     torch.cuda.synchronize()
@@ -141,13 +151,49 @@ def sps_fixed_nse(w, seeds):
     # in the precision of run B
     t_ll, t_gr = _call_times(ctx, w, fast)
     steps_ratio = float(np.mean([r["m_iters"] for r in out["A"]]) / np.mean([r["m_iters"] for r in out["B"]]))
-    return {"A": dict(summary(out["A"]), precision="fp64", kernel="rw"),
+    return {"A": dict(summary(out["A"]), precision="fp64", kernel="rw", h_min=rw_hmin),
             "B": dict(summary(out["B"]), precision=fast, kernel="mala"),
             "efficiency_ratio_A_over_B": round(float(np.mean(ratios)), 3),
             "max_mean_z_A_vs_B": round(float(z.max()), 2), "seeds": list(seeds),
             "m_steps_ratio_rw_over_mala": round(steps_ratio, 3),
             "grad_over_loglik_time": round(t_gr / t_ll, 3),
             "mixing_gain_per_call": round(steps_ratio / (t_gr / t_ll), 3)}
+
+
+def design_sweep(w, seeds, ess_fracs=(0.3, 0.5, 0.7), k_mids=(0.35, 0.9), kind="rw"):
+    """Algorithm 2 with other design constants (Section 2.3 discusses them):
+    the ESS threshold of the C phase and the RNE target K of the cycles before
+    the last.  One JSON line per setting: cycles, M steps, wall time, logML,
+    its reported NSE and the spread of logML over the seeds."""
+    import torch
+    from paper_1304_4333_amd import driver
+    X, y, _ = synth_data(w)
+    ctx = driver.setup(X, y, w.C, 0.0, w.prior_sd)
+    rows = []
+    for ef in ess_fracs:
+        for km in k_mids:
+            rs = []
+            for seed in seeds:
+                base = dict(J=w.J, N=w.N, precision=w.precision, seed=seed, ess_frac=ef, K_mid=km)
+                cfg = driver.SpsConfig.mala_defaults(**base) if kind == "mala" else driver.SpsConfig(**base)
+                rs.append(driver.run_sps(ctx, cfg))
+            torch.cuda.synchronize()
+            lm = np.array([r["logml"] for r in rs])
+            row = dict(workload=w.name, kind=kind, precision=w.precision, ess_frac=ef, K_mid=km,
+                       seeds=len(seeds), cycles=float(np.mean([r["cycles"] for r in rs])),
+                       m_steps=float(np.mean([r["m_iters"] for r in rs])),
+                       wall_s=round(float(np.mean([r["wall"] for r in rs])), 4),
+                       logml=round(float(lm.mean()), 4),
+                       logml_nse=round(float(np.mean([r["logml_nse"] for r in rs])), 4),
+                       logml_sd_over_seeds=round(float(lm.std(ddof=1)), 4) if len(rs) > 1 else None)
+            rows.append(row)
+            print(json.dumps(row), flush=True)
+    return rows
+
+
+def synth_data(w):
+    from paper_1304_4333_amd import synth
+    return synth.make_data(w)
 
 
 def _call_times(ctx, w, precision, reps=5):
@@ -336,8 +382,13 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sps", action="store_true", help="skip the fixed-NSE SPS comparison")
     ap.add_argument("--sps-seeds", type=int, default=2)
+    ap.add_argument("--rw-hmin", type=float, default=0.1,
+                    help="lower bound of the RW step-size factor in the fixed-NSE comparison")
     ap.add_argument("--kernel-table", default=None,
                     help="comma-separated workloads: print full-data loglik/grad rates instead")
+    ap.add_argument("--design-sweep", action="store_true",
+                    help="run Algorithm 2 over ESS thresholds and RNE targets and print one line each")
+    ap.add_argument("--sweep-kind", default="rw", choices=["rw", "mala"])
     ap.add_argument("--sps-only", action="store_true",
                     help="run only the fixed-NSE SPS comparison and print it")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -349,9 +400,14 @@ def main():
     if args.kernel_table:
         kernel_table(args.kernel_table.split(","))
         return
+    if args.design_sweep:
+        from paper_1304_4333_amd import synth
+        design_sweep(synth.workload(args.workload), list(range(1, 1 + args.sps_seeds)), kind=args.sweep_kind)
+        return
     if args.sps_only:
         from paper_1304_4333_amd import synth
-        print(json.dumps(sps_fixed_nse(synth.workload(args.workload), list(range(1, 1 + args.sps_seeds)))))
+        print(json.dumps(sps_fixed_nse(synth.workload(args.workload), list(range(1, 1 + args.sps_seeds)),
+                                       rw_hmin=args.rw_hmin)))
         return
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); the particle-group "

@@ -88,6 +88,7 @@ def run_sps(ctx: sps.Context, cfg: SpsConfig, log=None, record: bool = False) ->
     grad_b = torch.empty(P, d, **f64) if mala else None
     log_w = torch.empty(P, **f64)
     logml_j = torch.zeros(J, **f64)
+    inc_j = torch.empty(J, **f64)
     g = torch.empty(P, m, **f64)
     anc = torch.empty(P, dtype=torch.int32, device=dev)
 
@@ -103,8 +104,13 @@ def run_sps(ctx: sps.Context, cfg: SpsConfig, log=None, record: bool = False) ->
     logml = nse_logml = float("nan")
     while t < T:
         cycle += 1
+        t_prev = t
         log_w, t_end, ess = sps.sps_correct(ctx, theta, ll, J, N, t, cfg.ess_frac, prec, log_w)
         t = t_end
+        # log predictive likelihood of y_{t_prev+1 .. t} given y_{1 .. t_prev} (Section 3):
+        # the same estimator as the log marginal likelihood, on this cycle's weights alone
+        inc_j.zero_()
+        pred, pred_nse = sps.sps_logml(ctx, log_w, J, N, inc_j)
         logml, nse_logml = sps.sps_logml(ctx, log_w, J, N, logml_j)
         sps.sps_resample(ctx, log_w, J, N, scheme, seed=cfg.seed, stream=stream_id(cycle, 0, 2),
                          ancestor=anc, theta_in=theta, theta_out=theta_b, ll_in=ll, ll_out=ll_b)
@@ -132,7 +138,8 @@ def run_sps(ctx: sps.Context, cfg: SpsConfig, log=None, record: bool = False) ->
                 hit_R_max += 1
                 break
         m_iters += r
-        rec = dict(cycle=cycle, t=t, ess=ess, R=r, h=h, acc=rate, rne=agg, logml=logml)
+        rec = dict(cycle=cycle, t_prev=t_prev, t=t, ess=ess, R=r, h=h, acc=rate, rne=agg, logml=logml,
+                   pred=pred, pred_nse=pred_nse)
         records.append(rec)
         if log is not None:
             log(rec)

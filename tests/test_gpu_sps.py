@@ -90,3 +90,36 @@ def test_two_pass_vs_oracle_two_pass(orc):
     assert z.max() < 4.0
     zl = abs(g2["logml"] - o2["logml"]) / math.hypot(g2["logml_nse"], o2["logml_nse"])
     assert zl < 4.0
+
+
+def test_predictive_likelihoods_vs_quadrature():
+    """Section 3 by-product: each cycle's log predictive likelihood of its new
+    observations given the earlier ones, log p(y_{s+1:t} | y_{1:s}).  For the
+    intercept model it is log Z(t) - log Z(s) with Z the prefix marginal
+    likelihood, computed here by quadrature."""
+    need_gpu()
+    from paper_1304_4333_amd import driver
+    T = 80
+    X = np.ones((T, 1))
+    y = (synth.rng(6).random(T) < 0.7).astype(np.int32)
+
+    def logZ(t):
+        if t == 0:
+            return 0.0
+        m = int(y[:t].sum())
+        f = lambda a: math.exp(stats.norm.logpdf(a, 0, 5) + m * special.log_expit(a)
+                               + (t - m) * special.log_expit(-a))
+        return math.log(integrate.quad(f, -15, 15, epsabs=0, epsrel=1e-12, limit=400)[0])
+
+    ctx = driver.setup(X, y, 2, 0.0, 5.0)
+    r = driver.run_sps(ctx, driver.SpsConfig(J=32, N=512, precision="fp64", seed=9))
+    assert len(r["records"]) >= 3
+    zs = []
+    for rec in r["records"]:
+        exact = logZ(rec["t"]) - logZ(rec["t_prev"])
+        err = abs(rec["pred"] - exact)
+        zs.append(err / max(rec["pred_nse"], 1e-12))
+        assert err < 4 * rec["pred_nse"] + 2e-3, (rec, exact)
+    print("cycles", len(zs), "max z", round(max(zs), 2))
+    # the predictive likelihoods chain to the marginal likelihood of all T observations
+    assert abs(sum(rec["pred"] for rec in r["records"]) - logZ(T)) < 4 * r["logml_nse"] * len(zs) ** 0.5 + 0.02
