@@ -199,9 +199,10 @@ int sps_resample_int(sps_ctx* ctx, const uint64_t* W, int32_t J, int32_t N,
  * and, for MALA, grad (device P x d: its gradient) are updated in place for
  * accepted particles; accept iff log u < log alpha.  z: device P x d
  * normals, u: device P uniforms in (0, 1), or NULL for Philox draws from
- * (seed, stream) and (seed, stream + 1).  *accept_rate (host, may be NULL to
- * stay asynchronous) = accepted / P.  SPS_ERR_NOT_PD if V is not positive
- * definite (the failure of Section 4.2); then nothing is modified.
+ * (seed, stream) and (seed, stream + 1).  *accept_rate (host, may be NULL)
+ * = accepted / P.  The call synchronises the stream (the accepted count and
+ * the positive-definiteness flag are read back).  SPS_ERR_NOT_PD if V is not
+ * positive definite (the failure of Section 4.2); then nothing is modified.
  * The log-likelihood of the proposal uses precision prec. */
 int sps_mutate(sps_ctx* ctx, double* theta, double* ll, double* grad, int32_t J,
                int32_t N, int64_t t, double h, int kind, int prec, const double* z,
@@ -217,6 +218,28 @@ int sps_mutate_cov(sps_ctx* ctx, double* theta, double* ll, double* grad,
                    int32_t J, int32_t N, int64_t t, const double* Sigma, int kind,
                    int prec, const double* z, const double* u, uint64_t seed,
                    uint64_t stream, double* accept_rate);
+
+/* The M phase of one cycle, Algorithm 2 step 2(c), in one call.  Step
+ * r = 1, 2, ... is the step of sps_mutate with the current h and Philox
+ * streams stream0 + r stream_step (normals) and that + 1 (uniforms); after it
+ * the monitored functions (sps_monitor) and their RNEs (sps_moments) are
+ * formed on the device and aggregated (rne_rule 0: mean, 1: minimum).  The
+ * host reads back one small record per step and applies the step-size rule
+ * (h += h_step if the acceptance rate exceeds acc_target, else h -= h_step,
+ * kept in [h_min, h_max]) and the stopping rule (aggregate RNE >= K, or
+ * R_max steps).  theta, ll, grad: as sps_mutate.  h: host, in: the step-size
+ * factor of the first step, out: after the last update.  g_work: device
+ * scratch of P x (d + C - 1) FP64.  sigma_out: device, R_max x d x d FP64, or
+ * NULL; receives the proposal covariance of every step (the record of
+ * Algorithm 3's first pass).  *R_out: steps taken; *rne_out, *rate_out (host,
+ * may be NULL): aggregate RNE and acceptance rate of the last step.  Errors
+ * as sps_mutate (SPS_ERR_NOT_PD stops the loop; the steps before it stand). */
+int sps_mphase(sps_ctx* ctx, double* theta, double* ll, double* grad, int32_t J,
+               int32_t N, int64_t t, int kind, int prec, double* h, double h_step,
+               double h_min, double h_max, double acc_target, double K, int32_t R_max,
+               int rne_rule, uint64_t seed, uint64_t stream0, uint64_t stream_step,
+               double* g_work, double* sigma_out, int32_t* R_out, double* rne_out,
+               double* rate_out);
 
 /* Copy of the proposal covariance (h V, or the given Sigma) used by the last
  * sps_mutate / sps_mutate_cov call on ctx into Sigma (device, d x d FP64):

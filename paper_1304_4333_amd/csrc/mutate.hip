@@ -375,10 +375,11 @@ static inline unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
 // h V from the particles (Algorithm 2); otherwise the given matrix
 // (Algorithm 3, second pass).  The Sigma used stays in the context for
 // sps_last_sigma.
-static int mutate_impl(sps_ctx* c, const char* who, double* theta, double* ll, double* grad, int32_t J,
-                       int32_t N, int64_t t, double h, const double* Sigma_in, int kind, int prec,
-                       const double* z, const double* u, uint64_t seed, uint64_t stream,
-                       double* accept_rate) {
+// All launches of one M step; the accepted count and the status flags are
+// left in c->small (flags at byte 0, count at byte 8).  No synchronisation.
+static int mutate_launch(sps_ctx* c, const char* who, double* theta, double* ll, double* grad, int32_t J,
+                         int32_t N, int64_t t, double h, const double* Sigma_in, int kind, int prec,
+                         const double* z, const double* u, uint64_t seed, uint64_t stream) {
     if (!c->has_data || !c->has_prior) return fail(c, SPS_ERR_STATE, "%s: set data and prior first", who);
     if (J < 1 || N < 1 || (int64_t)J * N < 2 || !theta || !ll)
         return fail(c, SPS_ERR_ARG, "%s: bad arguments (need J N >= 2, theta, ll)", who);
@@ -501,15 +502,28 @@ static int mutate_impl(sps_ctx* c, const char* who, double* theta, double* ll, d
         mala ? (const double*)c->pstat.p : nullptr, u, c->prior_mean, c->prior_isd, R0, R1, P, d,
         mala ? 1 : 0, flags, count);
     SPS_CHECK(launched(c, "accept_kernel"));
-    SPS_HIP(c, hipMemcpyAsync(c->hostbuf.p, c->small.p, 16, hipMemcpyDeviceToHost, c->stream));
-    SPS_HIP(c, hipStreamSynchronize(c->stream));
     c->has_sigma = true;
+    return SPS_OK;
+}
+
+// Read back `bytes` of c->small (flags, accepted count, ...) and check the flags.
+static int mutate_readback(sps_ctx* c, const char* who, int64_t P, size_t bytes, double* accept_rate) {
+    SPS_HIP(c, hipMemcpyAsync(c->hostbuf.p, c->small.p, bytes, hipMemcpyDeviceToHost, c->stream));
+    SPS_HIP(c, hipStreamSynchronize(c->stream));
     const unsigned f = *(const unsigned*)c->hostbuf.p;
     const unsigned long long n_acc = *(const unsigned long long*)((const char*)c->hostbuf.p + 8);
     if (f & kFlagNotPD)
         return fail(c, SPS_ERR_NOT_PD, "%s: the proposal covariance is not positive definite", who);
     if (accept_rate) *accept_rate = (double)n_acc / (double)P;
     return SPS_OK;
+}
+
+static int mutate_impl(sps_ctx* c, const char* who, double* theta, double* ll, double* grad, int32_t J,
+                       int32_t N, int64_t t, double h, const double* Sigma_in, int kind, int prec,
+                       const double* z, const double* u, uint64_t seed, uint64_t stream,
+                       double* accept_rate) {
+    SPS_CHECK(mutate_launch(c, who, theta, ll, grad, J, N, t, h, Sigma_in, kind, prec, z, u, seed, stream));
+    return mutate_readback(c, who, (int64_t)J * N, 16, accept_rate);
 }
 
 }  // namespace sps
@@ -543,5 +557,49 @@ extern "C" int sps_last_sigma(sps_ctx* c, double* Sigma) {
     if (!c->has_sigma) return fail(c, SPS_ERR_STATE, "sps_last_sigma: no M step has run");
     SPS_HIP(c, hipMemcpyAsync(Sigma, c->chol.p, sizeof(double) * c->d * c->d, hipMemcpyDeviceToDevice,
                               c->stream));
+    return SPS_OK;
+}
+
+// The M phase of one cycle (Algorithm 2 step 2(c)) in one call: steps
+// r = 1, 2, ... each take sps_mutate's step with h, then the monitored
+// functions, their NSE/RNE and the aggregate RNE on the device; one read-back
+// per step (flags, accepted count, aggregate) drives the step-size rule and
+// the stopping rule on the host.
+extern "C" int sps_mphase(sps_ctx* c, double* theta, double* ll, double* grad, int32_t J, int32_t N,
+                          int64_t t, int kind, int prec, double* h, double h_step, double h_min,
+                          double h_max, double acc_target, double K, int32_t R_max, int rne_rule,
+                          uint64_t seed, uint64_t stream0, uint64_t stream_step, double* g_work,
+                          double* sigma_out, int32_t* R_out, double* rne_out, double* rate_out) {
+    if (!c) return SPS_ERR_ARG;
+    c->err.clear();
+    if (!h || !g_work || !R_out || R_max < 1 || (rne_rule != 0 && rne_rule != 1) ||
+        !(h_min > 0.0) || !(h_max >= h_min) || !(h_step >= 0.0) || !std::isfinite(K))
+        return fail(c, SPS_ERR_ARG, "sps_mphase: bad arguments");
+    const int64_t P = (int64_t)J * N;
+    const int32_t d = c->d, m = c->d + c->C - 1;
+    double hh = *h;
+    int32_t r = 0;
+    double agg = 0.0, rate = 0.0;
+    for (;;) {
+        ++r;
+        const uint64_t st = stream0 + (uint64_t)r * stream_step;
+        SPS_CHECK(mutate_launch(c, "sps_mphase", theta, ll, grad, J, N, t, hh, nullptr, kind, prec, nullptr,
+                                nullptr, seed, st));
+        if (sigma_out)
+            SPS_HIP(c, hipMemcpyAsync(sigma_out + (size_t)(r - 1) * d * d, c->chol.p, sizeof(double) * d * d,
+                                      hipMemcpyDeviceToDevice, c->stream));
+        SPS_CHECK(monitor_launch(c, theta, P, g_work));
+        double* mom = nullptr;
+        SPS_CHECK(moments_launch(c, g_work, J, N, m, &mom));
+        SPS_CHECK(rne_aggregate(c, mom, m, rne_rule, (double*)((char*)c->small.p + 16)));
+        SPS_CHECK(mutate_readback(c, "sps_mphase", P, 24, &rate));
+        agg = *(const double*)((const char*)c->hostbuf.p + 16);
+        hh = rate > acc_target ? std::min(hh + h_step, h_max) : std::max(hh - h_step, h_min);
+        if (agg >= K || r >= R_max) break;
+    }
+    *h = hh;
+    *R_out = r;
+    if (rne_out) *rne_out = agg;
+    if (rate_out) *rate_out = rate;
     return SPS_OK;
 }

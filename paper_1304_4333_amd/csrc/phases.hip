@@ -779,15 +779,57 @@ extern "C" int sps_resample_int(sps_ctx* c, const uint64_t* W, int32_t J, int32_
     return resample_common(c, nullptr, W, J, N, scheme, u53, ancestor, "sps_resample_int");
 }
 
+namespace sps {
+
+int monitor_launch(sps_ctx* c, const double* theta, int64_t P, double* g) {
+    const int64_t n = P * (c->d + c->C - 1);
+    if (n == 0) return SPS_OK;
+    monitor_kernel<<<(unsigned)((n + 255) / 256), 256, 0, c->stream>>>(theta, P, c->k, c->C, c->xbar, g);
+    return launched(c, "monitor_kernel");
+}
+
+int moments_launch(sps_ctx* c, const double* g, int32_t J, int32_t N, int32_t m, double** out) {
+    const int32_t nsub = (N + kMomSub - 1) / kMomSub;
+    SPS_CHECK(ensure(c, c->gstat, sizeof(double) * ((size_t)J * nsub * m * 2 + 4 * (size_t)m), "moments"));
+    double* part = (double*)c->gstat.p;
+    double* o = part + (size_t)J * nsub * m * 2;
+    moments_group_kernel<<<dim3((m + 63) / 64, J, nsub), 256, 0, c->stream>>>(g, N, m, nsub, part);
+    SPS_CHECK(launched(c, "moments_group_kernel"));
+    moments_final_kernel<<<m, 64, 0, c->stream>>>(g, part, J, N, m, nsub, o);
+    SPS_CHECK(launched(c, "moments_final_kernel"));
+    *out = o;
+    return SPS_OK;
+}
+
+// dst = mean or minimum of the RNEs (mom[3m .. 4m)), lanes in a fixed order.
+__global__ __launch_bounds__(64) void rne_aggregate_kernel(const double* __restrict__ mom, int32_t m, int rule,
+                                                           double* __restrict__ dst) {
+    const int lane = threadIdx.x;
+    double s = 0.0, mn = INFINITY;
+    for (int32_t f = lane; f < m; f += 64) {
+        const double v = mom[3 * m + f];
+        s += v;
+        mn = fmin(mn, v);
+    }
+    s = wave_sum64(s);
+#pragma unroll
+    for (int sh = 32; sh > 0; sh >>= 1) mn = fmin(mn, __shfl_xor(mn, sh, 64));
+    if (lane == 0) dst[0] = rule == 1 ? mn : s / (double)m;
+}
+
+int rne_aggregate(sps_ctx* c, const double* mom, int32_t m, int rule, double* dst) {
+    rne_aggregate_kernel<<<1, 64, 0, c->stream>>>(mom, m, rule, dst);
+    return launched(c, "rne_aggregate_kernel");
+}
+
+}  // namespace sps
+
 extern "C" int sps_monitor(sps_ctx* c, const double* theta, int64_t P, double* g) {
     if (!c) return SPS_ERR_ARG;
     c->err.clear();
     if (!c->has_data) return fail(c, SPS_ERR_STATE, "sps_monitor: call sps_set_data first");
     if (P < 0 || ((!theta || !g) && P > 0)) return fail(c, SPS_ERR_ARG, "sps_monitor: bad arguments");
-    const int64_t n = P * (c->d + c->C - 1);
-    if (n == 0) return SPS_OK;
-    monitor_kernel<<<(unsigned)((n + 255) / 256), 256, 0, c->stream>>>(theta, P, c->k, c->C, c->xbar, g);
-    return launched(c, "monitor_kernel");
+    return monitor_launch(c, theta, P, g);
 }
 
 extern "C" int sps_moments(sps_ctx* c, const double* g, int32_t J, int32_t N, int32_t m, double* mean,
@@ -795,15 +837,9 @@ extern "C" int sps_moments(sps_ctx* c, const double* g, int32_t J, int32_t N, in
     if (!c) return SPS_ERR_ARG;
     c->err.clear();
     if (J < 1 || N < 1 || m < 1 || !g) return fail(c, SPS_ERR_ARG, "sps_moments: bad arguments");
-    const int32_t nsub = (N + kMomSub - 1) / kMomSub;
-    SPS_CHECK(ensure(c, c->gstat, sizeof(double) * ((size_t)J * nsub * m * 2 + 4 * (size_t)m), "moments"));
     SPS_CHECK(ensure_host(c, c->hostbuf, sizeof(double) * 4 * (size_t)m + 64));
-    double* part = (double*)c->gstat.p;
-    double* out = part + (size_t)J * nsub * m * 2;
-    moments_group_kernel<<<dim3((m + 63) / 64, J, nsub), 256, 0, c->stream>>>(g, N, m, nsub, part);
-    SPS_CHECK(launched(c, "moments_group_kernel"));
-    moments_final_kernel<<<m, 64, 0, c->stream>>>(g, part, J, N, m, nsub, out);
-    SPS_CHECK(launched(c, "moments_final_kernel"));
+    double* out = nullptr;
+    SPS_CHECK(moments_launch(c, g, J, N, m, &out));
     SPS_HIP(c, hipMemcpyAsync(c->hostbuf.p, out, sizeof(double) * 4 * m, hipMemcpyDeviceToHost, c->stream));
     SPS_HIP(c, hipStreamSynchronize(c->stream));
     const double* h = (const double*)c->hostbuf.p;

@@ -146,6 +146,13 @@ int random_fill(sps_ctx* c, int kind, uint64_t seed, uint64_t stream, int64_t co
 // Base may be null or alias Out.
 int gemm_abt(sps_ctx* c, const double* A, const double* B, const double* Base, double* Out,
              int64_t P, int32_t d, double alpha);
+// Monitored functions (theta and theta_c' xbar) of P particles into g (P x m).
+int monitor_launch(sps_ctx* c, const double* theta, int64_t P, double* g);
+// Moments of g (J groups of N, m functions) on the device; *out points at
+// [mean | sd | NSE | RNE] (4 m doubles, context scratch).
+int moments_launch(sps_ctx* c, const double* g, int32_t J, int32_t N, int32_t m, double** out);
+// dst[0] = mean (rule 0) or minimum (rule 1) of the m RNEs in mom.
+int rne_aggregate(sps_ctx* c, const double* mom, int32_t m, int rule, double* dst);
 // Full prior: R = rows L^-1 (theta_p - mean); tmp (P x d) is scratch.
 int prior_whiten(sps_ctx* c, const double* theta, int64_t P, double* tmp, double* R);
 

@@ -67,9 +67,13 @@ class Design:
     sigma: list
 
 
-def run_sps(ctx: sps.Context, cfg: SpsConfig, log=None, record: bool = False) -> dict:
+def run_sps(ctx: sps.Context, cfg: SpsConfig, log=None, record: bool = False,
+            fused: bool = True) -> dict:
     """One pass of the adaptive SPS (Algorithm 2) on the data and prior set in
-    ctx.  record=True also returns the Design of Algorithm 3's first pass."""
+    ctx.  record=True also returns the Design of Algorithm 3's first pass.
+    fused=True runs each cycle's M phase in one library call (sps_mphase, one
+    read-back per step); False takes it step by step from here (same
+    arithmetic, more host round trips)."""
     J, N = cfg.J, cfg.N
     P, d, C, T = J * N, ctx.d, ctx.C, ctx.T
     m = d + C - 1
@@ -122,7 +126,17 @@ def run_sps(ctx: sps.Context, cfg: SpsConfig, log=None, record: bool = False) ->
         K = cfg.K_mid if t < T else cfg.K_final
         r = 0
         rate = 0.0
-        while True:
+        if fused:
+            sig = torch.empty(cfg.R_max, d, d, **f64) if record else None
+            r, h, agg, rate = sps.sps_mphase(ctx, theta, ll, grad, J, N, t, kind, prec, h, cfg.h_step,
+                                             cfg.h_min, cfg.h_max, cfg.acc_target, K, cfg.R_max,
+                                             1 if cfg.rne_rule == "min" else 0, cfg.seed,
+                                             stream_id(cycle, 0, 3), 1 << 4, g, sig)
+            if record:
+                sigmas.extend(sig[i].clone() for i in range(r))
+            if agg < K:
+                hit_R_max += 1
+        while not fused:
             r += 1
             rate = sps.sps_mutate(ctx, theta, ll, grad, J, N, t, h, kind, prec,
                                   seed=cfg.seed, stream=stream_id(cycle, r, 3))

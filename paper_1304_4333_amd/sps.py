@@ -63,6 +63,9 @@ _SIGS = {
     "sps_mutate_cov": [_vp, _vp, _vp, _vp, _i32, _i32, _i64, _vp, ct.c_int, ct.c_int, _vp, _vp,
                        _u64, _u64, ct.POINTER(_dbl)],
     "sps_last_sigma": [_vp, _vp],
+    "sps_mphase": [_vp, _vp, _vp, _vp, _i32, _i32, _i64, ct.c_int, ct.c_int, ct.POINTER(_dbl), _dbl,
+                   _dbl, _dbl, _dbl, _dbl, _i32, ct.c_int, _u64, _u64, _u64, _vp, _vp,
+                   ct.POINTER(_i32), ct.POINTER(_dbl), ct.POINTER(_dbl)],
     "sps_correct_fixed": [_vp, _vp, _vp, _i32, _i32, _i64, _i64, ct.c_int, _vp],
     "sps_timing_enable": [_vp, ct.c_int],
     "sps_timing_read": [_vp, ct.c_int, ct.POINTER(_i64), ct.POINTER(_dbl)],
@@ -327,6 +330,27 @@ def sps_mutate_cov(ctx: Context, theta: torch.Tensor, ll: torch.Tensor, grad: Op
                                    kind, prec, _ptr(z), _ptr(u), seed, stream,
                                    ct.byref(rate) if want_rate else None))
     return rate.value if want_rate else None
+
+
+def sps_mphase(ctx: Context, theta: torch.Tensor, ll: torch.Tensor, grad: Optional[torch.Tensor],
+               J: int, N: int, t: int, kind: int, prec: int, h: float, h_step: float, h_min: float,
+               h_max: float, acc_target: float, K: float, R_max: int, rne_rule: int, seed: int,
+               stream0: int, stream_step: int, g_work: torch.Tensor,
+               sigma_out: Optional[torch.Tensor] = None):
+    """One cycle's M phase.  Returns (R, h after the last update, aggregate
+    RNE, acceptance rate of the last step)."""
+    P, d = J * N, ctx.d
+    ctx._t(theta, torch.float64, (P, d), "theta")
+    ctx._t(ll, torch.float64, (P,), "ll")
+    ctx._t(grad, torch.float64, (P, d), "grad", allow_none=True)
+    ctx._t(g_work, torch.float64, (P, d + ctx.C - 1), "g_work")
+    ctx._t(sigma_out, torch.float64, (R_max, d, d), "sigma_out", allow_none=True)
+    hh, R, rne, rate = _dbl(h), _i32(0), _dbl(), _dbl()
+    ctx.check(lib().sps_mphase(ctx.handle, _ptr(theta), _ptr(ll), _ptr(grad), J, N, t, kind, prec,
+                               ct.byref(hh), h_step, h_min, h_max, acc_target, K, R_max, rne_rule, seed,
+                               stream0, stream_step, _ptr(g_work), _ptr(sigma_out), ct.byref(R),
+                               ct.byref(rne), ct.byref(rate)))
+    return R.value, hh.value, rne.value, rate.value
 
 
 def sps_last_sigma(ctx: Context, out: Optional[torch.Tensor] = None) -> torch.Tensor:

@@ -123,3 +123,25 @@ def test_predictive_likelihoods_vs_quadrature():
     print("cycles", len(zs), "max z", round(max(zs), 2))
     # the predictive likelihoods chain to the marginal likelihood of all T observations
     assert abs(sum(rec["pred"] for rec in r["records"]) - logZ(T)) < 4 * r["logml_nse"] * len(zs) ** 0.5 + 0.02
+
+
+@pytest.mark.parametrize("prec,kind", [("fp64", "rw"), ("bf16x3", "mala")])
+def test_fused_m_phase_matches_step_by_step(prec, kind):
+    """sps_mphase runs the same steps with the same streams as the driver's
+    step-by-step loop: identical cycles, step counts, step sizes and particles."""
+    need_gpu()
+    import torch
+    from paper_1304_4333_amd import driver
+    w = synth.workload("small", T=300)
+    X, y, _ = synth.make_data(w)
+    mk = (lambda: driver.SpsConfig(J=8, N=128, precision=prec, seed=17)) if kind == "rw" else \
+        (lambda: driver.SpsConfig.mala_defaults(J=8, N=128, precision=prec, seed=17))
+    ctx = driver.setup(X, y, w.C, 0.0, w.prior_sd)
+    a = driver.run_sps(ctx, mk(), fused=True, record=True)
+    b = driver.run_sps(ctx, mk(), fused=False, record=True)
+    assert a["cycles"] == b["cycles"] and a["m_iters"] == b["m_iters"]
+    assert [r["R"] for r in a["records"]] == [r["R"] for r in b["records"]]
+    assert [r["h"] for r in a["records"]] == [r["h"] for r in b["records"]]
+    assert torch.equal(a["theta"], b["theta"])
+    assert a["logml"] == b["logml"]
+    assert all(torch.equal(s, q) for s, q in zip(a["design"].sigma, b["design"].sigma))
