@@ -575,6 +575,7 @@ extern "C" int sps_mphase(sps_ctx* c, double* theta, double* ll, double* grad, i
     if (!h || !g_work || !R_out || R_max < 1 || (rne_rule != 0 && rne_rule != 1) ||
         !(h_min > 0.0) || !(h_max >= h_min) || !(h_step >= 0.0) || !std::isfinite(K))
         return fail(c, SPS_ERR_ARG, "sps_mphase: bad arguments");
+    if (J > 65535 || (N + 63) / 64 > 65535) return fail(c, SPS_ERR_ARG, "sps_mphase: J or N too large");
     const int64_t P = (int64_t)J * N;
     const int32_t d = c->d, m = c->d + c->C - 1;
     double hh = *h;

@@ -837,6 +837,8 @@ extern "C" int sps_moments(sps_ctx* c, const double* g, int32_t J, int32_t N, in
     if (!c) return SPS_ERR_ARG;
     c->err.clear();
     if (J < 1 || N < 1 || m < 1 || !g) return fail(c, SPS_ERR_ARG, "sps_moments: bad arguments");
+    if (J > 65535 || (N + kMomSub - 1) / kMomSub > 65535)
+        return fail(c, SPS_ERR_ARG, "sps_moments: J=%d or N=%d too large for the launch grid", J, N);
     SPS_CHECK(ensure_host(c, c->hostbuf, sizeof(double) * 4 * (size_t)m + 64));
     double* out = nullptr;
     SPS_CHECK(moments_launch(c, g, J, N, m, &out));

@@ -145,3 +145,28 @@ def test_fused_m_phase_matches_step_by_step(prec, kind):
     assert torch.equal(a["theta"], b["theta"])
     assert a["logml"] == b["logml"]
     assert all(torch.equal(s, q) for s, q in zip(a["design"].sigma, b["design"].sigma))
+
+
+@pytest.mark.parametrize("prec,kind", [("fp32", "rw"), ("bf16x3", "mala")])
+def test_sps_multinomial_vs_oracle(orc, prec, kind):
+    """C = 3 (the sufficient-statistic form of the reduced-precision kernels)
+    over a whole adaptive run, against the oracle's own SPS."""
+    need_gpu()
+    from paper_1304_4333_amd import driver
+    from gpu_common import dataset
+    X, y, _ = dataset(300, 4, 3, seed=61)
+    J, N = 16, 256
+    cfg = driver.SpsConfig(J=J, N=N, precision=prec, seed=31) if kind == "rw" else \
+        driver.SpsConfig.mala_defaults(J=J, N=N, precision=prec, seed=31)
+    print(f"sps multinomial prec={prec} kind={kind}", flush=True)
+    ctx = driver.setup(X, y, 3, 0.0, 5.0)
+    g = driver.run_sps(ctx, cfg)
+    okw = dict(kind=orc.MALA if kind == "mala" else orc.RW)
+    if kind == "mala":
+        okw.update(h_min=0.01, h_max=2.0, acc_target=0.574)
+    o = orc.sps_run(X, y, 3, 0.0, 5.0, J, N, seed=32, **okw)
+    z = _z(g["mean"], o["mean"], g["nse"], o["nse"])
+    print("z-scores:", np.round(z, 2))
+    assert z.max() < 4.0
+    zl = abs(g["logml"] - o["logml"]) / math.hypot(g["logml_nse"], o["logml_nse"])
+    assert zl < 4.0
