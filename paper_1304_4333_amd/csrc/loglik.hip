@@ -108,7 +108,7 @@ static LoglikEntry lookup(int prec, int nc, int ks, int mode) {
 // per-observation terms written to perobs[(t - t0) * P + p] (forward only).
 static int run_loglik(sps_ctx* c, const double* theta, int64_t P, int64_t t0, int64_t t1,
                       int prec, double* ll, double* grad, double* perobs) {
-    const int mode = grad ? MODE_GRAD : MODE_FWD;
+    const int mode = grad ? MODE_GRAD : (perobs ? MODE_PEROBS : MODE_FWD);
     const int ks = (prec == SPS_BF16X3) ? c->kb / 32 : c->kp / 4;
     LoglikEntry e = lookup(prec, c->C - 1, ks, mode);
     if (!e.fn) return fail(c, SPS_ERR_ARG, "no likelihood kernel for C=%d k=%d prec=%d", c->C, c->k, prec);
@@ -136,9 +136,9 @@ static int run_loglik(sps_ctx* c, const double* theta, int64_t P, int64_t t0, in
     a.binary = c->C == 2;
     a.nsteps = (int32_t)((t1 - a.t0a + kObsStep - 1) / kObsStep);
     const int64_t npt = (P + e.ppb - 1) / e.ppb;
-    // Observation splits: enough blocks to fill 256 CUs several times over,
-    // at least 4 steps of work per wave, bounded partial-gradient storage.
-    const int64_t target_blocks = 2048;
+    // Observation splits: the kernel's workgroup target (measured per kernel
+    // shape), at least 4 steps of work per wave, bounded partial-gradient storage.
+    const int64_t target_blocks = e.target;
     int64_t nsplit = std::max<int64_t>(1, (target_blocks + npt - 1) / npt);
     nsplit = std::min<int64_t>(nsplit, std::max<int64_t>(1, a.nsteps / 4));
     if (grad) {

@@ -4,9 +4,11 @@
 namespace sps {
 
 LoglikEntry lookup_fp64(int nc, int ks, int mode) {
-#define SPS_E(NC, KS) \
-    if (nc == NC && ks == KS) return mode == MODE_GRAD ? loglik_entry<SPS_FP64, NC, KS, MODE_GRAD>() \
-                                                      : loglik_entry<SPS_FP64, NC, KS, MODE_FWD>();
+#define SPS_E(NC, KS)                                                                          \
+    if (nc == NC && ks == KS)                                                                  \
+        return mode == MODE_GRAD     ? loglik_entry<SPS_FP64, NC, KS, MODE_GRAD>()                  \
+               : mode == MODE_PEROBS ? loglik_entry<SPS_FP64, NC, KS, MODE_PEROBS>()                \
+                                     : loglik_entry<SPS_FP64, NC, KS, MODE_FWD>();
     SPS_E(1, 4)
     SPS_E(1, 8)
     SPS_E(1, 16)

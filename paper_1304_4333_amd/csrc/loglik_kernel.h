@@ -55,7 +55,9 @@ typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 constexpr double kLog2e = 1.4426950408889634074;
 constexpr double kLn2 = 0.69314718055994530942;
 
-enum { MODE_FWD = 0, MODE_GRAD = 1 };
+// MODE_PEROBS: the forward kernel as launched for per-observation output (C
+// phase): same arithmetic, tuned for short observation ranges.
+enum { MODE_FWD = 0, MODE_GRAD = 1, MODE_PEROBS = 2 };
 
 struct LoglikArgs {
     const void* X;      // row-major kernel copy of X (FP64 / FP32 / BF16 hi)
@@ -140,11 +142,20 @@ struct Shape {
     // registers per block) is the exception.  Over 256 live registers per lane,
     // use one.
     static constexpr int PW =
-        (NC == 1 && MODE == MODE_FWD && PREC != SPS_FP64 && afrag + 4 * per1 <= 256) ? 4
+        MODE == MODE_PEROBS ? 1
+        : (NC == 1 && PREC != SPS_FP64 && afrag + 4 * per1 <= 160) ? 4
         : (NC == 1 && !(PREC == SPS_FP64 && MODE == MODE_GRAD) && afrag + 2 * per1 <= 256) ? 2 : 1;
     // Double-buffering the X fragments measured slower or equal everywhere
     // (it doubles the live fragments and accumulators): off by default.
     static constexpr bool PIPE = false;
+    // Workgroups per launch the observation split aims at.  Measured: the
+    // FP32/BF16 kernels run fastest with few, long workgroups (about one or
+    // two waves per SIMD; fewer split partials and prologues), the gradient
+    // kernels with 256, the forward with 512, C > 2 with 1024.  FP64 and the
+    // per-observation launches keep more workgroups for latency hiding.
+    static constexpr int TARGET =
+        (PREC == SPS_FP64 || MODE == MODE_PEROBS) ? 2048
+        : NC > 1 ? 1024 : (MODE == MODE_GRAD ? 256 : 512);
 };
 
 template <int PREC, int NC, int KS, int MODE>
@@ -625,7 +636,8 @@ constexpr int particles_per_block() {
 typedef hipError_t (*LoglikLaunchFn)(const LoglikArgs&, dim3, hipStream_t);
 struct LoglikEntry {
     LoglikLaunchFn fn = nullptr;
-    int ppb = 0;  // particles per 256-thread block
+    int ppb = 0;     // particles per 256-thread block
+    int target = 0;  // workgroups per launch the observation split aims at
 };
 
 template <int PREC, int NC, int KS, int MODE>
@@ -633,6 +645,7 @@ LoglikEntry loglik_entry() {
     LoglikEntry e;
     e.fn = &launch_loglik<PREC, NC, KS, MODE>;
     e.ppb = particles_per_block<PREC, NC, KS, MODE>();
+    e.target = Shape<PREC, NC, KS, MODE>::TARGET;
     return e;
 }
 

@@ -86,19 +86,23 @@ __global__ void correct_chunk_sum_kernel(const double* __restrict__ lw, int64_t 
 // Pass 2 of the scan fused with the ESS statistics.  Thread (p, chunk)
 // forms the running log-weights of its chunk from the carried value and the
 // chunk totals (nothing is written back: correct_column_kernel rebuilds the
-// one column that is needed, in the same order); for every observation u of
-// the chunk each block reduces, over its 256 particles, m = max lw,
-// s1 = sum exp(lw - m), s2 = sum exp(2 (lw - m)) into
-// part[(u * npb + block) * 3 + {0, 1, 2}].  flags |= 1 on NaN or +inf.
+// one column that is needed, in the same order) and stages them in LDS.  For
+// every observation u of the chunk the block then reduces, over its 256
+// particles, m = max lw, s1 = sum exp(lw - m), s2 = sum exp(2 (lw - m)) into
+// part[(u * npb + block) * 3 + {0, 1, 2}]: thread (u, segment) handles 32
+// particles in order and the 8 segments combine in order.  flags |= 1 on NaN
+// or +inf.
 __global__ __launch_bounds__(256) void correct_scan_ess_kernel(const double* __restrict__ lw,
                                                                const double* __restrict__ carry,
                                                                const double* __restrict__ tot, int64_t P,
                                                                int32_t nb, double* __restrict__ part,
                                                                unsigned* flags) {
-    __shared__ double wm[4][kScanChunk], ws1[4][kScanChunk], ws2[4][kScanChunk];
-    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    constexpr int kSeg = 256 / kScanChunk;  // particle segments per observation
+    __shared__ double V[kScanChunk][257];
+    __shared__ double Ms[kScanChunk][kSeg], S1s[kScanChunk][kSeg], S2s[kScanChunk][kSeg];
+    const int t = threadIdx.x;
+    const int64_t p = (int64_t)blockIdx.x * 256 + t;
     const int32_t ch = blockIdx.y;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int32_t npb = gridDim.x;
     const bool pv = p < P;
     double acc = 0.0;
@@ -107,50 +111,53 @@ __global__ __launch_bounds__(256) void correct_scan_ess_kernel(const double* __r
         for (int32_t q = 0; q < ch; ++q) acc += tot[(int64_t)q * P + p];
     }
     const int32_t u0 = ch * kScanChunk;
-    const int32_t u1 = min(nb, u0 + kScanChunk);
+    const int32_t nu = min(nb, u0 + kScanChunk) - u0;
     bool bad = false;
-    for (int32_t u = u0; u < u1; ++u) {
+    for (int32_t u = 0; u < nu; ++u) {
         double v = -INFINITY;
         if (pv) {
-            acc += lw[(int64_t)u * P + p];
+            acc += lw[(int64_t)(u0 + u) * P + p];
             v = acc;
             bad |= isnan(acc) || acc == INFINITY;
         }
-        double m = v;
-#pragma unroll
-        for (int sh = 32; sh > 0; sh >>= 1) m = fmax(m, __shfl_xor(m, sh, 64));
-        const double w = (m > -INFINITY && v > -INFINITY) ? exp(v - m) : 0.0;
-        double s1 = w, s2 = w * w;
-#pragma unroll
-        for (int sh = 32; sh > 0; sh >>= 1) {
-            s1 += __shfl_xor(s1, sh, 64);
-            s2 += __shfl_xor(s2, sh, 64);
-        }
-        if (lane == 0) {
-            wm[wave][u - u0] = m;
-            ws1[wave][u - u0] = s1;
-            ws2[wave][u - u0] = s2;
-        }
+        V[u][t] = v;
     }
     if (bad) atomicOr(flags, 1u);
     __syncthreads();
-    const int uu = threadIdx.x;
-    if (uu < u1 - u0) {
-        double M = fmax(fmax(wm[0][uu], wm[1][uu]), fmax(wm[2][uu], wm[3][uu]));
-        double S1 = 0.0, S2 = 0.0;
-        if (M > -INFINITY) {
-            for (int w = 0; w < 4; ++w) {
-                if (wm[w][uu] > -INFINITY) {
-                    const double f = exp(wm[w][uu] - M);
-                    S1 += ws1[w][uu] * f;
-                    S2 += ws2[w][uu] * f * f;
-                }
+    const int uu = t % kScanChunk, seg = t / kScanChunk;
+    double m = -INFINITY;
+    if (uu < nu)
+        for (int j = 0; j < 32; ++j) m = fmax(m, V[uu][seg * 32 + j]);
+    Ms[uu][seg] = m;
+    __syncthreads();
+    double M = -INFINITY;
+#pragma unroll
+    for (int q = 0; q < kSeg; ++q) M = fmax(M, Ms[uu][q]);
+    double s1 = 0.0, s2 = 0.0;
+    if (uu < nu && M > -INFINITY)
+        for (int j = 0; j < 32; ++j) {
+            const double v = V[uu][seg * 32 + j];
+            if (v > -INFINITY) {
+                const double w = exp(v - M);
+                s1 += w;
+                s2 += w * w;
             }
         }
-        double* o = part + ((int64_t)(u0 + uu) * npb + blockIdx.x) * 3;
-        o[0] = M;
-        o[1] = S1;
-        o[2] = S2;
+    S1s[uu][seg] = s1;
+    S2s[uu][seg] = s2;
+    __syncthreads();
+    if (t < nu) {
+        double a = 0.0, b = 0.0, mm = -INFINITY;
+#pragma unroll
+        for (int q = 0; q < kSeg; ++q) {
+            a += S1s[t][q];
+            b += S2s[t][q];
+            mm = fmax(mm, Ms[t][q]);
+        }
+        double* o = part + ((int64_t)(u0 + t) * npb + blockIdx.x) * 3;
+        o[0] = mm;
+        o[1] = a;
+        o[2] = b;
     }
 }
 
