@@ -49,7 +49,7 @@ def gpu_bench(w, steps, warmup, seed=1):
     ctx = driver.setup(X, y, w.C, 0.0, w.prior_sd)
     prec = sps.PREC[w.precision]
     J, N, P, d, T = w.J, w.N, w.P, w.d, w.T
-    s0 = T - C_BLOCK
+    s0 = max(0, T - C_BLOCK)
     f64 = dict(dtype=torch.float64, device="cuda")
     # particle cloud at posterior scale around the generating coefficients
     th_np = synth.make_particles(P, d, scale=0.02, seed=seed, center=B.reshape(-1))
@@ -290,7 +290,7 @@ def cpu_baseline(w, seconds, seed=1):
     X, y, B = synth.make_data(w)
     J, N = 16, 32
     P, d, T = J * N, w.d, w.T
-    s0 = T - C_BLOCK
+    s0 = max(0, T - C_BLOCK)
     th0 = synth.make_particles(w.P, d, scale=0.02, seed=seed, center=B.reshape(-1))[:P]
     ll0 = O.loglik(X, y, w.C, th0, 0, s0)
     evals = 0

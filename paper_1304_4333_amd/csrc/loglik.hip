@@ -112,6 +112,12 @@ static int run_loglik(sps_ctx* c, const double* theta, int64_t P, int64_t t0, in
     const int ks = (prec == SPS_BF16X3) ? c->kb / 32 : c->kp / 4;
     LoglikEntry e = lookup(prec, c->C - 1, ks, mode);
     if (!e.fn) return fail(c, SPS_ERR_ARG, "no likelihood kernel for C=%d k=%d prec=%d", c->C, c->k, prec);
+    if (mode == MODE_FWD && (P + e.ppb - 1) / e.ppb < 64) {
+        // few particles: more, narrower waves beat operand reuse (measured at
+        // P = 1024: 13 us with one block of 16 particles per wave, 24 us with two)
+        const LoglikEntry narrow = lookup(prec, c->C - 1, ks, MODE_PEROBS);
+        if (narrow.fn) e = narrow;
+    }
     if (P == 0) return SPS_OK;
     if (t1 == t0) {
         if (ll) SPS_CHECK(fill(c, ll, P, 0.0));
