@@ -220,7 +220,7 @@ def _call_times(ctx, w, precision, reps=5):
 
 
 PREC_SOURCES = {"fp64": ("loglik_fp64.hip",), "fp32": ("loglik_fp32.hip",),
-                "bf16x3": ("loglik_bf16.hip", "loglik_bf16_wide.hip")}
+                "bf16x3": ("loglik_bf16.hip", "loglik_bf16_wide.hip", "loglik_bf16_c8.hip")}
 
 
 def kernel_digest(precision):

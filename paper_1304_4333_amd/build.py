@@ -64,6 +64,12 @@ def _compile(src: str, incremental: bool) -> str:
         return obj
     tmp = obj + ".tmp"
     r = subprocess.run([HIPCC] + _flags(src) + ["-c", src, "-o", tmp], capture_output=True, text=True)
+    if r.returncode != 0 and FILE_FLAGS.get(os.path.basename(src)):
+        # the register-assignment option has crashed this compiler on some
+        # heavily spilling instantiations: build the unit without it instead
+        sys.stderr.write(f"warning: {os.path.basename(src)} failed with {FILE_FLAGS[os.path.basename(src)]}; "
+                         "compiling it with the default options\n")
+        r = subprocess.run([HIPCC] + CFLAGS + ["-c", src, "-o", tmp], capture_output=True, text=True)
     err = "\n".join(l for l in r.stderr.splitlines() if "not a recognized feature" not in l)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed on {src}:\n{err}")

@@ -1,5 +1,6 @@
 // loglik_bf16_wide.hip -- instantiations of the likelihood kernel for
-// SPS_BF16X3 with C >= 6 outcomes (five or more outcome chains per wave).
+// SPS_BF16X3 with C = 6 or 7 outcomes (five or six outcome chains per wave);
+// C = 8 lives in loglik_bf16_c8.hip.
 #include "loglik_kernel.h"
 
 namespace sps {
@@ -16,11 +17,8 @@ LoglikEntry lookup_bf16_wide(int nc, int ks, int mode) {
     SPS_E(6, 1)
     SPS_E(6, 2)
     SPS_E(6, 4)
-    SPS_E(7, 1)
-    SPS_E(7, 2)
-    SPS_E(7, 4)
 #undef SPS_E
-    return LoglikEntry{};
+    return lookup_bf16_c8(nc, ks, mode);
 }
 
 }  // namespace sps

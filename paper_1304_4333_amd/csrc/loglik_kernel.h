@@ -68,7 +68,8 @@ struct LoglikArgs {
     const double* theta;
     double* out_ll;     // nsplit == 1: final ll[P]; else partials [nsplit][P]
     double* out_g;      // nsplit == 1: final grad[P][d]; else partials [nsplit][P][d]
-    double* perobs;     // optional: per-observation terms [(t - t0) * P + p]
+    void* perobs;       // optional: per-observation terms [(t - t0) * P + p]:
+                        // FP64 in natural log (FP64 mode), else FP32 in base 2
     int64_t P;
     int64_t Tp;
     int64_t t0, t1, t0a;  // t0a = t0 rounded down to a multiple of 32
@@ -499,7 +500,11 @@ __global__ __launch_bounds__(256) void loglik_kernel(LoglikArgs a) {
                             if constexpr (PEROBS) {
                                 const int64_t p = pbase + b * 16 + r16;
                                 if (ov && p < a.P)
-                                    a.perobs[(obs - a.t0) * a.P + p] = F64 ? (double)lp : (double)lp * kLn2;
+                                {
+                                    const int64_t at = (obs - a.t0) * a.P + p;
+                                    if constexpr (F64) ((double*)a.perobs)[at] = (double)lp;
+                                    else ((float*)a.perobs)[at] = (float)lp;
+                                }
                             }
                         }
                     }
@@ -653,6 +658,7 @@ LoglikEntry loglik_entry() {
 LoglikEntry lookup_fp64(int nc, int ks, int mode);
 LoglikEntry lookup_fp32(int nc, int ks, int mode);
 LoglikEntry lookup_bf16(int nc, int ks, int mode);
-LoglikEntry lookup_bf16_wide(int nc, int ks, int mode);  // C >= 6
+LoglikEntry lookup_bf16_wide(int nc, int ks, int mode);  // C = 6, 7
+LoglikEntry lookup_bf16_c8(int nc, int ks, int mode);    // C = 8
 
 }  // namespace sps

@@ -72,14 +72,14 @@ __global__ void init_prior_kernel(double* __restrict__ theta, int64_t P, int32_t
 // chunks of kScanChunk observations: lw[u][p] holds the per-observation term
 // on entry and log w_p(s + u + 1) on exit.
 constexpr int kScanChunk = 32;
-__global__ void correct_chunk_sum_kernel(const double* __restrict__ lw, int64_t P, int32_t nb,
+__global__ void correct_chunk_sum_kernel(const void* __restrict__ lw, int f32, int64_t P, int32_t nb,
                                          double* __restrict__ tot) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int32_t ch = blockIdx.y;
     if (p >= P) return;
     const int32_t u1 = min(nb, (ch + 1) * kScanChunk);
     double s = 0.0;
-    for (int32_t u = ch * kScanChunk; u < u1; ++u) s += lw[(int64_t)u * P + p];
+    for (int32_t u = ch * kScanChunk; u < u1; ++u) s += perobs_value(lw, f32, (int64_t)u * P + p);
     tot[(int64_t)ch * P + p] = s;
 }
 
@@ -92,7 +92,7 @@ __global__ void correct_chunk_sum_kernel(const double* __restrict__ lw, int64_t 
 // part[(u * npb + block) * 3 + {0, 1, 2}]: thread (u, segment) handles 32
 // particles in order and the 8 segments combine in order.  flags |= 1 on NaN
 // or +inf.
-__global__ __launch_bounds__(256) void correct_scan_ess_kernel(const double* __restrict__ lw,
+__global__ __launch_bounds__(256) void correct_scan_ess_kernel(const void* __restrict__ lw, int f32,
                                                                const double* __restrict__ carry,
                                                                const double* __restrict__ tot, int64_t P,
                                                                int32_t nb, double* __restrict__ part,
@@ -116,7 +116,7 @@ __global__ __launch_bounds__(256) void correct_scan_ess_kernel(const double* __r
     for (int32_t u = 0; u < nu; ++u) {
         double v = -INFINITY;
         if (pv) {
-            acc += lw[(int64_t)(u0 + u) * P + p];
+            acc += perobs_value(lw, f32, (int64_t)(u0 + u) * P + p);
             v = acc;
             bad |= isnan(acc) || acc == INFINITY;
         }
@@ -226,7 +226,7 @@ __global__ __launch_bounds__(256) void correct_find_kernel(const double* __restr
 // Running log-weight of observation u of the block for every particle, in the
 // order of correct_scan_ess_kernel: carry + chunk totals before u's chunk +
 // the terms of u's chunk up to u.  Writes log_w (and adds it to ll if add_ll).
-__global__ void correct_column_kernel(const double* __restrict__ lw, const double* __restrict__ tot,
+__global__ void correct_column_kernel(const void* __restrict__ lw, int f32, const double* __restrict__ tot,
                                       int64_t P, int32_t u, double* __restrict__ log_w,
                                       double* __restrict__ ll, int add_ll) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -234,7 +234,7 @@ __global__ void correct_column_kernel(const double* __restrict__ lw, const doubl
     const int32_t ch = u / kScanChunk;
     double acc = log_w[p];
     for (int32_t q = 0; q < ch; ++q) acc += tot[(int64_t)q * P + p];
-    for (int32_t v = ch * kScanChunk; v <= u; ++v) acc += lw[(int64_t)v * P + p];
+    for (int32_t v = ch * kScanChunk; v <= u; ++v) acc += perobs_value(lw, f32, (int64_t)v * P + p);
     log_w[p] = acc;
     if (add_ll) ll[p] += acc;
 }
@@ -645,7 +645,8 @@ extern "C" int sps_correct(sps_ctx* c, const double* theta, double* ll, int32_t 
                      sizeof(double) * (kMaxBlock + (size_t)nchmax * P + (size_t)kMaxBlock * npb * 3),
                      "C-phase ESS"));
     SPS_CHECK(zero_flags(c));
-    double* lwblk = (double*)c->corr_lw.p;
+    void* lwblk = c->corr_lw.p;  // per-observation terms: FP64, or FP32 base 2 (reduced precision)
+    const int f32 = prec != SPS_FP64;
     double* ess = (double*)c->corr_red.p;
     double* tot = ess + kMaxBlock;
     double* epart = tot + (size_t)nchmax * P;
@@ -661,9 +662,9 @@ extern "C" int sps_correct(sps_ctx* c, const double* theta, double* ll, int32_t 
         const int32_t nb = (int32_t)std::min<int64_t>(B, c->T - s);
         const unsigned nch = (unsigned)((nb + kScanChunk - 1) / kScanChunk);
         SPS_CHECK(loglik_perobs(c, theta, P, s, s + nb, prec, lwblk));
-        correct_chunk_sum_kernel<<<dim3(pg, nch), 256, 0, c->stream>>>(lwblk, P, nb, tot);
+        correct_chunk_sum_kernel<<<dim3(pg, nch), 256, 0, c->stream>>>(lwblk, f32, P, nb, tot);
         SPS_CHECK(launched(c, "correct_chunk_sum_kernel"));
-        correct_scan_ess_kernel<<<dim3(pg, nch), 256, 0, c->stream>>>(lwblk, log_w, tot, P, nb, epart, flags);
+        correct_scan_ess_kernel<<<dim3(pg, nch), 256, 0, c->stream>>>(lwblk, f32, log_w, tot, P, nb, epart, flags);
         SPS_CHECK(launched(c, "correct_scan_ess_kernel"));
         correct_ess_combine_kernel<<<(unsigned)((nb + 3) / 4), 256, 0, c->stream>>>(epart, (int32_t)npb, nb, ess);
         SPS_CHECK(launched(c, "correct_ess_combine_kernel"));
@@ -677,13 +678,13 @@ extern "C" int sps_correct(sps_ctx* c, const double* theta, double* ll, int32_t 
                         (long long)(s + nb));
         const int64_t idx = (int64_t)h[2];
         if (idx >= 0) {
-            correct_column_kernel<<<pg, 256, 0, c->stream>>>(lwblk, tot, P, (int32_t)idx, log_w, ll, 1);
+            correct_column_kernel<<<pg, 256, 0, c->stream>>>(lwblk, f32, tot, P, (int32_t)idx, log_w, ll, 1);
             SPS_CHECK(launched(c, "correct_column_kernel"));
             *t_end = s + idx + 1;
             if (ess_end) *ess_end = h[3];
             return SPS_OK;
         }
-        correct_column_kernel<<<pg, 256, 0, c->stream>>>(lwblk, tot, P, nb - 1, log_w, ll, 0);
+        correct_column_kernel<<<pg, 256, 0, c->stream>>>(lwblk, f32, tot, P, nb - 1, log_w, ll, 0);
         SPS_CHECK(launched(c, "correct_column_kernel"));
         s += nb;
         B = std::min(2 * B, kMaxBlock);

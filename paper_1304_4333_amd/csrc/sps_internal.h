@@ -130,9 +130,15 @@ inline int launched(sps_ctx* c, const char* what) {
 // Writes ll (and grad when non-null) for observations [t0, t1).
 int loglik_launch(sps_ctx* c, const double* theta, int64_t P, int64_t t0, int64_t t1,
                   int prec, double* ll, double* grad);
-// Per-observation terms l_{p,t} for t0 <= t < t1 into perobs[(t - t0) * P + p].
+// Per-observation terms l_{p,t} for t0 <= t < t1 into perobs[(t - t0) * P + p]:
+// FP64 natural-log values in SPS_FP64 mode, otherwise the kernel's FP32
+// base-2 values (read them with perobs_value).
 int loglik_perobs(sps_ctx* c, const double* theta, int64_t P, int64_t t0, int64_t t1,
-                  int prec, double* perobs);
+                  int prec, void* perobs);
+// Entry i of a per-observation buffer as an FP64 natural-log value.
+__device__ __forceinline__ double perobs_value(const void* lw, int f32, int64_t i) {
+    return f32 ? (double)((const float*)lw)[i] * 0.69314718055994530942 : ((const double*)lw)[i];
+}
 // Event pair bracketing one timed launch (no-op unless timing is enabled).
 int timing_begin(sps_ctx* c, int which, int* slot);
 int timing_end(sps_ctx* c, int slot);
