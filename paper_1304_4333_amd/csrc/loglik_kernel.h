@@ -70,6 +70,8 @@ struct LoglikArgs {
     double* out_g;      // nsplit == 1: final grad[P][d]; else partials [nsplit][P][d]
     void* perobs;       // optional: per-observation terms [(t - t0) * P + p]:
                         // FP64 in natural log (FP64 mode), else FP32 in base 2
+    double* chunk_tot;  // with perobs: per-particle total of every 32-row step,
+                        // [step * P + p], natural log, FP64, summed in a fixed order
     int64_t P;
     int64_t Tp;
     int64_t t0, t1, t0a;  // t0a = t0 rounded down to a multiple of 32
@@ -391,6 +393,9 @@ __global__ __launch_bounds__(256) void loglik_kernel(LoglikArgs a) {
         E tsum[PW];
 #pragma unroll
         for (int b = 0; b < PW; ++b) tsum[b] = E(0);
+        double csum[PW];  // per-observation mode: this lane's share of the step total
+#pragma unroll
+        for (int b = 0; b < PW; ++b) csum[b] = 0.0;
 
             auto epilogue = [&](auto set_c, auto masked_c, auto perobs_c, auto fast_c) {
                 constexpr int CS = decltype(set_c)::value;
@@ -505,6 +510,8 @@ __global__ __launch_bounds__(256) void loglik_kernel(LoglikArgs a) {
                                     if constexpr (F64) ((double*)a.perobs)[at] = (double)lp;
                                     else ((float*)a.perobs)[at] = (float)lp;
                                 }
+                                // the stored value as the scan reads it (natural log)
+                                if (ov) csum[b] += F64 ? (double)lp : (double)(float)lp * kLn2;
                             }
                         }
                     }
@@ -520,6 +527,17 @@ __global__ __launch_bounds__(256) void loglik_kernel(LoglikArgs a) {
         if (a.perobs != nullptr) {
             if (PIPE && has_next) mfma_fwd(nxt_c);
             epilogue(cur_c, bconst<true>{}, bconst<true>{}, bconst<false>{});
+            if (a.chunk_tot != nullptr) {
+                // lane group g holds rows 8g .. 8g + 7 of the step: total = ((s0 + s1) + s2) + s3
+#pragma unroll
+                for (int b = 0; b < PW; ++b) {
+                    const double v1 = __shfl(csum[b], lane + 16, 64);
+                    const double v2 = __shfl(csum[b], lane + 32, 64);
+                    const double v3 = __shfl(csum[b], lane + 48, 64);
+                    const int64_t p = pbase + b * 16 + r16;
+                    if (g == 0 && p < a.P) a.chunk_tot[(int64_t)st * a.P + p] = ((csum[b] + v1) + v2) + v3;
+                }
+            }
         } else if constexpr (FASTOK) {
             if (full && has_next) {
                 if constexpr (PIPE) mfma_fwd(nxt_c);

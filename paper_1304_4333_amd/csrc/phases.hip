@@ -68,101 +68,137 @@ __global__ void init_prior_kernel(double* __restrict__ theta, int64_t P, int32_t
 }
 
 // ------------------------------------------------------------------ C phase
-// Running log-weights over a block of observations, as a two-pass scan over
-// chunks of kScanChunk observations: lw[u][p] holds the per-observation term
-// on entry and log w_p(s + u + 1) on exit.
+// Running log-weights over a block of nb observations s .. s + nb - 1 (u =
+// observation - s).  The block is cut into chunks on the 32-aligned grid of
+// the likelihood kernel's steps: chunk q holds rows r = u + off in
+// [32 q, 32 q + 32), off = s mod 32, and the likelihood kernel writes the
+// chunk totals tot[q][p] beside the per-observation terms.  A chunk is scanned
+// as four runs of 8 rows.  The running value of particle p at u is
+//   carry[p] + tot[0][p] + ... + tot[q-1][p]        (chunk_base)
+//   + run sums of the earlier runs of the chunk      (run_sum)
+//   + the terms of u's run up to u,
+// added left to right in exactly that order by correct_scan_ess_kernel and
+// correct_column_kernel, so both produce the same bits.
 constexpr int kScanChunk = 32;
-__global__ void correct_chunk_sum_kernel(const void* __restrict__ lw, int f32, int64_t P, int32_t nb,
-                                         double* __restrict__ tot) {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int32_t ch = blockIdx.y;
-    if (p >= P) return;
-    const int32_t u1 = min(nb, (ch + 1) * kScanChunk);
-    double s = 0.0;
-    for (int32_t u = ch * kScanChunk; u < u1; ++u) s += perobs_value(lw, f32, (int64_t)u * P + p);
-    tot[(int64_t)ch * P + p] = s;
+constexpr int kScanRun = 8;
+
+__device__ __forceinline__ double chunk_base(const double* __restrict__ carry, const double* __restrict__ tot,
+                                             int64_t P, int64_t p, int32_t q) {
+    double acc = carry[p];
+#pragma unroll 8
+    for (int32_t r = 0; r < q; ++r) acc += tot[(int64_t)r * P + p];
+    return acc;
 }
 
-// Pass 2 of the scan fused with the ESS statistics.  Thread (p, chunk)
-// forms the running log-weights of its chunk from the carried value and the
-// chunk totals (nothing is written back: correct_column_kernel rebuilds the
-// one column that is needed, in the same order) and stages them in LDS.  For
-// every observation u of the chunk the block then reduces, over its 256
-// particles, m = max lw, s1 = sum exp(lw - m), s2 = sum exp(2 (lw - m)) into
-// part[(u * npb + block) * 3 + {0, 1, 2}]: thread (u, segment) handles 32
-// particles in order and the 8 segments combine in order.  flags |= 1 on NaN
-// or +inf.
+// Sum of the terms of particle p over rows u0 .. u0 + 7 that lie in [0, nb).
+__device__ __forceinline__ double run_sum(const void* __restrict__ lw, int f32, int64_t P, int64_t p,
+                                          int32_t u0, int32_t nb) {
+    double sw = 0.0;
+#pragma unroll
+    for (int j = 0; j < kScanRun; ++j) {
+        const int32_t u = u0 + j;
+        if (u >= 0 && u < nb) sw += perobs_value(lw, f32, (int64_t)u * P + p);
+    }
+    return sw;
+}
+
+__device__ __forceinline__ double wave_sum64(double v) {
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m, 64);
+    return v;
+}
+
+// One workgroup per (64 particles, chunk q); wave w scans run w (rows
+// 32 q + 8 w .. + 7), one particle per lane, and stages the running values in
+// LDS.  Then 8 threads per row reduce over the 64 particles (thread j of a row
+// takes particles j, j + 8, ...): m = max log w, s1 = sum exp(log w - m),
+// s2 = sum exp(2 (log w - m)) into part[(u * npb + block) * 3 + {0, 1, 2}]
+// (npb = workgroups per chunk).  The running value at u = nb - 1 goes to
+// carry_out (the next block's carry).  flags |= 1 on NaN or +inf.
+constexpr int kScanLds = 72;  // row stride in doubles: rows 2i and 2i + 1 fall in different LDS banks
 __global__ __launch_bounds__(256) void correct_scan_ess_kernel(const void* __restrict__ lw, int f32,
                                                                const double* __restrict__ carry,
                                                                const double* __restrict__ tot, int64_t P,
-                                                               int32_t nb, double* __restrict__ part,
-                                                               unsigned* flags) {
-    constexpr int kSeg = 256 / kScanChunk;  // particle segments per observation
-    __shared__ double V[kScanChunk][257];
-    __shared__ double Ms[kScanChunk][kSeg], S1s[kScanChunk][kSeg], S2s[kScanChunk][kSeg];
-    const int t = threadIdx.x;
-    const int64_t p = (int64_t)blockIdx.x * 256 + t;
-    const int32_t ch = blockIdx.y;
+                                                               int32_t nb, int32_t off,
+                                                               double* __restrict__ carry_out,
+                                                               double* __restrict__ part, unsigned* flags) {
+    __shared__ double S[kScanChunk / kScanRun][64];
+    __shared__ double V[kScanChunk][kScanLds];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t p = (int64_t)blockIdx.x * 64 + lane;
+    const int32_t q = blockIdx.y;
     const int32_t npb = gridDim.x;
     const bool pv = p < P;
-    double acc = 0.0;
-    if (pv) {
-        acc = carry[p];
-        for (int32_t q = 0; q < ch; ++q) acc += tot[(int64_t)q * P + p];
+    const int32_t u0 = q * kScanChunk - off + w * kScanRun;
+    double val[kScanRun];
+#pragma unroll
+    for (int j = 0; j < kScanRun; ++j) {
+        const int32_t u = u0 + j;
+        val[j] = (pv && u >= 0 && u < nb) ? perobs_value(lw, f32, (int64_t)u * P + p) : 0.0;
     }
-    const int32_t u0 = ch * kScanChunk;
-    const int32_t nu = min(nb, u0 + kScanChunk) - u0;
-    bool bad = false;
-    for (int32_t u = 0; u < nu; ++u) {
-        double v = -INFINITY;
-        if (pv) {
-            acc += perobs_value(lw, f32, (int64_t)(u0 + u) * P + p);
-            v = acc;
-            bad |= isnan(acc) || acc == INFINITY;
+    double acc = pv ? chunk_base(carry, tot, P, p, q) : 0.0;
+    {
+        double sw = 0.0;  // run_sum's arithmetic on the loaded values
+#pragma unroll
+        for (int j = 0; j < kScanRun; ++j) {
+            const int32_t u = u0 + j;
+            if (u >= 0 && u < nb) sw += val[j];
         }
-        V[u][t] = v;
+        S[w][lane] = sw;
+    }
+    __syncthreads();
+    for (int w2 = 0; w2 < w; ++w2) acc += S[w2][lane];
+    bool bad = false;
+#pragma unroll
+    for (int j = 0; j < kScanRun; ++j) {
+        const int32_t u = u0 + j;
+        double v = -INFINITY;
+        if (u >= 0 && u < nb) {
+            acc += val[j];
+            if (pv) {
+                v = acc;
+                bad |= isnan(acc) || acc == INFINITY;
+                if (u == nb - 1) carry_out[p] = acc;
+            }
+        }
+        V[w * kScanRun + j][lane] = v;
     }
     if (bad) atomicOr(flags, 1u);
     __syncthreads();
-    const int uu = t % kScanChunk, seg = t / kScanChunk;
+    const int r = threadIdx.x >> 3, sg = threadIdx.x & 7;
     double m = -INFINITY;
-    if (uu < nu)
-        for (int j = 0; j < 32; ++j) m = fmax(m, V[uu][seg * 32 + j]);
-    Ms[uu][seg] = m;
-    __syncthreads();
-    double M = -INFINITY;
 #pragma unroll
-    for (int q = 0; q < kSeg; ++q) M = fmax(M, Ms[uu][q]);
+    for (int i = 0; i < 8; ++i) m = fmax(m, V[r][sg + 8 * i]);
+#pragma unroll
+    for (int sh = 1; sh < 8; sh <<= 1) m = fmax(m, __shfl_xor(m, sh, 64));
     double s1 = 0.0, s2 = 0.0;
-    if (uu < nu && M > -INFINITY)
-        for (int j = 0; j < 32; ++j) {
-            const double v = V[uu][seg * 32 + j];
-            if (v > -INFINITY) {
-                const double w = exp(v - M);
-                s1 += w;
-                s2 += w * w;
+    if (m > -INFINITY) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const double x = V[r][sg + 8 * i];
+            if (x > -INFINITY) {
+                const double e = exp(x - m);
+                s1 += e;
+                s2 += e * e;
             }
         }
-    S1s[uu][seg] = s1;
-    S2s[uu][seg] = s2;
-    __syncthreads();
-    if (t < nu) {
-        double a = 0.0, b = 0.0, mm = -INFINITY;
+    }
 #pragma unroll
-        for (int q = 0; q < kSeg; ++q) {
-            a += S1s[t][q];
-            b += S2s[t][q];
-            mm = fmax(mm, Ms[t][q]);
-        }
-        double* o = part + ((int64_t)(u0 + t) * npb + blockIdx.x) * 3;
-        o[0] = mm;
-        o[1] = a;
-        o[2] = b;
+    for (int sh = 1; sh < 8; sh <<= 1) {
+        s1 += __shfl_xor(s1, sh, 64);
+        s2 += __shfl_xor(s2, sh, 64);
+    }
+    const int32_t u = q * kScanChunk - off + r;
+    if (sg == 0 && u >= 0 && u < nb) {
+        double* o = part + ((int64_t)u * npb + blockIdx.x) * 3;
+        o[0] = m;
+        o[1] = s1;
+        o[2] = s2;
     }
 }
 
-// ESS(u) = S1^2 / S2 from the per-block partials.  One wave per
-// observation: lane l merges blocks l, l + 64, ... in order, then the lanes
+// ESS(u) = S1^2 / S2 from the per-workgroup partials.  One wave per
+// observation: lane l merges partials l, l + 64, ... in order, then the lanes
 // merge in a fixed butterfly (the same result on every run).
 __device__ __forceinline__ void merge_ms(double& m, double& s1, double& s2, double m2, double t1, double t2) {
     const double M = fmax(m, m2);
@@ -199,42 +235,21 @@ __global__ __launch_bounds__(256) void correct_ess_combine_kernel(const double* 
     if (lane == 0) ess[u] = (m > -INFINITY) ? s1 * s1 / s2 : 0.0;
 }
 
-// First u in [0, nb) with ESS(u) < thr, or the last observation of the data.
-// out[0] = index (-1 if none), out[1] = ESS there.  One block of 256.
-__global__ __launch_bounds__(256) void correct_find_kernel(const double* __restrict__ ess, int32_t nb, double thr,
-                                                           int64_t s, int64_t T, double* out) {
-    __shared__ int32_t red[256];
-    int32_t first = INT32_MAX;
-    for (int32_t u = threadIdx.x; u < nb; u += 256)
-        if (ess[u] < thr || s + u + 1 == T) {
-            first = u;
-            break;
-        }
-    red[threadIdx.x] = first;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) red[threadIdx.x] = min(red[threadIdx.x], red[threadIdx.x + w]);
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        const int32_t f = red[0];
-        out[0] = f == INT32_MAX ? -1.0 : (double)f;
-        out[1] = f == INT32_MAX ? 0.0 : ess[f];
-    }
-}
-
-// Running log-weight of observation u of the block for every particle, in the
-// order of correct_scan_ess_kernel: carry + chunk totals before u's chunk +
-// the terms of u's chunk up to u.  Writes log_w (and adds it to ll if add_ll).
-__global__ void correct_column_kernel(const void* __restrict__ lw, int f32, const double* __restrict__ tot,
-                                      int64_t P, int32_t u, double* __restrict__ log_w,
-                                      double* __restrict__ ll, int add_ll) {
+// Running log-weight at observation u of the block for every particle, in
+// the order of correct_scan_ess_kernel.  Writes log_w (may alias carry) and
+// adds it to ll if add_ll.
+__global__ void correct_column_kernel(const void* __restrict__ lw, int f32, const double* carry,
+                                      const double* __restrict__ tot, int64_t P, int32_t nb, int32_t off,
+                                      int32_t u, double* log_w, double* __restrict__ ll, int add_ll) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= P) return;
-    const int32_t ch = u / kScanChunk;
-    double acc = log_w[p];
-    for (int32_t q = 0; q < ch; ++q) acc += tot[(int64_t)q * P + p];
-    for (int32_t v = ch * kScanChunk; v <= u; ++v) acc += perobs_value(lw, f32, (int64_t)v * P + p);
+    const int32_t r = u + off;
+    const int32_t q = r / kScanChunk, w = (r % kScanChunk) / kScanRun;
+    const int32_t c0 = q * kScanChunk - off;
+    double acc = chunk_base(carry, tot, P, p, q);
+    for (int32_t w2 = 0; w2 < w; ++w2) acc += run_sum(lw, f32, P, p, c0 + w2 * kScanRun, nb);
+    for (int32_t v = c0 + w * kScanRun; v <= u; ++v)
+        if (v >= 0) acc += perobs_value(lw, f32, (int64_t)v * P + p);
     log_w[p] = acc;
     if (add_ll) ll[p] += acc;
 }
@@ -529,11 +544,6 @@ __global__ __launch_bounds__(256) void moments_group_kernel(const double* __rest
 // out[f] = mean, out[m+f] = sd, out[2m+f] = NSE, out[3m+f] = RNE.  One wave
 // per function: lane l takes groups l, l + 64, ... (each group's sub-block
 // sums added in order), then fixed butterflies combine the lanes.
-__device__ __forceinline__ double wave_sum64(double v) {
-#pragma unroll
-    for (int sh = 32; sh > 0; sh >>= 1) v += __shfl_xor(v, sh, 64);
-    return v;
-}
 __global__ __launch_bounds__(64) void moments_final_kernel(const double* __restrict__ g,
                                                            const double* __restrict__ part, int32_t J,
                                                            int32_t N, int32_t m, int32_t nsub,
@@ -638,54 +648,64 @@ extern "C" int sps_correct(sps_ctx* c, const double* theta, double* ll, int32_t 
     // (P x block FP64) capped at 256 MiB.
     const int32_t kMaxBlock =
         (int32_t)std::max<int64_t>(kScanChunk, std::min<int64_t>(2048, (int64_t(32) << 20) / P / kScanChunk * kScanChunk));
-    const int32_t nchmax = (kMaxBlock + kScanChunk - 1) / kScanChunk;
-    const int64_t npb = (P + 255) / 256;
+    const int32_t nchmax = (kMaxBlock + 2 * kScanChunk - 1) / kScanChunk;  // chunks of a block at any alignment
+    const int64_t npb = (P + 63) / 64;  // scan workgroups per chunk
+    constexpr int kHdr = 8;             // doubles before ess: [0] = flags word
     SPS_CHECK(ensure(c, c->corr_lw, sizeof(double) * P * kMaxBlock, "C-phase block"));
     SPS_CHECK(ensure(c, c->corr_red,
-                     sizeof(double) * (kMaxBlock + (size_t)nchmax * P + (size_t)kMaxBlock * npb * 3),
+                     sizeof(double) * (kHdr + kMaxBlock + (size_t)nchmax * P + (size_t)kMaxBlock * npb * 3 + P),
                      "C-phase ESS"));
-    SPS_CHECK(zero_flags(c));
+    SPS_CHECK(ensure_host(c, c->hostbuf, sizeof(double) * (kHdr + kMaxBlock)));
     void* lwblk = c->corr_lw.p;  // per-observation terms: FP64, or FP32 base 2 (reduced precision)
     const int f32 = prec != SPS_FP64;
-    double* ess = (double*)c->corr_red.p;
+    double* hdr = (double*)c->corr_red.p;
+    unsigned* flags = (unsigned*)hdr;  // sticky: the first NaN / +inf ends the call
+    double* ess = hdr + kHdr;
     double* tot = ess + kMaxBlock;
     double* epart = tot + (size_t)nchmax * P;
-    double* res = (double*)c->small.p + 2;  // [2], [3]: index, ESS
-    unsigned* flags = (unsigned*)c->small.p;
+    double* spare = epart + (size_t)kMaxBlock * npb * 3;  // the other carry column
     const unsigned pg = (unsigned)((P + 255) / 256);
     const double thr = ess_frac * (double)P;
 
+    SPS_CHECK(fill(c, hdr, kHdr, 0.0));
     SPS_CHECK(fill(c, log_w, P, 0.0));  // w = 1 after observation s0
+    // The running log-weights carried from one block to the next alternate
+    // between log_w and spare; the final column is written into log_w.
+    double* carry = log_w;
+    double* next = spare;
     int64_t s = s0;
     int32_t B = std::min<int32_t>(64, kMaxBlock);
     for (;;) {
         const int32_t nb = (int32_t)std::min<int64_t>(B, c->T - s);
-        const unsigned nch = (unsigned)((nb + kScanChunk - 1) / kScanChunk);
-        SPS_CHECK(loglik_perobs(c, theta, P, s, s + nb, prec, lwblk));
-        correct_chunk_sum_kernel<<<dim3(pg, nch), 256, 0, c->stream>>>(lwblk, f32, P, nb, tot);
-        SPS_CHECK(launched(c, "correct_chunk_sum_kernel"));
-        correct_scan_ess_kernel<<<dim3(pg, nch), 256, 0, c->stream>>>(lwblk, f32, log_w, tot, P, nb, epart, flags);
+        const int32_t off = (int32_t)(s & (kScanChunk - 1));
+        const unsigned nch = (unsigned)((nb + off + kScanChunk - 1) / kScanChunk);
+        SPS_CHECK(loglik_perobs(c, theta, P, s, s + nb, prec, lwblk, tot));
+        correct_scan_ess_kernel<<<dim3((unsigned)npb, nch), 256, 0, c->stream>>>(lwblk, f32, carry, tot, P, nb, off,
+                                                                                 next, epart, flags);
         SPS_CHECK(launched(c, "correct_scan_ess_kernel"));
         correct_ess_combine_kernel<<<(unsigned)((nb + 3) / 4), 256, 0, c->stream>>>(epart, (int32_t)npb, nb, ess);
         SPS_CHECK(launched(c, "correct_ess_combine_kernel"));
-        correct_find_kernel<<<1, 256, 0, c->stream>>>(ess, nb, thr, s, c->T, res);
-        SPS_CHECK(launched(c, "correct_find_kernel"));
-        SPS_HIP(c, hipMemcpyAsync(c->hostbuf.p, c->small.p, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        SPS_HIP(c, hipMemcpyAsync(c->hostbuf.p, hdr, sizeof(double) * (kHdr + nb), hipMemcpyDeviceToHost, c->stream));
         SPS_HIP(c, hipStreamSynchronize(c->stream));
         const double* h = (const double*)c->hostbuf.p;
         if (*(const unsigned*)h & 1u)
             return fail(c, SPS_ERR_NONFINITE, "sps_correct: NaN or +inf log-weight before observation %lld",
                         (long long)(s + nb));
-        const int64_t idx = (int64_t)h[2];
+        // eq. (ESS_rule): the first observation with ESS below the threshold, or the last one
+        int32_t idx = -1;
+        for (int32_t u = 0; u < nb; ++u)
+            if (h[kHdr + u] < thr || s + u + 1 == c->T) {
+                idx = u;
+                break;
+            }
         if (idx >= 0) {
-            correct_column_kernel<<<pg, 256, 0, c->stream>>>(lwblk, f32, tot, P, (int32_t)idx, log_w, ll, 1);
+            correct_column_kernel<<<pg, 256, 0, c->stream>>>(lwblk, f32, carry, tot, P, nb, off, idx, log_w, ll, 1);
             SPS_CHECK(launched(c, "correct_column_kernel"));
             *t_end = s + idx + 1;
-            if (ess_end) *ess_end = h[3];
+            if (ess_end) *ess_end = h[kHdr + idx];
             return SPS_OK;
         }
-        correct_column_kernel<<<pg, 256, 0, c->stream>>>(lwblk, f32, tot, P, nb - 1, log_w, ll, 0);
-        SPS_CHECK(launched(c, "correct_column_kernel"));
+        std::swap(carry, next);
         s += nb;
         B = std::min(2 * B, kMaxBlock);
     }

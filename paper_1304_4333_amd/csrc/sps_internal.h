@@ -132,11 +132,17 @@ int loglik_launch(sps_ctx* c, const double* theta, int64_t P, int64_t t0, int64_
                   int prec, double* ll, double* grad);
 // Per-observation terms l_{p,t} for t0 <= t < t1 into perobs[(t - t0) * P + p]:
 // FP64 natural-log values in SPS_FP64 mode, otherwise the kernel's FP32
-// base-2 values (read them with perobs_value).
+// base-2 values (read them with perobs_value).  chunk_tot (optional):
+// chunk_tot[q * P + p] = sum of the terms of particle p over the observations
+// of [t0, t1) in the q-th 32-aligned row block counted from t0 rounded down to
+// a multiple of 32 (the kernel's observation steps).
 int loglik_perobs(sps_ctx* c, const double* theta, int64_t P, int64_t t0, int64_t t1,
-                  int prec, void* perobs);
-// Entry i of a per-observation buffer as an FP64 natural-log value.
+                  int prec, void* perobs, double* chunk_tot);
+// Entry i of a per-observation buffer as an FP64 natural-log value.  Not
+// contracted into a following add, so every kernel that sums these values
+// in the same order gets the same bits.
 __device__ __forceinline__ double perobs_value(const void* lw, int f32, int64_t i) {
+#pragma clang fp contract(off)
     return f32 ? (double)((const float*)lw)[i] * 0.69314718055994530942 : ((const double*)lw)[i];
 }
 // Event pair bracketing one timed launch (no-op unless timing is enabled).

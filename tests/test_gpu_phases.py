@@ -74,6 +74,31 @@ def test_correct_matches_oracle(orc, prec, C, k, J, N, s0, scale):
     assert rel_err(llg.cpu().numpy(), ll_o).max() <= tol
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("scale", [0.02, 0.01])
+def test_correct_full_size_binary30(orc, prec, scale):
+    """The C phase at the binary30 shape (16384 particles, k = 30) from
+    observation 9000 (not 32-aligned): scale 0.02 crosses the ESS threshold in
+    the fourth block (t_end 9524 in the oracle), scale 0.01 runs to T."""
+    need_gpu()
+    sps = _sps()
+    w = synth.workload("binary30")
+    X, y, B = synth.make_data(w)
+    P = w.J * w.N
+    th = synth.make_particles(P, w.k, scale=scale, seed=61, center=B.reshape(-1))
+    ll0 = synth.make_normals(P, 1, seed=62)[:, 0]
+    print(f"correct binary30 scale={scale} prec={prec}", flush=True)
+    ctx = make_ctx(X, y, 2, prior_sd=5.0)
+    llg = to_gpu(ll0.copy())
+    lw, t_end, ess = sps.sps_correct(ctx, to_gpu(th), llg, w.J, w.N, 9000, 0.5, prec)
+    lw_o, ll_o, t_o, ess_o = orc.correct(X, y, 2, th, ll0, w.J, w.N, 9000, 0.5)
+    tol = 1e-10 if prec == 0 else 1e-4
+    assert t_end == t_o
+    assert ess == pytest.approx(ess_o, rel=10 * tol)
+    assert rel_err(lw.cpu().numpy(), lw_o).max() <= tol
+    assert rel_err(llg.cpu().numpy(), ll_o).max() <= tol
+
+
 def test_correct_runs_to_T_with_equal_particles():
     need_gpu()
     import torch
