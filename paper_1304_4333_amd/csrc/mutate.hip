@@ -12,6 +12,7 @@
 namespace sps {
 
 constexpr unsigned kFlagNotPD = 1u;
+constexpr int kSmallD = 64;  // d at or below this: the matrices of the M step fit one workgroup's LDS
 
 // Sample variance in one pass, shifted by the first particle c = theta[0]
 // for stability: over each chunk of particles
@@ -201,9 +202,344 @@ __global__ __launch_bounds__(256) void gemm_abt_kernel(const double* __restrict_
     }
 }
 
+// ---------------------------------------------------------------- d <= 64
+// Partial sums of the shifted sample variance for d <= 64: one workgroup per
+// chunk of particles, staged in LDS 64 particles at a time while the next 64
+// are loaded into registers.  Thread (ty, tx) of a 16 x 16 grid owns the
+// TILE x TILE block (a, b) = (ty TILE + i, tx TILE + j); every (a, b) and
+// (b, a) run the same products in the same order (V exactly symmetric).
+template <int TILE>
+__global__ __launch_bounds__(256) void cov_partial_small_kernel(const double* __restrict__ theta, int64_t P,
+                                                                int32_t d, int64_t chunk,
+                                                                double* __restrict__ part,
+                                                                double* __restrict__ psum) {
+    constexpr int kSub = 64;
+    constexpr int kW = 16 * TILE;           // covered width: 32 or 64 parameters
+    constexpr int kPer = kSub * kW / 256;   // staged values per thread
+    __shared__ double Xs[kSub][kW + 1];
+    const int t = threadIdx.x, tx = t & 15, ty = t >> 4;
+    const int64_t pbeg = (int64_t)blockIdx.x * chunk;
+    const int64_t pend = std::min<int64_t>(P, pbeg + chunk);
+    double pre[kPer];
+    auto load = [&](int64_t p0) {
+#pragma unroll
+        for (int l = 0; l < kPer; ++l) {
+            const int e = t + 256 * l;
+            const int r = e / kW, a = e % kW;
+            const int64_t p = p0 + r;
+            pre[l] = (p < pend && a < d) ? theta[p * d + a] - theta[a] : 0.0;
+        }
+    };
+    double acc[TILE][TILE] = {};
+    double cs[TILE] = {};
+    load(pbeg);
+    for (int64_t p0 = pbeg; p0 < pend; p0 += kSub) {
+        __syncthreads();  // the previous sub-chunk has been read
+#pragma unroll
+        for (int l = 0; l < kPer; ++l) {
+            const int e = t + 256 * l;
+            Xs[e / kW][e % kW] = pre[l];
+        }
+        __syncthreads();
+        if (p0 + kSub < pend) load(p0 + kSub);
+#pragma unroll 4
+        for (int r = 0; r < kSub; ++r) {
+            double av[TILE], bv[TILE];
+#pragma unroll
+            for (int i = 0; i < TILE; ++i) av[i] = Xs[r][ty * TILE + i];
+#pragma unroll
+            for (int j = 0; j < TILE; ++j) bv[j] = Xs[r][tx * TILE + j];
+#pragma unroll
+            for (int i = 0; i < TILE; ++i) {
+                cs[i] += av[i];
+#pragma unroll
+                for (int j = 0; j < TILE; ++j) acc[i][j] += av[i] * bv[j];
+            }
+        }
+    }
+    double* out = part + (int64_t)blockIdx.x * d * d;
+#pragma unroll
+    for (int i = 0; i < TILE; ++i) {
+        const int a = ty * TILE + i;
+        if (a >= d) continue;
+#pragma unroll
+        for (int j = 0; j < TILE; ++j) {
+            const int b = tx * TILE + j;
+            if (b < d) out[(int64_t)a * d + b] = acc[i][j];
+        }
+        if (tx == 0) psum[(int64_t)blockIdx.x * d + a] = cs[i];
+    }
+}
+
+// d <= 64: right-looking Cholesky in LDS with 256 threads.  Per column j the
+// pivot's square root and reciprocal are formed by every thread (same value),
+// the column is scaled, and thread (ty, tx) of a 16 x 16 grid updates the
+// trailing entries (j + 1 + ty + 16 a, j + 1 + tx + 16 b) on or below the
+// diagonal.  A non-positive or non-finite pivot sets kFlagNotPD.
+__global__ __launch_bounds__(256) void cholesky_small_kernel(const double* __restrict__ V, int32_t d,
+                                                             double* __restrict__ L, unsigned* flags) {
+    __shared__ double A[kSmallD][kSmallD + 1];
+    const int t = threadIdx.x, tx = t & 15, ty = t >> 4;
+    for (int r = ty; r < d; r += 16)
+        for (int q = tx; q < d; q += 16) A[r][q] = (q <= r) ? V[r * d + q] : 0.0;
+    __syncthreads();
+    for (int j = 0; j < d; ++j) {
+        const double piv = A[j][j];
+        if (!(piv > 0.0) || !isfinite(piv)) {  // same value in every thread: uniform exit
+            if (t == 0) atomicOr(flags, kFlagNotPD);
+            return;
+        }
+        const double ljj = sqrt(piv);
+        const double inv = 1.0 / ljj;
+        __syncthreads();  // every thread has read the pivot
+        if (t == j) A[j][j] = ljj;
+        else if (t > j && t < d) A[t][j] *= inv;
+        __syncthreads();
+        for (int r = j + 1 + ty; r < d; r += 16) {
+            const double lr = A[r][j];
+            for (int q = j + 1 + tx; q <= r; q += 16) A[r][q] -= lr * A[q][j];
+        }
+        __syncthreads();
+    }
+    for (int r = ty; r < d; r += 16)
+        for (int q = tx; q < d; q += 16) L[r * d + q] = A[r][q];
+}
+
+// d <= 64: W = L^-1 by forward substitution, one column per thread (the
+// columns are independent), reciprocals of the diagonal formed once.
+__global__ __launch_bounds__(64) void trinv_small_kernel(const double* __restrict__ L, int32_t d,
+                                                         double* __restrict__ W, const unsigned* flags) {
+    __shared__ double Ls[kSmallD][kSmallD + 1];
+    __shared__ double Ws[kSmallD][kSmallD + 1];
+    __shared__ double rd[kSmallD];
+    if (*flags & kFlagNotPD) return;
+    const int t = threadIdx.x;
+    for (int r = 0; r < d; ++r)
+        if (t < d) {
+            Ls[r][t] = L[r * d + t];
+            Ws[r][t] = 0.0;
+        }
+    if (t < d) rd[t] = 1.0 / L[t * d + t];
+    __syncthreads();
+    if (t < d) {
+        for (int r = t; r < d; ++r) {
+            double s = (r == t) ? 1.0 : 0.0;
+            for (int q = t; q < r; ++q) s -= Ls[r][q] * Ws[q][t];
+            Ws[r][t] = s * rd[r];
+        }
+    }
+    __syncthreads();
+    for (int r = 0; r < d; ++r)
+        if (t < d) W[r * d + t] = Ws[r][t];
+}
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+// d <= 64: small contractions on the FP64 matrix cores (16 x 16 x 4).  A
+// workgroup takes 64 consecutive particles (a contiguous block in memory),
+// wave w the tile of particles 16 w .. 16 w + 15 and every 16-wide tile of
+// outputs.  Operands are staged in LDS with every load issued before the
+// first store, and the result block goes back through LDS so that
+// consecutive lanes write consecutive addresses.
+//   GM_PLAIN:    Out = Base + alpha A B^T                     (A: P x d, B: d x d)
+//   GM_MALA_FWD: u = z + L^T g(theta) / 2 -> U;  theta' = theta + L u -> Out
+//   GM_MALA_REV: w = u + L^T g(theta') / 2 -> Out (Base = U; may alias Out)
+// with g(x) = grad + the gradient of the independent normal prior,
+// -(x - mu) / sd^2.  Since theta' - theta = L u, the MALA reverse term
+// L^-1 (theta - mu(theta')) = -(u + L^T g(theta') / 2) = -w needs no inverse.
+enum { GM_PLAIN = 0, GM_MALA_FWD = 1, GM_MALA_REV = 2 };
+struct SmallGemm {
+    const double* A;     // GM_PLAIN: P x d
+    const double* B;     // GM_PLAIN: d x d
+    const double* Base;  // GM_PLAIN (may be null), GM_MALA_REV: u
+    double* Out;
+    double* U;           // GM_MALA_FWD: u out
+    const double* th;    // MALA_FWD: theta
+    const double* th2;   // MALA_REV: theta'
+    const double* g;     // MALA: likelihood gradient at theta (FWD) or theta' (REV)
+    const double* z;     // MALA_FWD: standard normals
+    const double* mu;    // prior mean and 1 / sd
+    const double* isd;
+    const double* L;     // lower factor of the proposal covariance
+    int64_t P;
+    int32_t d;
+    double alpha;        // GM_PLAIN
+};
+constexpr int kGemmRows = 64;
+constexpr int kStagePer = kGemmRows * kSmallD / 256;  // elements of a 64 x d tile per thread
+
+template <int MODE>
+__global__ __launch_bounds__(256) void gemm_small_kernel(SmallGemm g) {
+    extern __shared__ double lds[];
+    const int d = g.d;
+    const int ld = d + 1;
+    const int NT = (d + 15) / 16;   // output tiles
+    const int KS = (d + 3) / 4;     // contraction steps
+    double* As = lds;               // [64][ld]: A operand, then u, then the result block
+    double* Bs = lds + kGemmRows * ld;  // [d][ld]: B of the first contraction
+    double* B2 = Bs + d * ld;       // [d][ld]: MALA_FWD: L
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int64_t p0 = (int64_t)blockIdx.x * kGemmRows;
+    const int64_t nA = std::min<int64_t>(kGemmRows, g.P - p0) * d;  // valid elements of the block
+    const int64_t base = p0 * d;
+    // element e = t + 256 l of a tile: row e / d, column e % d (updated incrementally)
+    const int dr = 256 / d, dq = 256 % d;
+    {
+        double v0[kStagePer], v1[kStagePer];
+#pragma unroll
+        for (int l = 0; l < kStagePer; ++l) {
+            const int64_t e = t + 256 * l;
+            const bool ok = e < nA;
+            if constexpr (MODE == GM_PLAIN) {
+                v0[l] = ok ? g.A[base + e] : 0.0;
+            } else {
+                v0[l] = ok ? g.g[base + e] : 0.0;
+                v1[l] = ok ? (MODE == GM_MALA_FWD ? g.th : g.th2)[base + e] : 0.0;
+            }
+        }
+        int r = t / d, q = t % d;
+#pragma unroll
+        for (int l = 0; l < kStagePer; ++l) {
+            if (r < kGemmRows) {
+                if constexpr (MODE == GM_PLAIN) As[r * ld + q] = v0[l];
+                else As[r * ld + q] = v0[l] - (v1[l] - g.mu[q]) * g.isd[q] * g.isd[q];
+            }
+            r += dr;
+            q += dq;
+            if (q >= d) {
+                q -= d;
+                ++r;
+            }
+        }
+    }
+    {
+        const int nB = d * d;
+        double v0[kStagePer];
+#pragma unroll
+        for (int l = 0; l < kStagePer; ++l) {
+            const int e = t + 256 * l;
+            v0[l] = e < nB ? (MODE == GM_PLAIN ? g.B : g.L)[e] : 0.0;
+        }
+        int r = t / d, q = t % d;
+#pragma unroll
+        for (int l = 0; l < kStagePer; ++l) {
+            if (r < d) {
+                if constexpr (MODE == GM_PLAIN) {
+                    Bs[r * ld + q] = v0[l];
+                } else {
+                    Bs[q * ld + r] = 0.5 * v0[l];  // L^T / 2
+                    if constexpr (MODE == GM_MALA_FWD) B2[r * ld + q] = v0[l];
+                }
+            }
+            r += dr;
+            q += dq;
+            if (q >= d) {
+                q -= d;
+                ++r;
+            }
+        }
+    }
+    __syncthreads();
+    // A lane supplies A[16 w + m][4 s + kg] and B[16 n + m][4 s + kg]; result
+    // element i of tile n sits at row 16 w + kg + 4 i, column 16 n + m.
+    const int m = lane & 15, kg = lane >> 4;
+    f64x4 acc[4];
+    auto contract = [&](const double* Bm) {
+#pragma unroll
+        for (int n = 0; n < 4; ++n) acc[n] = f64x4{0, 0, 0, 0};
+        for (int s = 0; s < KS; ++s) {
+            const int q = 4 * s + kg;
+            const double a = q < d ? As[(16 * w + m) * ld + q] : 0.0;
+#pragma unroll
+            for (int n = 0; n < 4; ++n) {
+                if (n < NT) {  // uniform
+                    const int an = 16 * n + m;
+                    const double b = (q < d && an < d) ? Bm[an * ld + q] : 0.0;
+                    acc[n] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[n], 0, 0, 0);
+                }
+            }
+        }
+    };
+    contract(Bs);
+    if constexpr (MODE == GM_MALA_FWD) {
+        // u = z + acc, written out and kept in LDS as the A operand of L u
+        __syncthreads();
+#pragma unroll
+        for (int n = 0; n < 4; ++n)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int row = 16 * w + kg + 4 * i, col = 16 * n + m;
+                const int64_t p = p0 + row;
+                if (n < NT && col < d) {
+                    const double u = (p < g.P ? g.z[p * d + col] : 0.0) + acc[n][i];
+                    As[row * ld + col] = u;
+                    if (p < g.P) g.U[p * d + col] = u;
+                }
+            }
+        __syncthreads();
+        contract(B2);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int n = 0; n < 4; ++n)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int row = 16 * w + kg + 4 * i, col = 16 * n + m;
+            if (n < NT && col < d) As[row * ld + col] = acc[n][i];
+        }
+    __syncthreads();
+    const double* Bsrc = MODE == GM_MALA_FWD ? g.th : g.Base;
+    const double al = MODE == GM_PLAIN ? g.alpha : 1.0;
+    double bv[kStagePer];
+#pragma unroll
+    for (int l = 0; l < kStagePer; ++l) {
+        const int64_t e = t + 256 * l;
+        bv[l] = (Bsrc && e < nA) ? Bsrc[base + e] : 0.0;
+    }
+    int rr = t / d, qq = t % d;
+#pragma unroll
+    for (int l = 0; l < kStagePer; ++l) {
+        const int64_t e = t + 256 * l;
+        if (e < nA) g.Out[base + e] = bv[l] + al * As[rr * ld + qq];
+        rr += dr;
+        qq += dq;
+        if (qq >= d) {
+            qq -= d;
+            ++rr;
+        }
+    }
+}
+
+template <int MODE>
+static int gemm_small(sps_ctx* c, const SmallGemm& g) {
+    constexpr int KM = MODE == GM_MALA_FWD ? 2 : 1;  // B matrices staged
+    const size_t bytes = sizeof(double) * (size_t)(kGemmRows + KM * g.d) * (g.d + 1);
+    // the kernel's dynamic LDS limit (above the default for large d), set once per device
+    constexpr int kMaxDev = 64;
+    static bool attr_set[kMaxDev] = {};
+    if (c->device < 0 || c->device >= kMaxDev || !attr_set[c->device]) {
+        SPS_HIP(c, hipFuncSetAttribute(reinterpret_cast<const void*>(&gemm_small_kernel<MODE>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)(sizeof(double) * (kGemmRows + KM * kSmallD) * (kSmallD + 1))));
+        if (c->device >= 0 && c->device < kMaxDev) attr_set[c->device] = true;
+    }
+    gemm_small_kernel<MODE><<<(unsigned)((g.P + kGemmRows - 1) / kGemmRows), 256, bytes, c->stream>>>(g);
+    return launched(c, "gemm_small_kernel");
+}
+
 int gemm_abt(sps_ctx* c, const double* A, const double* B, const double* Base, double* Out,
              int64_t P, int32_t d, double alpha) {
     if (P <= 0 || d <= 0) return SPS_OK;
+    if (d <= kSmallD) {
+        SmallGemm g{};
+        g.A = A;
+        g.B = B;
+        g.Base = Base;
+        g.Out = Out;
+        g.P = P;
+        g.d = d;
+        g.alpha = alpha;
+        return gemm_small<GM_PLAIN>(c, g);
+    }
     const dim3 gg((unsigned)((P + 63) / 64), (unsigned)((d + 63) / 64));
     gemm_abt_kernel<<<gg, 256, 0, c->stream>>>(A, B, Base, Out, P, d, alpha);
     return launched(c, "gemm_abt_kernel");
@@ -306,69 +642,6 @@ __global__ __launch_bounds__(256) void accept_kernel(
     }
 }
 
-// Cholesky and triangular inverse with the matrix held in LDS (d <= 64).
-constexpr int kSmallD = 64;
-// d <= 64: right-looking Cholesky in LDS with 256 threads.  Per column j the
-// pivot's square root and reciprocal are formed by every thread (same value),
-// the column is scaled, and thread (ty, tx) of a 16 x 16 grid updates the
-// trailing entries (j + 1 + ty + 16 a, j + 1 + tx + 16 b) on or below the
-// diagonal.  A non-positive or non-finite pivot sets kFlagNotPD.
-__global__ __launch_bounds__(256) void cholesky_small_kernel(const double* __restrict__ V, int32_t d,
-                                                             double* __restrict__ L, unsigned* flags) {
-    __shared__ double A[kSmallD][kSmallD + 1];
-    const int t = threadIdx.x, tx = t & 15, ty = t >> 4;
-    for (int r = ty; r < d; r += 16)
-        for (int q = tx; q < d; q += 16) A[r][q] = (q <= r) ? V[r * d + q] : 0.0;
-    __syncthreads();
-    for (int j = 0; j < d; ++j) {
-        const double piv = A[j][j];
-        if (!(piv > 0.0) || !isfinite(piv)) {  // same value in every thread: uniform exit
-            if (t == 0) atomicOr(flags, kFlagNotPD);
-            return;
-        }
-        const double ljj = sqrt(piv);
-        const double inv = 1.0 / ljj;
-        __syncthreads();  // every thread has read the pivot
-        if (t == j) A[j][j] = ljj;
-        else if (t > j && t < d) A[t][j] *= inv;
-        __syncthreads();
-        for (int r = j + 1 + ty; r < d; r += 16) {
-            const double lr = A[r][j];
-            for (int q = j + 1 + tx; q <= r; q += 16) A[r][q] -= lr * A[q][j];
-        }
-        __syncthreads();
-    }
-    for (int r = ty; r < d; r += 16)
-        for (int q = tx; q < d; q += 16) L[r * d + q] = A[r][q];
-}
-
-// d <= 64: W = L^-1 by forward substitution, one column per thread (the
-// columns are independent), reciprocals of the diagonal formed once.
-__global__ __launch_bounds__(64) void trinv_small_kernel(const double* __restrict__ L, int32_t d,
-                                                         double* __restrict__ W, const unsigned* flags) {
-    __shared__ double Ls[kSmallD][kSmallD + 1];
-    __shared__ double Ws[kSmallD][kSmallD + 1];
-    __shared__ double rd[kSmallD];
-    if (*flags & kFlagNotPD) return;
-    const int t = threadIdx.x;
-    for (int r = 0; r < d; ++r)
-        if (t < d) {
-            Ls[r][t] = L[r * d + t];
-            Ws[r][t] = 0.0;
-        }
-    if (t < d) rd[t] = 1.0 / L[t * d + t];
-    __syncthreads();
-    if (t < d) {
-        for (int r = t; r < d; ++r) {
-            double s = (r == t) ? 1.0 : 0.0;
-            for (int q = t; q < r; ++q) s -= Ls[r][q] * Ws[q][t];
-            Ws[r][t] = s * rd[r];
-        }
-    }
-    __syncthreads();
-    for (int r = 0; r < d; ++r)
-        if (t < d) W[r * d + t] = Ws[r][t];
-}
 static inline unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 // One M step for every particle.  Sigma_in == nullptr: proposal covariance
@@ -394,10 +667,18 @@ static int mutate_launch(sps_ctx* c, const char* who, double* theta, double* ll,
     if (d > 1024) return fail(c, SPS_ERR_ARG, "%s: d=%d above 1024", who, d);
     const bool mala = kind == SPS_MALA;
     const int64_t Pd = P * d;
-    // covariance chunks: about 2048 blocks in flight, at least 64 particles each
-    const int64_t tiles = (int64_t)((d + 63) / 64) * ((d + 63) / 64);
-    const int64_t nch0 = std::max<int64_t>(1, std::min<int64_t>((2048 + tiles - 1) / tiles, (P + 63) / 64));
-    const int64_t chunk = (((P + nch0 - 1) / nch0) + 15) / 16 * 16;
+    const bool small = d <= kSmallD;
+    // covariance chunks: d <= 64: at most 64 (one workgroup sums them before
+    // the Cholesky); otherwise about 2048 blocks in flight, at least 64
+    // particles each
+    int64_t chunk;
+    if (small) {
+        chunk = 64;  // one load round per workgroup; the partials are summed by cov_final_kernel
+    } else {
+        const int64_t tiles = (int64_t)((d + 63) / 64) * ((d + 63) / 64);
+        const int64_t nch0 = std::max<int64_t>(1, std::min<int64_t>((2048 + tiles - 1) / tiles, (P + 63) / 64));
+        chunk = (((P + nch0 - 1) / nch0) + 15) / 16 * 16;
+    }
     const int32_t nchunk = (int32_t)((P + chunk - 1) / chunk);
 
     SPS_CHECK(ensure(c, c->theta2, sizeof(double) * Pd, "proposals"));
@@ -433,23 +714,44 @@ static int mutate_launch(sps_ctx* c, const char* who, double* theta, double* ll,
         u = (const double*)c->u.p;
     }
 
-    if (Sigma_in) {
-        SPS_HIP(c, hipMemcpyAsync(Sg, Sigma_in, sizeof(double) * d * d, hipMemcpyDeviceToDevice, c->stream));
+    double* part = Sigma_in ? nullptr : (double*)c->cov.p;
+    double* psum = Sigma_in ? nullptr : (double*)c->mean.p;
+    if (small) {
+        if (Sigma_in) {
+            SPS_HIP(c, hipMemcpyAsync(Sg, Sigma_in, sizeof(double) * d * d, hipMemcpyDeviceToDevice, c->stream));
+        } else {
+            if (d <= 32) cov_partial_small_kernel<2><<<nchunk, 256, 0, c->stream>>>(theta, P, d, chunk, part, psum);
+            else cov_partial_small_kernel<4><<<nchunk, 256, 0, c->stream>>>(theta, P, d, chunk, part, psum);
+            SPS_CHECK(launched(c, "cov_partial_small_kernel"));
+            cov_final_kernel<<<(unsigned)(((int64_t)d * d + 3) / 4), 256, 0, c->stream>>>(part, psum, nchunk, d,
+                                                                                          P, h, Sg);
+            SPS_CHECK(launched(c, "cov_final_kernel"));
+        }
+        cholesky_small_kernel<<<1, 256, 0, c->stream>>>(Sg, d, L, flags);
+        SPS_CHECK(launched(c, "cholesky_small_kernel"));
+        if (mala && c->prior_full) {  // the generic MALA path below uses L^-1
+            trinv_small_kernel<<<1, 64, 0, c->stream>>>(L, d, W, flags);
+            SPS_CHECK(launched(c, "trinv_small_kernel"));
+        }
     } else {
-        double* part = (double*)c->cov.p;
-        double* psum = (double*)c->mean.p;
-        cov_partial_kernel<<<dim3((d + 63) / 64, (d + 63) / 64, nchunk), 256, 0, c->stream>>>(
-            theta, P, d, chunk, part, psum);
-        SPS_CHECK(launched(c, "cov_partial_kernel"));
-        cov_final_kernel<<<(unsigned)(((int64_t)d * d + 3) / 4), 256, 0, c->stream>>>(part, psum, nchunk, d, P,
-                                                                                      h, Sg);
-        SPS_CHECK(launched(c, "cov_final_kernel"));
+        if (Sigma_in) {
+            SPS_HIP(c, hipMemcpyAsync(Sg, Sigma_in, sizeof(double) * d * d, hipMemcpyDeviceToDevice, c->stream));
+        } else {
+            cov_partial_kernel<<<dim3((d + 63) / 64, (d + 63) / 64, nchunk), 256, 0, c->stream>>>(
+                theta, P, d, chunk, part, psum);
+            SPS_CHECK(launched(c, "cov_partial_kernel"));
+            cov_final_kernel<<<(unsigned)(((int64_t)d * d + 3) / 4), 256, 0, c->stream>>>(part, psum, nchunk, d,
+                                                                                          P, h, Sg);
+            SPS_CHECK(launched(c, "cov_final_kernel"));
+        }
+        cholesky_kernel<<<1, 1024, 0, c->stream>>>(Sg, d, L, flags);
+        SPS_CHECK(launched(c, "cholesky_kernel"));
+        if (mala) {
+            trinv_kernel<<<1, 1024, 0, c->stream>>>(L, d, W, flags);
+            SPS_CHECK(launched(c, "trinv_kernel"));
+        }
     }
-    if (d <= kSmallD) cholesky_small_kernel<<<1, 256, 0, c->stream>>>(Sg, d, L, flags);
-    else cholesky_kernel<<<1, 1024, 0, c->stream>>>(Sg, d, L, flags);
-    SPS_CHECK(launched(c, "cholesky_kernel"));
 
-    const dim3 gg((unsigned)((P + 63) / 64), (unsigned)((d + 63) / 64));
     // Full prior: whitened particles r = L^-1 (theta - mean) for the prior
     // terms of log alpha and, for MALA, its gradient -L^-T r.
     double* wtmp = nullptr;
@@ -469,33 +771,54 @@ static int mutate_launch(sps_ctx* c, const char* who, double* theta, double* ll,
     };
     if (!mala) {
         // theta' = theta + L z
-        gemm_abt_kernel<<<gg, 256, 0, c->stream>>>(z, L, theta, th2, P, d, 1.0);
-        SPS_CHECK(launched(c, "gemm_abt_kernel"));
+        SPS_CHECK(gemm_abt(c, z, L, theta, th2, P, d, 1.0));
         SPS_CHECK(loglik_launch(c, th2, P, 0, t, prec, ll2, nullptr));
         if (c->prior_full) SPS_CHECK(prior_whiten(c, th2, P, wtmp, R1));
+    } else if (small && !c->prior_full) {
+        // theta' = mu(theta) + L z through u = z + L^T g(theta) / 2 (theta' = theta + L u);
+        // after the likelihood at theta', v = -(u + L^T g(theta') / 2) (only |v|^2 is used)
+        double* v = (double*)c->pstat.p;
+        double* g2 = (double*)c->grad2.p;
+        SmallGemm f{};
+        f.th = theta;
+        f.g = grad;
+        f.z = z;
+        f.mu = c->prior_mean;
+        f.isd = c->prior_isd;
+        f.L = L;
+        f.Out = th2;
+        f.U = v;
+        f.P = P;
+        f.d = d;
+        SPS_CHECK(gemm_small<GM_MALA_FWD>(c, f));
+        SPS_CHECK(loglik_launch(c, th2, P, 0, t, prec, ll2, g2));
+        SmallGemm r{};
+        r.th2 = th2;
+        r.g = g2;
+        r.mu = c->prior_mean;
+        r.isd = c->prior_isd;
+        r.L = L;
+        r.Base = v;
+        r.Out = v;
+        r.P = P;
+        r.d = d;
+        SPS_CHECK(gemm_small<GM_MALA_REV>(c, r));
     } else {
         double* gpi = (double*)c->pstat.p;
         double* work = gpi + Pd;
         double* g2 = (double*)c->grad2.p;
-        if (d <= kSmallD) trinv_small_kernel<<<1, 64, 0, c->stream>>>(L, d, W, flags);
-        else trinv_kernel<<<1, 1024, 0, c->stream>>>(L, d, W, flags);
-        SPS_CHECK(launched(c, "trinv_kernel"));
         // mu(theta) = theta + (1/2) Sigma grad log pi(theta); theta' = mu + L z
         SPS_CHECK(grad_logpost(grad, theta, R0, gpi));
-        gemm_abt_kernel<<<gg, 256, 0, c->stream>>>(gpi, Sg, theta, work, P, d, 0.5);
-        SPS_CHECK(launched(c, "gemm_abt_kernel"));
-        gemm_abt_kernel<<<gg, 256, 0, c->stream>>>(z, L, work, th2, P, d, 1.0);
-        SPS_CHECK(launched(c, "gemm_abt_kernel"));
+        SPS_CHECK(gemm_abt(c, gpi, Sg, theta, work, P, d, 0.5));
+        SPS_CHECK(gemm_abt(c, z, L, work, th2, P, d, 1.0));
         SPS_CHECK(loglik_launch(c, th2, P, 0, t, prec, ll2, g2));
         // v = L^-1 (theta - mu(theta'))
         if (c->prior_full) SPS_CHECK(prior_whiten(c, th2, P, wtmp, R1));
         SPS_CHECK(grad_logpost(g2, th2, R1, gpi));
         sub_kernel<<<nblk(Pd), 256, 0, c->stream>>>(theta, th2, work, Pd);
         SPS_CHECK(launched(c, "sub_kernel"));
-        gemm_abt_kernel<<<gg, 256, 0, c->stream>>>(gpi, Sg, work, work, P, d, -0.5);
-        SPS_CHECK(launched(c, "gemm_abt_kernel"));
-        gemm_abt_kernel<<<gg, 256, 0, c->stream>>>(work, W, nullptr, gpi, P, d, 1.0);
-        SPS_CHECK(launched(c, "gemm_abt_kernel"));
+        SPS_CHECK(gemm_abt(c, gpi, Sg, work, work, P, d, -0.5));
+        SPS_CHECK(gemm_abt(c, work, W, nullptr, gpi, P, d, 1.0));
     }
     accept_kernel<<<(unsigned)((P + kAccPerBlock - 1) / kAccPerBlock), 256, 0, c->stream>>>(
         theta, ll, grad, th2, ll2, mala ? (const double*)c->grad2.p : nullptr, z,
