@@ -107,7 +107,8 @@ static LoglikEntry lookup(int prec, int nc, int ks, int mode) {
 // Common launcher.  grad != nullptr -> forward + adjoint.  perobs != nullptr ->
 // per-observation terms written to perobs[(t - t0) * P + p] (forward only).
 static int run_loglik(sps_ctx* c, const double* theta, int64_t P, int64_t t0, int64_t t1,
-                      int prec, double* ll, double* grad, void* perobs, double* chunk_tot = nullptr) {
+                      int prec, double* ll, double* grad, void* perobs, double* chunk_tot = nullptr,
+                      const unsigned* skip = nullptr) {
     const int mode = grad ? MODE_GRAD : (perobs ? MODE_PEROBS : MODE_FWD);
     const int ks = (prec == SPS_BF16X3) ? c->kb / 32 : c->kp / 4;
     LoglikEntry e = lookup(prec, c->C - 1, ks, mode);
@@ -167,6 +168,7 @@ static int run_loglik(sps_ctx* c, const double* theta, int64_t P, int64_t t0, in
     }
     a.perobs = perobs;
     a.chunk_tot = perobs ? chunk_tot : nullptr;
+    a.skip = skip;
     dim3 grid((unsigned)(npt * nsplit));
     int slot = -1;
     SPS_CHECK(timing_begin(c, grad ? SPS_KT_LOGLIK_GRAD : (perobs ? SPS_KT_PEROBS : SPS_KT_LOGLIK), &slot));
@@ -218,8 +220,8 @@ int loglik_launch(sps_ctx* c, const double* theta, int64_t P, int64_t t0, int64_
 }
 
 int loglik_perobs(sps_ctx* c, const double* theta, int64_t P, int64_t t0, int64_t t1, int prec,
-                  void* perobs, double* chunk_tot) {
-    return run_loglik(c, theta, P, t0, t1, prec, nullptr, nullptr, perobs, chunk_tot);
+                  void* perobs, double* chunk_tot, const unsigned* skip) {
+    return run_loglik(c, theta, P, t0, t1, prec, nullptr, nullptr, perobs, chunk_tot, skip);
 }
 
 }  // namespace sps

@@ -72,6 +72,7 @@ struct LoglikArgs {
                         // FP64 in natural log (FP64 mode), else FP32 in base 2
     double* chunk_tot;  // with perobs: per-particle total of every 32-row step,
                         // [step * P + p], natural log, FP64, summed in a fixed order
+    const unsigned* skip;  // optional: the launch does nothing when *skip is nonzero
     int64_t P;
     int64_t Tp;
     int64_t t0, t1, t0a;  // t0a = t0 rounded down to a multiple of 32
@@ -196,6 +197,7 @@ __global__ __launch_bounds__(256) void loglik_kernel(LoglikArgs a) {
     // of any FP32 running sum; FP64 accumulates in registers throughout.
     constexpr int kFoldSteps = F64 ? (1 << 30) : 128;
 
+    if (a.skip != nullptr && *a.skip != 0u) return;  // the same value for every wave
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int g = lane >> 4;

@@ -830,11 +830,13 @@ static int mutate_launch(sps_ctx* c, const char* who, double* theta, double* ll,
 }
 
 // Read back `bytes` of c->small (flags, accepted count, ...) and check the flags.
-static int mutate_readback(sps_ctx* c, const char* who, int64_t P, size_t bytes, double* accept_rate) {
-    SPS_HIP(c, hipMemcpyAsync(c->hostbuf.p, c->small.p, bytes, hipMemcpyDeviceToHost, c->stream));
-    SPS_HIP(c, hipStreamSynchronize(c->stream));
-    const unsigned f = *(const unsigned*)c->hostbuf.p;
-    const unsigned long long n_acc = *(const unsigned long long*)((const char*)c->hostbuf.p + 8);
+static int mutate_readback(sps_ctx* c, const char* who, int64_t P, size_t bytes, double* accept_rate,
+                           const void** host_out = nullptr) {
+    const void* h = nullptr;
+    SPS_CHECK(readback(c, c->small.p, bytes, &h));
+    if (host_out) *host_out = h;
+    const unsigned f = *(const unsigned*)h;
+    const unsigned long long n_acc = *(const unsigned long long*)((const char*)h + 8);
     if (f & kFlagNotPD)
         return fail(c, SPS_ERR_NOT_PD, "%s: the proposal covariance is not positive definite", who);
     if (accept_rate) *accept_rate = (double)n_acc / (double)P;
@@ -916,8 +918,9 @@ extern "C" int sps_mphase(sps_ctx* c, double* theta, double* ll, double* grad, i
         double* mom = nullptr;
         SPS_CHECK(moments_launch(c, g_work, J, N, m, &mom));
         SPS_CHECK(rne_aggregate(c, mom, m, rne_rule, (double*)((char*)c->small.p + 16)));
-        SPS_CHECK(mutate_readback(c, "sps_mphase", P, 24, &rate));
-        agg = *(const double*)((const char*)c->hostbuf.p + 16);
+        const void* rec = nullptr;
+        SPS_CHECK(mutate_readback(c, "sps_mphase", P, 24, &rate, &rec));
+        agg = *(const double*)((const char*)rec + 16);
         hh = rate > acc_target ? std::min(hh + h_step, h_max) : std::max(hh - h_step, h_min);
         if (agg >= K || r >= R_max) break;
     }

@@ -121,9 +121,11 @@ __global__ __launch_bounds__(256) void correct_scan_ess_kernel(const void* __res
                                                                const double* __restrict__ tot, int64_t P,
                                                                int32_t nb, int32_t off,
                                                                double* __restrict__ carry_out,
-                                                               double* __restrict__ part, unsigned* flags) {
+                                                               double* __restrict__ part, unsigned* flags,
+                                                               const unsigned* skip) {
     __shared__ double S[kScanChunk / kScanRun][64];
     __shared__ double V[kScanChunk][kScanLds];
+    if (*skip) return;  // the same value for the whole workgroup
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t p = (int64_t)blockIdx.x * 64 + lane;
     const int32_t q = blockIdx.y;
@@ -211,10 +213,11 @@ __device__ __forceinline__ void merge_ms(double& m, double& s1, double& s2, doub
 }
 
 __global__ __launch_bounds__(256) void correct_ess_combine_kernel(const double* __restrict__ part, int32_t npb,
-                                                                  int32_t nb, double* __restrict__ ess) {
+                                                                  int32_t nb, double* __restrict__ ess,
+                                                                  const unsigned* skip) {
     const int32_t u = blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    if (u >= nb) return;
+    if (u >= nb || *skip) return;
     const double* q = part + (int64_t)u * npb * 3;
     double m = -INFINITY, s1 = 0.0, s2 = 0.0;
     for (int32_t b = lane; b < npb; b += 64) merge_ms(m, s1, s2, q[3 * b], q[3 * b + 1], q[3 * b + 2]);
@@ -233,6 +236,39 @@ __global__ __launch_bounds__(256) void correct_ess_combine_kernel(const double* 
         }
     }
     if (lane == 0) ess[u] = (m > -INFINITY) ? s1 * s1 / s2 : 0.0;
+}
+
+// C-phase header (doubles): [0] flags word (bit 0: NaN or +inf log-weight),
+// [1] done word, [2] index found, [3] ESS there.
+constexpr int kDoneWord = 2;  // the done word as an unsigned index (byte 8)
+
+// eq. (ESS_rule): the first u in [0, nb) with ESS(u) < thr, or with
+// s + u + 1 = T.  One workgroup.  hdr[2] = that u (-1 if none), hdr[3] = its
+// ESS; the done word is set when a u is found or the NaN flag is up, which
+// turns the launches of any later block into no-ops.
+__global__ __launch_bounds__(256) void correct_find_kernel(const double* __restrict__ ess, int32_t nb, double thr,
+                                                           int64_t s, int64_t T, double* hdr) {
+    __shared__ int32_t red[256];
+    unsigned* words = (unsigned*)hdr;
+    if (words[kDoneWord] != 0u) return;  // the same value for the whole workgroup
+    int32_t first = INT32_MAX;
+    for (int32_t u = threadIdx.x; u < nb; u += 256)
+        if (ess[u] < thr || s + u + 1 == T) {
+            first = u;
+            break;
+        }
+    red[threadIdx.x] = first;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] = min(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const int32_t f = red[0];
+        hdr[2] = f == INT32_MAX ? -1.0 : (double)f;
+        hdr[3] = f == INT32_MAX ? 0.0 : ess[f];
+        if (f != INT32_MAX || (words[0] & 1u)) words[kDoneWord] = 1u;
+    }
 }
 
 // Running log-weight at observation u of the block for every particle, in
@@ -579,9 +615,9 @@ __global__ __launch_bounds__(64) void moments_final_kernel(const double* __restr
 }
 
 static int read_flags(sps_ctx* c, unsigned* dflags, unsigned* out) {
-    SPS_HIP(c, hipMemcpyAsync(c->hostbuf.p, dflags, sizeof(unsigned), hipMemcpyDeviceToHost, c->stream));
-    SPS_HIP(c, hipStreamSynchronize(c->stream));
-    *out = *(unsigned*)c->hostbuf.p;
+    const void* h = nullptr;
+    SPS_CHECK(readback(c, dflags, sizeof(unsigned), &h));
+    *out = *(const unsigned*)h;
     return SPS_OK;
 }
 
@@ -655,7 +691,6 @@ extern "C" int sps_correct(sps_ctx* c, const double* theta, double* ll, int32_t 
     SPS_CHECK(ensure(c, c->corr_red,
                      sizeof(double) * (kHdr + kMaxBlock + (size_t)nchmax * P + (size_t)kMaxBlock * npb * 3 + P),
                      "C-phase ESS"));
-    SPS_CHECK(ensure_host(c, c->hostbuf, sizeof(double) * (kHdr + kMaxBlock)));
     void* lwblk = c->corr_lw.p;  // per-observation terms: FP64, or FP32 base 2 (reduced precision)
     const int f32 = prec != SPS_FP64;
     double* hdr = (double*)c->corr_red.p;
@@ -669,45 +704,71 @@ extern "C" int sps_correct(sps_ctx* c, const double* theta, double* ll, int32_t 
 
     SPS_CHECK(fill(c, hdr, kHdr, 0.0));
     SPS_CHECK(fill(c, log_w, P, 0.0));  // w = 1 after observation s0
+    const unsigned* done = (const unsigned*)hdr + kDoneWord;
+    // Blocks of observations double in size.  The host queues block i + 1
+    // before it reads block i's outcome; a block queued after the crossing
+    // (or after a NaN) finds the done word set and its launches do nothing.
     // The running log-weights carried from one block to the next alternate
     // between log_w and spare; the final column is written into log_w.
-    double* carry = log_w;
-    double* next = spare;
-    int64_t s = s0;
-    int32_t B = std::min<int32_t>(64, kMaxBlock);
-    for (;;) {
-        const int32_t nb = (int32_t)std::min<int64_t>(B, c->T - s);
-        const int32_t off = (int32_t)(s & (kScanChunk - 1));
-        const unsigned nch = (unsigned)((nb + off + kScanChunk - 1) / kScanChunk);
-        SPS_CHECK(loglik_perobs(c, theta, P, s, s + nb, prec, lwblk, tot));
-        correct_scan_ess_kernel<<<dim3((unsigned)npb, nch), 256, 0, c->stream>>>(lwblk, f32, carry, tot, P, nb, off,
-                                                                                 next, epart, flags);
+    struct Block {
+        int64_t s;
+        int32_t nb, off;
+        double* carry;
+        double* next;
+        PubTicket tk;
+    };
+    auto launch_block = [&](Block& b) -> int {
+        const unsigned nch = (unsigned)((b.nb + b.off + kScanChunk - 1) / kScanChunk);
+        SPS_CHECK(loglik_perobs(c, theta, P, b.s, b.s + b.nb, prec, lwblk, tot, done));
+        correct_scan_ess_kernel<<<dim3((unsigned)npb, nch), 256, 0, c->stream>>>(lwblk, f32, b.carry, tot, P, b.nb,
+                                                                                 b.off, b.next, epart, flags, done);
         SPS_CHECK(launched(c, "correct_scan_ess_kernel"));
-        correct_ess_combine_kernel<<<(unsigned)((nb + 3) / 4), 256, 0, c->stream>>>(epart, (int32_t)npb, nb, ess);
+        correct_ess_combine_kernel<<<(unsigned)((b.nb + 3) / 4), 256, 0, c->stream>>>(epart, (int32_t)npb, b.nb,
+                                                                                      ess, done);
         SPS_CHECK(launched(c, "correct_ess_combine_kernel"));
-        SPS_HIP(c, hipMemcpyAsync(c->hostbuf.p, hdr, sizeof(double) * (kHdr + nb), hipMemcpyDeviceToHost, c->stream));
-        SPS_HIP(c, hipStreamSynchronize(c->stream));
-        const double* h = (const double*)c->hostbuf.p;
+        correct_find_kernel<<<1, 256, 0, c->stream>>>(ess, b.nb, thr, b.s, c->T, hdr);
+        SPS_CHECK(launched(c, "correct_find_kernel"));
+        return publish_async(c, hdr, 4 * sizeof(double), &b.tk);
+    };
+    auto make_block = [&](int64_t s, int32_t B, double* carry, double* next) {
+        Block b{};
+        b.s = s;
+        b.nb = (int32_t)std::min<int64_t>(B, c->T - s);
+        b.off = (int32_t)(s & (kScanChunk - 1));
+        b.carry = carry;
+        b.next = next;
+        return b;
+    };
+    int32_t B = std::min<int32_t>(64, kMaxBlock);
+    Block cur = make_block(s0, B, log_w, spare);
+    SPS_CHECK(launch_block(cur));
+    for (;;) {
+        const int64_t s1 = cur.s + cur.nb;
+        const int32_t B1 = std::min(2 * B, kMaxBlock);
+        Block nxt{};
+        const bool ahead = s1 < c->T;
+        if (ahead) {
+            nxt = make_block(s1, B1, cur.next, cur.carry);
+            SPS_CHECK(launch_block(nxt));
+        }
+        const void* hv = nullptr;
+        SPS_CHECK(publish_wait(c, cur.tk, &hv));
+        const double* h = (const double*)hv;
         if (*(const unsigned*)h & 1u)
             return fail(c, SPS_ERR_NONFINITE, "sps_correct: NaN or +inf log-weight before observation %lld",
-                        (long long)(s + nb));
-        // eq. (ESS_rule): the first observation with ESS below the threshold, or the last one
-        int32_t idx = -1;
-        for (int32_t u = 0; u < nb; ++u)
-            if (h[kHdr + u] < thr || s + u + 1 == c->T) {
-                idx = u;
-                break;
-            }
+                        (long long)(cur.s + cur.nb));
+        const int64_t idx = (int64_t)h[2];
         if (idx >= 0) {
-            correct_column_kernel<<<pg, 256, 0, c->stream>>>(lwblk, f32, carry, tot, P, nb, off, idx, log_w, ll, 1);
+            correct_column_kernel<<<pg, 256, 0, c->stream>>>(lwblk, f32, cur.carry, tot, P, cur.nb, cur.off,
+                                                             (int32_t)idx, log_w, ll, 1);
             SPS_CHECK(launched(c, "correct_column_kernel"));
-            *t_end = s + idx + 1;
-            if (ess_end) *ess_end = h[kHdr + idx];
+            *t_end = cur.s + idx + 1;
+            if (ess_end) *ess_end = h[3];
             return SPS_OK;
         }
-        std::swap(carry, next);
-        s += nb;
-        B = std::min(2 * B, kMaxBlock);
+        if (!ahead) return fail(c, SPS_ERR_STATE, "sps_correct: no stopping point before T");  // unreachable
+        cur = nxt;
+        B = B1;
     }
 }
 
@@ -739,9 +800,9 @@ extern "C" int sps_logml(sps_ctx* c, const double* log_w, int32_t J, int32_t N, 
     SPS_CHECK(launched(c, "logml_group_kernel"));
     logml_total_kernel<<<1, 256, 0, c->stream>>>(logml_j, J, res);
     SPS_CHECK(launched(c, "logml_total_kernel"));
-    SPS_HIP(c, hipMemcpyAsync(c->hostbuf.p, c->small.p, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-    SPS_HIP(c, hipStreamSynchronize(c->stream));
-    const double* h = (const double*)c->hostbuf.p;
+    const void* hv = nullptr;
+    SPS_CHECK(readback(c, c->small.p, 4 * sizeof(double), &hv));
+    const double* h = (const double*)hv;
     const unsigned f = *(const unsigned*)h;
     if (f & 2u) return fail(c, SPS_ERR_NONFINITE, "sps_logml: NaN or +inf log-weight");
     if (f & 1u) return fail(c, SPS_ERR_DEGENERATE, "sps_logml: a group has every weight zero");
@@ -867,12 +928,11 @@ extern "C" int sps_moments(sps_ctx* c, const double* g, int32_t J, int32_t N, in
     if (J < 1 || N < 1 || m < 1 || !g) return fail(c, SPS_ERR_ARG, "sps_moments: bad arguments");
     if (J > 65535 || (N + kMomSub - 1) / kMomSub > 65535)
         return fail(c, SPS_ERR_ARG, "sps_moments: J=%d or N=%d too large for the launch grid", J, N);
-    SPS_CHECK(ensure_host(c, c->hostbuf, sizeof(double) * 4 * (size_t)m + 64));
     double* out = nullptr;
     SPS_CHECK(moments_launch(c, g, J, N, m, &out));
-    SPS_HIP(c, hipMemcpyAsync(c->hostbuf.p, out, sizeof(double) * 4 * m, hipMemcpyDeviceToHost, c->stream));
-    SPS_HIP(c, hipStreamSynchronize(c->stream));
-    const double* h = (const double*)c->hostbuf.p;
+    const void* hv = nullptr;
+    SPS_CHECK(readback(c, out, sizeof(double) * 4 * m, &hv));
+    const double* h = (const double*)hv;
     for (int32_t f = 0; f < m; ++f) {
         if (mean) mean[f] = h[f];
         if (sd) sd[f] = h[m + f];

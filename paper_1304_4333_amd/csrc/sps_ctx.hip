@@ -1,6 +1,7 @@
 // sps_ctx.hip -- context lifetime, errors, scratch, and the data/prior set-up
 // of libsps: the kernel copies of X in every precision are built once here.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -60,6 +61,85 @@ int ensure_host(sps_ctx* c, Buf& b, size_t bytes) {
     }
     b.bytes = bytes;
     return SPS_OK;
+}
+
+// ------------------------------------------------------------------ read-back
+// One wave copies n8 words into host memory; after a system-scope fence
+// (the wave's stores are complete and visible) lane 0 writes the sequence
+// number.
+__global__ __launch_bounds__(64) void publish_kernel(const unsigned long long* __restrict__ src, int64_t n8,
+                                                     unsigned long long* dst, unsigned long long* flag,
+                                                     unsigned long long seq) {
+    for (int64_t i = threadIdx.x; i < n8; i += 64) dst[i] = src[i];
+    __threadfence_system();
+    if (threadIdx.x == 0) __hip_atomic_store(flag, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// Pinned memory: kPublishSlots slots of [sequence word, padding to 64 bytes,
+// kPublishBytes of data].
+constexpr size_t kPubHeader = 64;
+constexpr size_t kPubSlot = kPubHeader + kPublishBytes;
+
+int publish_async(sps_ctx* c, const void* dsrc, size_t bytes, PubTicket* t) {
+    if (bytes > kPublishBytes) return fail(c, SPS_ERR_ARG, "read-back of %zu bytes above the slot size", bytes);
+    if (!c->pub) {
+        hipError_t e = hipHostMalloc(&c->pub, kPubSlot * kPublishSlots, hipHostMallocCoherent);
+        if (e != hipSuccess) {
+            c->pub = nullptr;
+            return hip_fail(c, e, "hipHostMalloc(read-back)");
+        }
+        c->pub_bytes = kPubSlot * kPublishSlots;
+        for (int i = 0; i < kPublishSlots; ++i) *(volatile unsigned long long*)((char*)c->pub + i * kPubSlot) = 0;
+        c->pub_seq = 0;
+    }
+    const uint64_t seq = ++c->pub_seq;
+    const int slot = (int)(seq % kPublishSlots);
+    char* base = (char*)c->pub + slot * kPubSlot;
+    publish_kernel<<<1, 64, 0, c->stream>>>((const unsigned long long*)dsrc, (int64_t)((bytes + 7) / 8),
+                                            (unsigned long long*)(base + kPubHeader), (unsigned long long*)base,
+                                            seq);
+    SPS_CHECK(launched(c, "publish_kernel"));
+    *t = PubTicket{slot, seq, dsrc, bytes};
+    return SPS_OK;
+}
+
+int publish_wait(sps_ctx* c, const PubTicket& t, const void** host) {
+    char* base = (char*)c->pub + t.slot * kPubSlot;
+    volatile unsigned long long* flag = (volatile unsigned long long*)base;
+    for (uint64_t n = 1; *flag != t.seq; ++n) {
+        if ((n & 1023) == 0) {
+            const hipError_t e = hipStreamQuery(c->stream);
+            if (e == hipSuccess) {
+                if (*flag == t.seq) break;
+                // the stream drained without the number: read it the plain way
+                SPS_CHECK(ensure_host(c, c->hostbuf, t.bytes));
+                SPS_HIP(c, hipMemcpyAsync(c->hostbuf.p, t.dsrc, t.bytes, hipMemcpyDeviceToHost, c->stream));
+                SPS_HIP(c, hipStreamSynchronize(c->stream));
+                *host = c->hostbuf.p;
+                return SPS_OK;
+            }
+            if (e != hipErrorNotReady) return hip_fail(c, e, "read-back");
+        }
+#if defined(__x86_64__)
+        __builtin_ia32_pause();
+#endif
+    }
+    std::atomic_thread_fence(std::memory_order_acquire);
+    *host = base + kPubHeader;
+    return SPS_OK;
+}
+
+int readback(sps_ctx* c, const void* dsrc, size_t bytes, const void** host) {
+    if (bytes > kPublishBytes) {
+        SPS_CHECK(ensure_host(c, c->hostbuf, bytes));
+        SPS_HIP(c, hipMemcpyAsync(c->hostbuf.p, dsrc, bytes, hipMemcpyDeviceToHost, c->stream));
+        SPS_HIP(c, hipStreamSynchronize(c->stream));
+        *host = c->hostbuf.p;
+        return SPS_OK;
+    }
+    PubTicket t;
+    SPS_CHECK(publish_async(c, dsrc, bytes, &t));
+    return publish_wait(c, t, host);
 }
 
 // Round-to-nearest-even FP32 -> BF16 bits (inputs are finite).
@@ -279,6 +359,7 @@ extern "C" void sps_destroy(sps_ctx* c) {
     for (Buf* b : bufs)
         if (b->p) (void)hipFree(b->p);
     if (c->hostbuf.p) (void)hipHostFree(c->hostbuf.p);
+    if (c->pub) (void)hipHostFree(c->pub);
     timing_release(c);
     delete c;
 }

@@ -79,6 +79,9 @@ struct sps_ctx {
     sps::Buf corr_red;   // C phase per-observation reductions
     sps::Buf small;      // small device results (status words, sums)
     sps::Buf hostbuf;    // pinned host staging for scalar read-back
+    void* pub = nullptr;       // fine-grained pinned host memory written by publish_kernel
+    size_t pub_bytes = 0;
+    uint64_t pub_seq = 0;      // sequence number of the last read-back
     sps::Buf W;          // resampling integer weights
     sps::Buf gstat;      // moments partials
     sps::Buf suff;       // multinomial sufficient statistics for one observation range
@@ -135,9 +138,10 @@ int loglik_launch(sps_ctx* c, const double* theta, int64_t P, int64_t t0, int64_
 // base-2 values (read them with perobs_value).  chunk_tot (optional):
 // chunk_tot[q * P + p] = sum of the terms of particle p over the observations
 // of [t0, t1) in the q-th 32-aligned row block counted from t0 rounded down to
-// a multiple of 32 (the kernel's observation steps).
+// a multiple of 32 (the kernel's observation steps).  skip (optional, device):
+// the launch does nothing when *skip is nonzero at the time it runs.
 int loglik_perobs(sps_ctx* c, const double* theta, int64_t P, int64_t t0, int64_t t1,
-                  int prec, void* perobs, double* chunk_tot);
+                  int prec, void* perobs, double* chunk_tot, const unsigned* skip);
 // Entry i of a per-observation buffer as an FP64 natural-log value.  Not
 // contracted into a following add, so every kernel that sums these values
 // in the same order gets the same bits.
@@ -145,6 +149,27 @@ __device__ __forceinline__ double perobs_value(const void* lw, int f32, int64_t 
 #pragma clang fp contract(off)
     return f32 ? (double)((const float*)lw)[i] * 0.69314718055994530942 : ((const double*)lw)[i];
 }
+// Reads `bytes` of device memory at dsrc into host memory once every earlier
+// launch on the context stream has finished, without a stream
+// synchronisation: a one-wave kernel copies the bytes into fine-grained
+// pinned host memory and then writes a sequence number there, on which the
+// host spins (checking the stream for errors, and falling back to a copy and
+// a synchronisation if the stream drains without the number appearing).
+// *host points at the bytes until the next read-back on the context.
+int readback(sps_ctx* c, const void* dsrc, size_t bytes, const void** host);
+// The same in two halves, for reads that overlap later launches: the copy is
+// queued now (at most kPublishBytes, up to kPublishSlots in flight) and
+// publish_wait returns its bytes, valid until kPublishSlots more publishes.
+constexpr size_t kPublishBytes = 4096;
+constexpr int kPublishSlots = 4;
+struct PubTicket {
+    int slot;
+    uint64_t seq;
+    const void* dsrc;
+    size_t bytes;
+};
+int publish_async(sps_ctx* c, const void* dsrc, size_t bytes, PubTicket* t);
+int publish_wait(sps_ctx* c, const PubTicket& t, const void** host);
 // Event pair bracketing one timed launch (no-op unless timing is enabled).
 int timing_begin(sps_ctx* c, int which, int* slot);
 int timing_end(sps_ctx* c, int slot);
