@@ -15,8 +15,13 @@
  *    "host" are host memory.  The library keeps no pointer to caller memory
  *    after a call returns, except the data and prior it copies.
  *  - Asynchrony: work is enqueued on the context's stream.  A call returns
- *    before the GPU finishes unless it has a host output; calls with host
- *    outputs synchronise the stream before returning.
+ *    before the GPU finishes unless it has a host output.  A call with host
+ *    outputs ("waits" below) returns once the stream has run everything up
+ *    to those outputs; it reads them from pinned host memory that a small
+ *    kernel fills, without a stream synchronisation, so launches queued
+ *    after that point (device outputs, empty look-ahead launches) may still
+ *    be in flight.  Device outputs are complete in stream order, as for any
+ *    launch; reading them from another stream needs an event.
  *  - Model layout: X is T x k covariates (FP64), y holds T outcomes in
  *    [0, C), outcome 0 is the base outcome whose coefficients are fixed at 0
  *    (the normalisation theta_c = 0 of Section 2.1).  A particle is the
@@ -153,7 +158,7 @@ int sps_loglik_grad(sps_ctx* ctx, const double* theta, int64_t P, int64_t t0,
  * and stop at the first s with ESS(s) < ess_frac J N (ESS pooled over all
  * J N particles) or s = T.  Outputs: log_w (device, P FP64) = log w(t_end);
  * ll (device, P FP64, in/out) += log_w; *t_end, *ess_end (host) = t_l and
- * ESS(t_l).  0 <= s0 < T, 0 < ess_frac < 1.  Synchronises. */
+ * ESS(t_l).  0 <= s0 < T, 0 < ess_frac < 1.  Waits (for t_end and ESS). */
 int sps_correct(sps_ctx* ctx, const double* theta, double* ll, int32_t J,
                 int32_t N, int64_t s0, double ess_frac, int prec,
                 double* log_w, int64_t* t_end, double* ess_end);
@@ -163,7 +168,7 @@ int sps_correct(sps_ctx* ctx, const double* theta, double* ll, int32_t J,
  * logml_j (device, J FP64, in/out) += log(N^-1 sum_n exp(log_w[j N + n])).
  * The combined estimate log(J^-1 sum_j exp(logml_j)) and its delta-method
  * NSE, sd_j(exp(logml_j - logml)) / sqrt(J), are returned in *logml, *nse
- * (host, each may be NULL).  Synchronises.  SPS_ERR_DEGENERATE if a group has
+ * (host, each may be NULL).  Waits.  SPS_ERR_DEGENERATE if a group has
  * every log_w = -inf, SPS_ERR_NONFINITE on NaN or +inf. */
 int sps_logml(sps_ctx* ctx, const double* log_w, int32_t J, int32_t N,
               double* logml_j, double* logml, double* nse);
@@ -200,8 +205,8 @@ int sps_resample_int(sps_ctx* ctx, const uint64_t* W, int32_t J, int32_t N,
  * accepted particles; accept iff log u < log alpha.  z: device P x d
  * normals, u: device P uniforms in (0, 1), or NULL for Philox draws from
  * (seed, stream) and (seed, stream + 1).  *accept_rate (host, may be NULL)
- * = accepted / P.  The call synchronises the stream (the accepted count and
- * the positive-definiteness flag are read back).  SPS_ERR_NOT_PD if V is not
+ * = accepted / P.  The call waits (the accepted count and the
+ * positive-definiteness flag are read back).  SPS_ERR_NOT_PD if V is not
  * positive definite (the failure of Section 4.2); then nothing is modified.
  * The log-likelihood of the proposal uses precision prec. */
 int sps_mutate(sps_ctx* ctx, double* theta, double* ll, double* grad, int32_t J,
@@ -262,7 +267,7 @@ int sps_monitor(sps_ctx* ctx, const double* theta, int64_t P, double* g);
 
 /* Eqs. (partial_g)-(RNE_def) for each of m functions: g device P x m FP64;
  * mean, sd, nse, rne: host, m FP64 each (any may be NULL).
- * NSE = sqrt(v_hat / (J N)).  Synchronises. */
+ * NSE = sqrt(v_hat / (J N)).  Waits. */
 int sps_moments(sps_ctx* ctx, const double* g, int32_t J, int32_t N, int32_t m,
                 double* mean, double* sd, double* nse, double* rne);
 

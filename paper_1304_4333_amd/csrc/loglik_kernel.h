@@ -395,9 +395,9 @@ __global__ __launch_bounds__(256) void loglik_kernel(LoglikArgs a) {
         E tsum[PW];
 #pragma unroll
         for (int b = 0; b < PW; ++b) tsum[b] = E(0);
-        double csum[PW];  // per-observation mode: this lane's share of the step total
+        double csum[MODE == MODE_PEROBS ? PW : 1];  // per-observation mode: this lane's share of the step total
 #pragma unroll
-        for (int b = 0; b < PW; ++b) csum[b] = 0.0;
+        for (int b = 0; b < (MODE == MODE_PEROBS ? PW : 1); ++b) csum[b] = 0.0;
 
             auto epilogue = [&](auto set_c, auto masked_c, auto perobs_c, auto fast_c) {
                 constexpr int CS = decltype(set_c)::value;
@@ -526,43 +526,54 @@ __global__ __launch_bounds__(256) void loglik_kernel(LoglikArgs a) {
 
         const bool full = (o >= a.t0) && (o + 32 <= a.t1);
         const std::integral_constant<int, NXT> nxt_c{};
-        if (a.perobs != nullptr) {
-            if (PIPE && has_next) mfma_fwd(nxt_c);
-            epilogue(cur_c, bconst<true>{}, bconst<true>{}, bconst<false>{});
-            if (a.chunk_tot != nullptr) {
-                // lane group g holds rows 8g .. 8g + 7 of the step: total = ((s0 + s1) + s2) + s3
-#pragma unroll
-                for (int b = 0; b < PW; ++b) {
-                    const double v1 = __shfl(csum[b], lane + 16, 64);
-                    const double v2 = __shfl(csum[b], lane + 32, 64);
-                    const double v3 = __shfl(csum[b], lane + 48, 64);
-                    const int64_t p = pbase + b * 16 + r16;
-                    if (g == 0 && p < a.P) a.chunk_tot[(int64_t)st * a.P + p] = ((csum[b] + v1) + v2) + v3;
+        // Non-per-observation steps; the per-observation output exists only in
+        // the MODE_PEROBS instantiation, so the other kernels carry none of it.
+        auto regular = [&]() {
+            if constexpr (FASTOK) {
+                if (full && has_next) {
+                    if constexpr (PIPE) mfma_fwd(nxt_c);
+                    epilogue(cur_c, bconst<false>{}, bconst<false>{}, bconst<true>{});
+                } else {
+                    if (PIPE && has_next) mfma_fwd(nxt_c);
+                    epilogue(cur_c, bconst<true>{}, bconst<false>{}, bconst<true>{});
                 }
-            }
-        } else if constexpr (FASTOK) {
-            if (full && has_next) {
+                if constexpr (NC == 1) {
+    #pragma unroll
+                    for (int b = 0; b < PW; ++b) bad |= !(tsum[b] > -INFINITY);  // -inf or NaN
+                }
+                if (__any(bad)) {  // wave-uniform: redo this step with the max shift
+    #pragma unroll
+                    for (int b = 0; b < PW; ++b) tsum[b] = E(0);
+                    epilogue(cur_c, bconst<true>{}, bconst<false>{}, bconst<false>{});
+                }
+            } else if (full && has_next) {
                 if constexpr (PIPE) mfma_fwd(nxt_c);
-                epilogue(cur_c, bconst<false>{}, bconst<false>{}, bconst<true>{});
+                epilogue(cur_c, bconst<false>{}, bconst<false>{}, bconst<false>{});
             } else {
                 if (PIPE && has_next) mfma_fwd(nxt_c);
-                epilogue(cur_c, bconst<true>{}, bconst<false>{}, bconst<true>{});
-            }
-            if constexpr (NC == 1) {
-#pragma unroll
-                for (int b = 0; b < PW; ++b) bad |= !(tsum[b] > -INFINITY);  // -inf or NaN
-            }
-            if (__any(bad)) {  // wave-uniform: redo this step with the max shift
-#pragma unroll
-                for (int b = 0; b < PW; ++b) tsum[b] = E(0);
                 epilogue(cur_c, bconst<true>{}, bconst<false>{}, bconst<false>{});
             }
-        } else if (full && has_next) {
-            if constexpr (PIPE) mfma_fwd(nxt_c);
-            epilogue(cur_c, bconst<false>{}, bconst<false>{}, bconst<false>{});
+        };
+        if constexpr (MODE == MODE_PEROBS) {
+            if (a.perobs != nullptr) {
+                if (PIPE && has_next) mfma_fwd(nxt_c);
+                epilogue(cur_c, bconst<true>{}, bconst<true>{}, bconst<false>{});
+                if (a.chunk_tot != nullptr) {
+                    // lane group g holds rows 8g .. 8g + 7 of the step: total = ((s0 + s1) + s2) + s3
+    #pragma unroll
+                    for (int b = 0; b < PW; ++b) {
+                        const double v1 = __shfl(csum[b], lane + 16, 64);
+                        const double v2 = __shfl(csum[b], lane + 32, 64);
+                        const double v3 = __shfl(csum[b], lane + 48, 64);
+                        const int64_t p = pbase + b * 16 + r16;
+                        if (g == 0 && p < a.P) a.chunk_tot[(int64_t)st * a.P + p] = ((csum[b] + v1) + v2) + v3;
+                    }
+                }
+            } else {
+                regular();
+            }
         } else {
-            if (PIPE && has_next) mfma_fwd(nxt_c);
-            epilogue(cur_c, bconst<true>{}, bconst<false>{}, bconst<false>{});
+            regular();
         }
 #pragma unroll
         for (int b = 0; b < PW; ++b) acc64[b] += (double)tsum[b];
