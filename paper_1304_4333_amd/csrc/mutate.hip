@@ -97,39 +97,72 @@ __global__ __launch_bounds__(256) void cov_final_kernel(const double* __restrict
     if (lane == 0) V[e] = h * ((s - sa * sb / (double)P) / (double)(P - 1));
 }
 
-// Cholesky V = L L' in one workgroup (left-looking, one column per step).
-// Sets flags |= kFlagNotPD and stops if a pivot is not positive and finite.
-__global__ __launch_bounds__(1024) void cholesky_kernel(const double* __restrict__ V, int32_t d,
-                                                        double* __restrict__ L, unsigned* flags) {
-    __shared__ double col[1024];
+// d > 64: blocked right-looking Cholesky in one workgroup of 1024 threads,
+// in place in L (which starts as the lower triangle of V).  Per panel of NB
+// columns: the panel's rows are staged in LDS, factored there column by
+// column, written back, and the trailing lower triangle is updated with the
+// panel's rank-NB product (every entry a dot product of two LDS rows).  LT
+// receives L^T.  A non-positive or non-finite pivot sets kFlagNotPD and stops.
+template <int NB, int ROWS>
+__global__ __launch_bounds__(1024) void cholesky_blocked_kernel(const double* __restrict__ V, int32_t d,
+                                                                double* __restrict__ L, double* __restrict__ LT,
+                                                                unsigned* flags) {
+    __shared__ double Pn[ROWS][NB + 1];
     __shared__ int fail_s;
     const int t = threadIdx.x;
     if (t == 0) fail_s = 0;
-    for (int64_t e = t; e < (int64_t)d * d; e += 1024) L[e] = 0.0;
+    for (int e = t; e < d * d; e += 1024) {
+        const int r = e / d, q = e % d;
+        L[e] = q <= r ? V[e] : 0.0;
+    }
     __syncthreads();
-    for (int32_t j = 0; j < d; ++j) {
-        // t_i = V[i][j] - sum_{q<j} L[i][q] L[j][q] for i >= j
-        for (int32_t i = j + t; i < d; i += 1024) {
-            double s = V[(int64_t)i * d + j];
-            const double* Li = L + (int64_t)i * d;
-            const double* Lj = L + (int64_t)j * d;
-            for (int32_t q = 0; q < j; ++q) s -= Li[q] * Lj[q];
-            col[i - j] = s;  // d <= 1024
+    for (int k = 0; k < d; k += NB) {
+        const int kw = min(NB, d - k);  // panel width
+        const int m = d - k;            // panel rows k .. d-1
+        for (int e = t; e < m * kw; e += 1024) {
+            const int i = e / kw, jj = e % kw;
+            Pn[i][jj] = L[(int64_t)(k + i) * d + k + jj];
         }
         __syncthreads();
-        const double piv = col[0];
-        if (!(piv > 0.0) || !isfinite(piv)) {
-            if (t == 0) {
-                fail_s = 1;
-                atomicOr(flags, kFlagNotPD);
+        for (int jj = 0; jj < kw; ++jj) {
+            const double piv = Pn[jj][jj];
+            if (!(piv > 0.0) || !isfinite(piv)) {  // the same value in every thread
+                if (t == 0) atomicOr(flags, kFlagNotPD);
+                return;
+            }
+            const double ljj = sqrt(piv);
+            const double inv = 1.0 / ljj;
+            __syncthreads();  // every thread has read the pivot
+            for (int i = jj + t; i < m; i += 1024) Pn[i][jj] = (i == jj) ? ljj : Pn[i][jj] * inv;
+            __syncthreads();
+            const int nc = kw - jj - 1;  // panel columns right of jj
+            if (nc > 0) {
+                for (int e = t; e < (m - jj - 1) * nc; e += 1024) {
+                    const int i = jj + 1 + e / nc, c = jj + 1 + e % nc;
+                    if (c <= i) Pn[i][c] -= Pn[i][jj] * Pn[c][jj];
+                }
+            }
+            __syncthreads();
+        }
+        for (int e = t; e < m * kw; e += 1024) {
+            const int i = e / kw, jj = e % kw;
+            L[(int64_t)(k + i) * d + k + jj] = i >= jj ? Pn[i][jj] : 0.0;
+        }
+        const int n = m - kw;  // trailing rows and columns k + kw .. d-1
+        for (int e = t; e < n * n; e += 1024) {
+            const int i = kw + e / n, c = kw + e % n;  // panel rows of the entry (r, q) = (k + i, k + c)
+            if (c <= i) {
+                double s = 0.0;
+#pragma unroll 8
+                for (int jj = 0; jj < kw; ++jj) s += Pn[i][jj] * Pn[c][jj];
+                L[(int64_t)(k + i) * d + k + c] -= s;
             }
         }
         __syncthreads();
-        if (fail_s) return;
-        const double ljj = sqrt(piv);
-        for (int32_t i = j + t; i < d; i += 1024)
-            L[(int64_t)i * d + j] = (i == j) ? ljj : col[i - j] / ljj;
-        __syncthreads();
+    }
+    for (int e = t; e < d * d; e += 1024) {
+        const int r = e / d, q = e % d;
+        LT[(int64_t)q * d + r] = L[e];
     }
 }
 
@@ -685,18 +718,19 @@ static int mutate_launch(sps_ctx* c, const char* who, double* theta, double* ll,
     SPS_CHECK(ensure(c, c->ll2, sizeof(double) * P, "proposal log-likelihoods"));
     if (mala) {
         SPS_CHECK(ensure(c, c->grad2, sizeof(double) * Pd, "proposal gradients"));
-        SPS_CHECK(ensure(c, c->pstat, sizeof(double) * 2 * Pd, "MALA work"));
+        SPS_CHECK(ensure(c, c->pstat, sizeof(double) * 3 * Pd, "MALA work"));
     }
-    SPS_CHECK(ensure(c, c->chol, sizeof(double) * 3 * (size_t)d * d, "proposal covariance"));
+    SPS_CHECK(ensure(c, c->chol, sizeof(double) * 4 * (size_t)d * d, "proposal covariance"));
     if (!Sigma_in) {
         SPS_CHECK(ensure(c, c->cov, sizeof(double) * (size_t)nchunk * d * d, "covariance partials"));
         SPS_CHECK(ensure(c, c->mean, sizeof(double) * (size_t)nchunk * d, "covariance sums"));
     }
     SPS_CHECK(ensure(c, c->small, 4096, "small"));
     SPS_CHECK(ensure_host(c, c->hostbuf, 4096));
-    double* Sg = (double*)c->chol.p;  // Sigma, then its factor and inverse
+    double* Sg = (double*)c->chol.p;  // Sigma, then its factor, its inverse and its transpose
     double* L = Sg + (size_t)d * d;
     double* W = L + (size_t)d * d;
+    double* LT = W + (size_t)d * d;
     double* th2 = (double*)c->theta2.p;
     double* ll2 = (double*)c->ll2.p;
     unsigned* flags = (unsigned*)c->small.p;
@@ -744,9 +778,10 @@ static int mutate_launch(sps_ctx* c, const char* who, double* theta, double* ll,
                                                                                           P, h, Sg);
             SPS_CHECK(launched(c, "cov_final_kernel"));
         }
-        cholesky_kernel<<<1, 1024, 0, c->stream>>>(Sg, d, L, flags);
-        SPS_CHECK(launched(c, "cholesky_kernel"));
-        if (mala) {
+        if (d <= 512) cholesky_blocked_kernel<32, 512><<<1, 1024, 0, c->stream>>>(Sg, d, L, LT, flags);
+        else cholesky_blocked_kernel<16, 1024><<<1, 1024, 0, c->stream>>>(Sg, d, L, LT, flags);
+        SPS_CHECK(launched(c, "cholesky_blocked_kernel"));
+        if (mala && c->prior_full) {  // the generic MALA path below uses L^-1
             trinv_kernel<<<1, 1024, 0, c->stream>>>(L, d, W, flags);
             SPS_CHECK(launched(c, "trinv_kernel"));
         }
@@ -803,6 +838,19 @@ static int mutate_launch(sps_ctx* c, const char* who, double* theta, double* ll,
         r.P = P;
         r.d = d;
         SPS_CHECK(gemm_small<GM_MALA_REV>(c, r));
+    } else if (!c->prior_full) {
+        // d > 64: the same u-form with FP64 VALU contractions and L^T from the factorisation:
+        // u = z + L^T g(theta) / 2, theta' = theta + L u, after the likelihood w = u + L^T g(theta') / 2
+        double* v = (double*)c->pstat.p;
+        double* uu = v + Pd;
+        double* gpi = uu + Pd;
+        double* g2 = (double*)c->grad2.p;
+        SPS_CHECK(grad_logpost(grad, theta, R0, gpi));
+        SPS_CHECK(gemm_abt(c, gpi, LT, z, uu, P, d, 0.5));
+        SPS_CHECK(gemm_abt(c, uu, L, theta, th2, P, d, 1.0));
+        SPS_CHECK(loglik_launch(c, th2, P, 0, t, prec, ll2, g2));
+        SPS_CHECK(grad_logpost(g2, th2, R1, gpi));
+        SPS_CHECK(gemm_abt(c, gpi, LT, uu, v, P, d, 0.5));
     } else {
         double* gpi = (double*)c->pstat.p;
         double* work = gpi + Pd;

@@ -199,7 +199,7 @@ def test_resample_errors():
 @pytest.mark.parametrize("kind", [0, 1])
 @pytest.mark.parametrize("prec", [0, 1, 2])
 @pytest.mark.parametrize("C,k,J,N,t", [(2, 5, 4, 256, 400), (3, 10, 4, 200, 777), (2, 30, 16, 128, 2000),
-                                         (3, 20, 3, 100, 900), (2, 80, 4, 64, 500)])
+                                         (3, 20, 3, 100, 900), (2, 80, 4, 64, 500), (3, 65, 2, 200, 700)])
 def test_mutate_matches_oracle(orc, kind, prec, C, k, J, N, t):
     need_gpu()
     sps = _sps()
