@@ -264,7 +264,7 @@ __global__ __launch_bounds__(256) void loglik_kernel(LoglikArgs a) {
     double* const g_out = GRAD ? a.out_g + (int64_t)split * a.P * a.d : nullptr;
     bool g_first = true;
     // Add the FP32/FP64 adjoint tiles into the wave's slice of the output.
-    auto fold = [&]() {
+    auto fold = [&]() __attribute__((always_inline)) {
         if constexpr (GRAD) {
 #pragma unroll
             for (int b = 0; b < PW; ++b) {
@@ -305,7 +305,7 @@ __global__ __launch_bounds__(256) void loglik_kernel(LoglikArgs a) {
     AReg ah[NSET][2][KS];                       // [set][tile][k-step]
     AReg al[NSET][BF ? 2 : 1][BF ? KS : 1];
     Acc acc[NSET][2][PW][NC];                   // [set][tile][block][outcome]
-    auto load_a = [&](auto set_c, int64_t o) {
+    auto load_a = [&](auto set_c, int64_t o) __attribute__((always_inline)) {
         constexpr int S_ = decltype(set_c)::value;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
@@ -326,7 +326,7 @@ __global__ __launch_bounds__(256) void loglik_kernel(LoglikArgs a) {
         }
     };
     // forward contraction of one step into set S_, independent chains interleaved
-    auto mfma_fwd = [&](auto set_c) {
+    auto mfma_fwd = [&](auto set_c) __attribute__((always_inline)) {
         constexpr int S_ = decltype(set_c)::value;
 #pragma unroll
         for (int h = 0; h < 2; ++h)
@@ -354,7 +354,12 @@ __global__ __launch_bounds__(256) void loglik_kernel(LoglikArgs a) {
 
     // One step: epilogue (and adjoint) of step st from set CUR, overlapped
     // with the forward MFMAs of step st + 1 into the other set.
-    auto body = [&](auto cur_c, int st, bool has_next) {
+    // interior_c: the step is known to lie inside [t0, t1) with a successor,
+    // so the unmasked epilogue is chosen at compile time (given one body with
+    // both epilogues behind a runtime test, the compiler merges them into one
+    // path that pays the masking selects on every step).
+    auto body = [&](auto cur_c, int st, bool has_next, auto interior_c) __attribute__((always_inline)) {
+        constexpr bool INTERIOR = decltype(interior_c)::value;
         constexpr int CUR = decltype(cur_c)::value;
         constexpr int NXT = PIPE ? 1 - CUR : CUR;
         const int64_t o = a.t0a + (int64_t)st * 32;
@@ -399,7 +404,7 @@ __global__ __launch_bounds__(256) void loglik_kernel(LoglikArgs a) {
 #pragma unroll
         for (int b = 0; b < (MODE == MODE_PEROBS ? PW : 1); ++b) csum[b] = 0.0;
 
-            auto epilogue = [&](auto set_c, auto masked_c, auto perobs_c, auto fast_c) {
+            auto epilogue = [&](auto set_c, auto masked_c, auto perobs_c, auto fast_c) __attribute__((always_inline)) {
                 constexpr int CS = decltype(set_c)::value;
                 constexpr bool MASKED = decltype(masked_c)::value;
                 constexpr bool PEROBS = decltype(perobs_c)::value;
@@ -528,9 +533,9 @@ __global__ __launch_bounds__(256) void loglik_kernel(LoglikArgs a) {
         const std::integral_constant<int, NXT> nxt_c{};
         // Non-per-observation steps; the per-observation output exists only in
         // the MODE_PEROBS instantiation, so the other kernels carry none of it.
-        auto regular = [&]() {
+        auto regular = [&]() __attribute__((always_inline)) {
             if constexpr (FASTOK) {
-                if (full && has_next) {
+                if (INTERIOR || (full && has_next)) {
                     if constexpr (PIPE) mfma_fwd(nxt_c);
                     epilogue(cur_c, bconst<false>{}, bconst<false>{}, bconst<true>{});
                 } else {
@@ -546,7 +551,7 @@ __global__ __launch_bounds__(256) void loglik_kernel(LoglikArgs a) {
                     for (int b = 0; b < PW; ++b) tsum[b] = E(0);
                     epilogue(cur_c, bconst<true>{}, bconst<false>{}, bconst<false>{});
                 }
-            } else if (full && has_next) {
+            } else if (INTERIOR || (full && has_next)) {
                 if constexpr (PIPE) mfma_fwd(nxt_c);
                 epilogue(cur_c, bconst<false>{}, bconst<false>{}, bconst<false>{});
             } else {
@@ -626,12 +631,20 @@ __global__ __launch_bounds__(256) void loglik_kernel(LoglikArgs a) {
             if (st_begin + 1 < st_end) load_a(set1, a.t0a + (int64_t)(st_begin + 1) * 32);
             mfma_fwd(set0);
             for (int st = st_begin; st < st_end; st += 2) {
-                body(set0, st, st + 1 < st_end);
+                body(set0, st, st + 1 < st_end, bconst<false>{});
                 if (st + 1 >= st_end) break;
-                body(set1, st + 1, st + 2 < st_end);
+                body(set1, st + 1, st + 2 < st_end, bconst<false>{});
             }
         } else {
-            for (int st = st_begin; st < st_end; ++st) body(set0, st, st + 1 < st_end);
+            // steps whose 32 rows all lie in [t0, t1) and that have a successor run
+            // a body without the masked epilogue; the others (at most one at each
+            // end of the split) run the general body
+            const int lo = max(st_begin, a.t0 > a.t0a ? 1 : 0);
+            const int hi = min(st_end - 1, (int)((a.t1 - a.t0a) / 32));
+            int st = st_begin;
+            for (; st < st_end && st < lo; ++st) body(set0, st, st + 1 < st_end, bconst<false>{});
+            for (; st < hi; ++st) body(set0, st, true, bconst<true>{});
+            for (; st < st_end; ++st) body(set0, st, st + 1 < st_end, bconst<false>{});
         }
     }
     if constexpr (GRAD) {
