@@ -155,10 +155,11 @@ struct Shape {
     // Workgroups per launch the observation split aims at.  Measured: the
     // FP32/BF16 kernels run fastest with few, long workgroups (about one or
     // two waves per SIMD; fewer split partials and prologues), the gradient
-    // kernels with 256, the forward with 512, C > 2 with 1024.  FP64 and the
-    // per-observation launches keep more workgroups for latency hiding.
+    // kernels with 256, the forward with 512, C > 2 gradients with 1024.  FP64,
+    // the C > 2 forward kernels (multi4: 350 us at 2048 against 367 us at 1024)
+    // and the per-observation launches keep more workgroups for latency hiding.
     static constexpr int TARGET =
-        (PREC == SPS_FP64 || MODE == MODE_PEROBS) ? 2048
+        (PREC == SPS_FP64 || MODE == MODE_PEROBS || (NC > 1 && MODE == MODE_FWD)) ? 2048
         : NC > 1 ? 1024 : (MODE == MODE_GRAD ? 256 : 512);
 };
 

@@ -76,6 +76,36 @@ def test_loglik_grad_matches_oracle(orc, prec, case):
     assert np.allclose(ll, ll2, rtol=TOL[prec], atol=TOL[prec])
 
 
+# observation ranges at the edges of the kernel's 32-row steps: inside one step,
+# exactly one or two aligned steps, a ragged pair, single observations
+EDGE_RANGES = [(5, 20), (0, 32), (0, 64), (31, 33), (32, 96), (17, 81), (0, 1), (63, 64), (40, 200)]
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+@pytest.mark.parametrize("C", [2, 3])
+def test_loglik_step_edges(orc, prec, C):
+    """Forward and adjoint on ranges whose steps are all edge steps, or
+    interior steps bounded by edge steps (the two step bodies of the kernel)."""
+    need_gpu()
+    from paper_1304_4333_amd import sps
+    k, T, P = 10, 200, 100
+    X, y, _ = dataset(T, k, C, seed=300 + C)
+    d = k * (C - 1)
+    th = _theta(P, d, seed=31 + C, scale=2.0 / np.sqrt(k))
+    ctx = make_ctx(X, y, C)
+    thg = to_gpu(th)
+    for t0, t1 in EDGE_RANGES:
+        print(f"edges C={C} prec={prec} [{t0},{t1})", flush=True)
+        ll = sps.sps_loglik(ctx, thg, t0, t1, prec).cpu().numpy()
+        llg, g = sps.sps_loglik_grad(ctx, thg, t0, t1, prec)
+        ref_ll, ref_g = orc.loglik(X, y, C, th, t0, t1, grad=True)
+        assert rel_err(ll, ref_ll).max() <= TOL[prec], (t0, t1)
+        assert rel_err(llg.cpu().numpy(), ref_ll).max() <= TOL[prec], (t0, t1)
+        g = g.cpu().numpy()
+        nrm = np.linalg.norm(g - ref_g, axis=1) / np.maximum(1.0, np.linalg.norm(ref_g, axis=1))
+        assert nrm.max() <= GTOL[prec], (t0, t1, nrm.max())
+
+
 def test_loglik_large_predictors(orc):
     """Prior draws with |eta| ~ 10^2: no overflow in any precision."""
     need_gpu()
