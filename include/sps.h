@@ -190,8 +190,8 @@ int sps_resample(sps_ctx* ctx, const double* log_w, int32_t J, int32_t N,
 
 /* The S phase on given integer weights W (device, J x N uint64, each group's
  * total in (0, 2^52)); the bit-exactness entry point of sps_resample. */
-int sps_resample_int(sps_ctx* ctx, const uint64_t* W, int32_t J, int32_t N,
-                     int scheme, const uint64_t* u53, int32_t* ancestor);
+int sps_resample_fixed(sps_ctx* ctx, const uint64_t* W, int32_t J, int32_t N,
+                       int scheme, const uint64_t* u53, int32_t* ancestor);
 
 /* M phase, one Metropolis step for every particle (Algorithm 2 step 2(c)):
  * V = sample variance of all J N particles (divisor P - 1), L = chol(V),

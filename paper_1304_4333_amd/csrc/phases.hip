@@ -860,12 +860,12 @@ extern "C" int sps_resample(sps_ctx* c, const double* log_w, int32_t J, int32_t 
     return SPS_OK;
 }
 
-extern "C" int sps_resample_int(sps_ctx* c, const uint64_t* W, int32_t J, int32_t N, int scheme,
+extern "C" int sps_resample_fixed(sps_ctx* c, const uint64_t* W, int32_t J, int32_t N, int scheme,
                                 const uint64_t* u53, int32_t* ancestor) {
     if (!c) return SPS_ERR_ARG;
     c->err.clear();
-    if (!W) return fail(c, SPS_ERR_ARG, "sps_resample_int: null W");
-    return resample_common(c, nullptr, W, J, N, scheme, u53, ancestor, "sps_resample_int");
+    if (!W) return fail(c, SPS_ERR_ARG, "sps_resample_fixed: null W");
+    return resample_common(c, nullptr, W, J, N, scheme, u53, ancestor, "sps_resample_fixed");
 }
 
 namespace sps {

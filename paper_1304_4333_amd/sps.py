@@ -54,7 +54,7 @@ _SIGS = {
     "sps_logml": [_vp, _vp, _i32, _i32, _vp, ct.POINTER(_dbl), ct.POINTER(_dbl)],
     "sps_resample": [_vp, _vp, _i32, _i32, ct.c_int, _vp, _u64, _u64, _vp, _vp, _vp, _vp, _vp,
                      _vp, _vp],
-    "sps_resample_int": [_vp, _vp, _i32, _i32, ct.c_int, _vp, _vp],
+    "sps_resample_fixed": [_vp, _vp, _i32, _i32, ct.c_int, _vp, _vp],
     "sps_mutate": [_vp, _vp, _vp, _vp, _i32, _i32, _i64, _dbl, ct.c_int, ct.c_int, _vp, _vp,
                    _u64, _u64, ct.POINTER(_dbl)],
     "sps_monitor": [_vp, _vp, _i64, _vp],
@@ -285,7 +285,7 @@ def sps_resample(ctx: Context, log_w: torch.Tensor, J: int, N: int, scheme: int,
     return ancestor
 
 
-def sps_resample_int(ctx: Context, W: torch.Tensor, J: int, N: int, scheme: int,
+def sps_resample_fixed(ctx: Context, W: torch.Tensor, J: int, N: int, scheme: int,
                      u53: torch.Tensor, ancestor: Optional[torch.Tensor] = None) -> torch.Tensor:
     P = J * N
     ctx._t(W, torch.uint64, (P,), "W")
@@ -293,7 +293,7 @@ def sps_resample_int(ctx: Context, W: torch.Tensor, J: int, N: int, scheme: int,
     if ancestor is None:
         ancestor = torch.empty(P, dtype=torch.int32, device=ctx.device)
     ctx._t(ancestor, torch.int32, (P,), "ancestor")
-    ctx.check(lib().sps_resample_int(ctx.handle, _ptr(W), J, N, scheme, _ptr(u53), _ptr(ancestor)))
+    ctx.check(lib().sps_resample_fixed(ctx.handle, _ptr(W), J, N, scheme, _ptr(u53), _ptr(ancestor)))
     return ancestor
 
 

@@ -137,14 +137,14 @@ def test_logml_matches_oracle(orc):
 # ------------------------------------------------------------------ S phase
 @pytest.mark.parametrize("scheme", [0, 1])
 @pytest.mark.parametrize("J,N", [(1, 1), (3, 7), (16, 1024), (2, 4096), (5, 1000)])
-def test_resample_int_bit_exact(orc, scheme, J, N):
+def test_resample_fixed_bit_exact(orc, scheme, J, N):
     need_gpu()
     sps = _sps()
     X, y, _ = dataset(20, 2, 2, seed=9)
     ctx = make_ctx(X, y, 2)
     W = synth.make_int_weights(J, N, seed=J + N)
     U = synth.make_u53(J * N, seed=N)
-    anc = sps.sps_resample_int(ctx, to_gpu(W), J, N, scheme, to_gpu(U)).cpu().numpy()
+    anc = sps.sps_resample_fixed(ctx, to_gpu(W), J, N, scheme, to_gpu(U)).cpu().numpy()
     assert np.array_equal(anc, orc.resample_int(W, J, N, scheme, U))
 
 
