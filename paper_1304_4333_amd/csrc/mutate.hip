@@ -396,6 +396,9 @@ struct SmallGemm {
     int64_t P;
     int32_t d;
     double alpha;        // GM_PLAIN
+    int32_t zgen;        // GM_PLAIN (A = z) and GM_MALA_FWD: draw z from Philox (seed, zstream)
+    uint64_t seed;
+    uint64_t zstream;
 };
 constexpr int kGemmRows = 64;
 constexpr int kStagePer = kGemmRows * kSmallD / 256;  // elements of a 64 x d tile per thread
@@ -423,7 +426,7 @@ __global__ __launch_bounds__(256) void gemm_small_kernel(SmallGemm g) {
             const int64_t e = t + 256 * l;
             const bool ok = e < nA;
             if constexpr (MODE == GM_PLAIN) {
-                v0[l] = ok ? g.A[base + e] : 0.0;
+                v0[l] = (ok && !g.zgen) ? g.A[base + e] : 0.0;
             } else {
                 v0[l] = ok ? g.g[base + e] : 0.0;
                 v1[l] = ok ? (MODE == GM_MALA_FWD ? g.th : g.th2)[base + e] : 0.0;
@@ -433,8 +436,12 @@ __global__ __launch_bounds__(256) void gemm_small_kernel(SmallGemm g) {
 #pragma unroll
         for (int l = 0; l < kStagePer; ++l) {
             if (r < kGemmRows) {
-                if constexpr (MODE == GM_PLAIN) As[r * ld + q] = v0[l];
-                else As[r * ld + q] = v0[l] - (v1[l] - g.mu[q]) * g.isd[q] * g.isd[q];
+                if constexpr (MODE == GM_PLAIN) {
+                    As[r * ld + q] = !g.zgen ? v0[l]
+                                   : (p0 + r < g.P ? philox_normal(g.seed, g.zstream, p0 + r, q, d) : 0.0);
+                } else {
+                    As[r * ld + q] = v0[l] - (v1[l] - g.mu[q]) * g.isd[q] * g.isd[q];
+                }
             }
             r += dr;
             q += dq;
@@ -503,7 +510,9 @@ __global__ __launch_bounds__(256) void gemm_small_kernel(SmallGemm g) {
                 const int row = 16 * w + kg + 4 * i, col = 16 * n + m;
                 const int64_t p = p0 + row;
                 if (n < NT && col < d) {
-                    const double u = (p < g.P ? g.z[p * d + col] : 0.0) + acc[n][i];
+                    const double zz = p >= g.P ? 0.0
+                                    : (g.zgen ? philox_normal(g.seed, g.zstream, p, col, d) : g.z[p * d + col]);
+                    const double u = zz + acc[n][i];
                     As[row * ld + col] = u;
                     if (p < g.P) g.U[p * d + col] = u;
                 }
@@ -618,6 +627,8 @@ __global__ void sub_kernel(const double* __restrict__ a, const double* __restric
 // The prior terms use the whitened particles w0, w1 when given (full prior),
 // else (theta - mu) / sd.  Sums over the 16 lanes are fixed butterflies.
 // Accepted particles are counted per workgroup and added with one atomic.
+// z / u null: the normals (MALA) and uniforms are drawn here from Philox
+// streams zstream / zstream + 1 (the values sps_random gives).
 constexpr int kAccLanes = 16;
 constexpr int kAccPerBlock = 256 / kAccLanes;
 __device__ __forceinline__ double sum16(double v) {
@@ -631,7 +642,8 @@ __global__ __launch_bounds__(256) void accept_kernel(
     const double* __restrict__ grad2, const double* __restrict__ z, const double* __restrict__ v,
     const double* __restrict__ u, const double* __restrict__ mu, const double* __restrict__ isd,
     const double* __restrict__ w0, const double* __restrict__ w1,
-    int64_t P, int32_t d, int mala, const unsigned* flags, unsigned long long* count) {
+    int64_t P, int32_t d, int mala, const unsigned* flags, unsigned long long* count,
+    uint64_t seed, uint64_t zstream) {
     __shared__ unsigned nacc[256 / kAccLanes];
     const int sub = threadIdx.x & (kAccLanes - 1);
     const int slot = threadIdx.x / kAccLanes;
@@ -649,7 +661,8 @@ __global__ __launch_bounds__(256) void accept_kernel(
             q1 += zb * zb;
             if (mala) {
                 vv += v[p * d + i] * v[p * d + i];
-                zz += z[p * d + i] * z[p * d + i];
+                const double zi = z ? z[p * d + i] : philox_normal(seed, zstream, p, i, d);
+                zz += zi * zi;
             }
         }
         q0 = sum16(q0);
@@ -657,7 +670,15 @@ __global__ __launch_bounds__(256) void accept_kernel(
         double la = (ll2[p] - 0.5 * q1) - (ll[p] - 0.5 * q0);
         if (mala) la += -0.5 * sum16(vv) + 0.5 * sum16(zz);
         if (isnan(la)) la = -INFINITY;
-        if (log(u[p]) < la) {
+        double up;
+        if (u) {
+            up = u[p];
+        } else {  // the uniform of stream zstream + 1, as sps_random kind 1
+            uint64_t ua, ub;
+            philox_u53x2(seed, zstream + 1, (uint64_t)p, ua, ub);
+            up = u53_to_uniform(ua);
+        }
+        if (log(up) < la) {
             for (int32_t i = sub; i < d; i += kAccLanes) {
                 theta[p * d + i] = b[i];
                 if (mala) grad[p * d + i] = grad2[p * d + i];
@@ -737,15 +758,15 @@ static int mutate_launch(sps_ctx* c, const char* who, double* theta, double* ll,
     unsigned long long* count = (unsigned long long*)((char*)c->small.p + 8);
     SPS_CHECK(fill(c, (double*)c->small.p, 2, 0.0));
 
-    if (!z) {
+    // Normals and uniforms that are not given come from Philox streams
+    // (seed, stream) and (seed, stream + 1).  The d <= 64 proposal kernels and
+    // the MH test draw them where they are used; the other proposal paths read
+    // the normals from memory.
+    const bool zgen = !z && small && (!mala || !c->prior_full);
+    if (!z && !zgen) {
         SPS_CHECK(ensure(c, c->z, sizeof(double) * Pd, "normals"));
         SPS_CHECK(random_fill(c, 2, seed, stream, P, d, c->z.p));
         z = (const double*)c->z.p;
-    }
-    if (!u) {
-        SPS_CHECK(ensure(c, c->u, sizeof(double) * P, "uniforms"));
-        SPS_CHECK(random_fill(c, 1, seed, stream + 1, P, 1, c->u.p));
-        u = (const double*)c->u.p;
     }
 
     double* part = Sigma_in ? nullptr : (double*)c->cov.p;
@@ -806,7 +827,21 @@ static int mutate_launch(sps_ctx* c, const char* who, double* theta, double* ll,
     };
     if (!mala) {
         // theta' = theta + L z
-        SPS_CHECK(gemm_abt(c, z, L, theta, th2, P, d, 1.0));
+        if (zgen) {
+            SmallGemm g{};
+            g.B = L;
+            g.Base = theta;
+            g.Out = th2;
+            g.P = P;
+            g.d = d;
+            g.alpha = 1.0;
+            g.zgen = 1;
+            g.seed = seed;
+            g.zstream = stream;
+            SPS_CHECK(gemm_small<GM_PLAIN>(c, g));
+        } else {
+            SPS_CHECK(gemm_abt(c, z, L, theta, th2, P, d, 1.0));
+        }
         SPS_CHECK(loglik_launch(c, th2, P, 0, t, prec, ll2, nullptr));
         if (c->prior_full) SPS_CHECK(prior_whiten(c, th2, P, wtmp, R1));
     } else if (small && !c->prior_full) {
@@ -825,6 +860,9 @@ static int mutate_launch(sps_ctx* c, const char* who, double* theta, double* ll,
         f.U = v;
         f.P = P;
         f.d = d;
+        f.zgen = zgen ? 1 : 0;
+        f.seed = seed;
+        f.zstream = stream;
         SPS_CHECK(gemm_small<GM_MALA_FWD>(c, f));
         SPS_CHECK(loglik_launch(c, th2, P, 0, t, prec, ll2, g2));
         SmallGemm r{};
@@ -871,7 +909,7 @@ static int mutate_launch(sps_ctx* c, const char* who, double* theta, double* ll,
     accept_kernel<<<(unsigned)((P + kAccPerBlock - 1) / kAccPerBlock), 256, 0, c->stream>>>(
         theta, ll, grad, th2, ll2, mala ? (const double*)c->grad2.p : nullptr, z,
         mala ? (const double*)c->pstat.p : nullptr, u, c->prior_mean, c->prior_isd, R0, R1, P, d,
-        mala ? 1 : 0, flags, count);
+        mala ? 1 : 0, flags, count, seed, stream);
     SPS_CHECK(launched(c, "accept_kernel"));
     c->has_sigma = true;
     return SPS_OK;

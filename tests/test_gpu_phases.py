@@ -238,6 +238,38 @@ def test_mutate_matches_oracle(orc, kind, prec, C, k, J, N, t):
         assert nrm.max() <= (1e-9 if prec == 0 else 1e-3)
 
 
+@pytest.mark.parametrize("kind", [0, 1])
+@pytest.mark.parametrize("C,k", [(2, 30), (2, 80)])
+def test_mutate_drawn_variates_match_explicit(orc, kind, C, k):
+    """Without z and u the M step draws them from Philox (seed, stream) and
+    (seed, stream + 1), inside the proposal and MH kernels for d <= 64; the
+    result is identical to passing those variates explicitly."""
+    need_gpu()
+    sps = _sps()
+    T, J, N, t = 1000, 4, 96, 900
+    X, y, B = dataset(T, k, C, seed=60 + k)
+    d = k * (C - 1)
+    P = J * N
+    th = synth.make_particles(P, d, scale=0.05, seed=61, center=B.reshape(-1))
+    ll, gr = orc.loglik(X, y, C, th, 0, t, grad=True)
+    ctx = make_ctx(X, y, C)
+    seed, stream = 77, (5 << 32) | 3
+    print(f"drawn variates C={C} k={k} kind={kind}", flush=True)
+    th1, ll1 = to_gpu(th), to_gpu(ll)
+    g1 = to_gpu(gr) if kind == 1 else None
+    r1 = sps.sps_mutate(ctx, th1, ll1, g1, J, N, t, 0.3, kind, 1, seed=seed, stream=stream)
+    z = sps.sps_random(ctx, 2, seed, stream, P, d)
+    u = sps.sps_random(ctx, 1, seed, stream + 1, P)
+    th2, ll2 = to_gpu(th), to_gpu(ll)
+    g2 = to_gpu(gr) if kind == 1 else None
+    r2 = sps.sps_mutate(ctx, th2, ll2, g2, J, N, t, 0.3, kind, 1, z=z, u=u)
+    assert r1 == r2 and 0.0 < r1 < 1.0
+    assert np.array_equal(th1.cpu().numpy(), th2.cpu().numpy())
+    assert np.array_equal(ll1.cpu().numpy(), ll2.cpu().numpy())
+    if kind == 1:
+        assert np.array_equal(g1.cpu().numpy(), g2.cpu().numpy())
+
+
 def test_mutate_not_pd_leaves_state():
     need_gpu()
     import torch
