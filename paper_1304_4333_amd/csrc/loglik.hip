@@ -108,7 +108,8 @@ static LoglikEntry lookup(int prec, int nc, int ks, int mode) {
 // per-observation terms written to perobs[(t - t0) * P + p] (forward only).
 static int run_loglik(sps_ctx* c, const double* theta, int64_t P, int64_t t0, int64_t t1,
                       int prec, double* ll, double* grad, void* perobs, double* chunk_tot = nullptr,
-                      const unsigned* skip = nullptr) {
+                      const unsigned* skip = nullptr, LoglikSplit* keep = nullptr) {
+    if (keep) *keep = LoglikSplit{ll, grad, 1};
     const int mode = grad ? MODE_GRAD : (perobs ? MODE_PEROBS : MODE_FWD);
     const int ks = (prec == SPS_BF16X3) ? c->kb / 32 : c->kp / 4;
     LoglikEntry e = lookup(prec, c->C - 1, ks, mode);
@@ -175,6 +176,12 @@ static int run_loglik(sps_ctx* c, const double* theta, int64_t P, int64_t t0, in
     hipError_t err = e.fn(a, grid, c->stream);
     if (err != hipSuccess) return hip_fail(c, err, "loglik_kernel launch");
     SPS_CHECK(timing_end(c, slot));
+    const bool suff_term = ll && c->C > 2 && prec != SPS_FP64;
+    if (ll && a.out_ll != ll && keep && !suff_term) {
+        // the caller sums the observation-split partials itself
+        *keep = LoglikSplit{a.out_ll, a.out_g, a.nsplit};
+        return SPS_OK;
+    }
     if (ll && a.out_ll != ll) {
         const int64_t n = grad ? P * c->d : P;
         loglik_reduce_kernel<<<(unsigned)((n + 255) / 256), 256, 0, c->stream>>>(
@@ -182,7 +189,7 @@ static int run_loglik(sps_ctx* c, const double* theta, int64_t P, int64_t t0, in
             a.nsplit, ll, grad);
         SPS_CHECK(launched(c, "loglik_reduce_kernel"));
     }
-    if (ll && c->C > 2 && prec != SPS_FP64) {
+    if (suff_term) {
         // the eta_{y_t} / 1{y_t = c} terms the kernel leaves out
         SPS_CHECK(ensure(c, c->suff, sizeof(double) * c->d, "sufficient statistics"));
         if (!(c->suff_valid && c->suff_t0 == t0 && c->suff_t1 == t1 && c->suff_prec == prec)) {
@@ -217,6 +224,11 @@ static int check_loglik_args(sps_ctx* c, const char* who, const double* theta, i
 int loglik_launch(sps_ctx* c, const double* theta, int64_t P, int64_t t0, int64_t t1, int prec,
                   double* ll, double* grad) {
     return run_loglik(c, theta, P, t0, t1, prec, ll, grad, nullptr);
+}
+
+int loglik_launch_split(sps_ctx* c, const double* theta, int64_t P, int64_t t0, int64_t t1, int prec,
+                        double* ll, double* grad, LoglikSplit* out) {
+    return run_loglik(c, theta, P, t0, t1, prec, ll, grad, nullptr, nullptr, nullptr, out);
 }
 
 int loglik_perobs(sps_ctx* c, const double* theta, int64_t P, int64_t t0, int64_t t1, int prec,

@@ -241,11 +241,15 @@ __global__ __launch_bounds__(256) void gemm_abt_kernel(const double* __restrict_
 // are loaded into registers.  Thread (ty, tx) of a 16 x 16 grid owns the
 // TILE x TILE block (a, b) = (ty TILE + i, tx TILE + j); every (a, b) and
 // (b, a) run the same products in the same order (V exactly symmetric).
+// zero2 (optional): two words cleared by workgroup 0 (the step's status
+// flags and accepted count, which later kernels of the step update).
 template <int TILE>
 __global__ __launch_bounds__(256) void cov_partial_small_kernel(const double* __restrict__ theta, int64_t P,
                                                                 int32_t d, int64_t chunk,
                                                                 double* __restrict__ part,
-                                                                double* __restrict__ psum) {
+                                                                double* __restrict__ psum,
+                                                                unsigned long long* zero2) {
+    if (zero2 != nullptr && blockIdx.x == 0 && threadIdx.x < 2) zero2[threadIdx.x] = 0ull;
     constexpr int kSub = 64;
     constexpr int kW = 16 * TILE;           // covered width: 32 or 64 parameters
     constexpr int kPer = kSub * kW / 256;   // staged values per thread
@@ -399,6 +403,8 @@ struct SmallGemm {
     int32_t zgen;        // GM_PLAIN (A = z) and GM_MALA_FWD: draw z from Philox (seed, zstream)
     uint64_t seed;
     uint64_t zstream;
+    int32_t gsplit;      // GM_MALA_REV: g holds gsplit slices of P x d, summed in slice order
+    double* gout;        // GM_MALA_REV: receives the summed gradient (may equal g when gsplit = 1)
 };
 constexpr int kGemmRows = 64;
 constexpr int kStagePer = kGemmRows * kSmallD / 256;  // elements of a 64 x d tile per thread
@@ -427,9 +433,15 @@ __global__ __launch_bounds__(256) void gemm_small_kernel(SmallGemm g) {
             const bool ok = e < nA;
             if constexpr (MODE == GM_PLAIN) {
                 v0[l] = (ok && !g.zgen) ? g.A[base + e] : 0.0;
-            } else {
+            } else if constexpr (MODE == GM_MALA_FWD) {
                 v0[l] = ok ? g.g[base + e] : 0.0;
-                v1[l] = ok ? (MODE == GM_MALA_FWD ? g.th : g.th2)[base + e] : 0.0;
+                v1[l] = ok ? g.th[base + e] : 0.0;
+            } else {
+                double gs = 0.0;
+                if (ok)
+                    for (int32_t q = 0; q < g.gsplit; ++q) gs += g.g[(int64_t)q * g.P * d + base + e];
+                v0[l] = gs;
+                v1[l] = ok ? g.th2[base + e] : 0.0;
             }
         }
         int r = t / d, q = t % d;
@@ -441,6 +453,9 @@ __global__ __launch_bounds__(256) void gemm_small_kernel(SmallGemm g) {
                                    : (p0 + r < g.P ? philox_normal(g.seed, g.zstream, p0 + r, q, d) : 0.0);
                 } else {
                     As[r * ld + q] = v0[l] - (v1[l] - g.mu[q]) * g.isd[q] * g.isd[q];
+                    if constexpr (MODE == GM_MALA_REV) {
+                        if (p0 + r < g.P) g.gout[(p0 + r) * d + q] = v0[l];
+                    }
                 }
             }
             r += dr;
@@ -627,6 +642,8 @@ __global__ void sub_kernel(const double* __restrict__ a, const double* __restric
 // The prior terms use the whitened particles w0, w1 when given (full prior),
 // else (theta - mu) / sd.  Sums over the 16 lanes are fixed butterflies.
 // Accepted particles are counted per workgroup and added with one atomic.
+// ll2 holds ll2n slices of P (the likelihood kernel's observation splits),
+// summed here in slice order.
 // z / u null: the normals (MALA) and uniforms are drawn here from Philox
 // streams zstream / zstream + 1 (the values sps_random gives).
 constexpr int kAccLanes = 16;
@@ -643,7 +660,7 @@ __global__ __launch_bounds__(256) void accept_kernel(
     const double* __restrict__ u, const double* __restrict__ mu, const double* __restrict__ isd,
     const double* __restrict__ w0, const double* __restrict__ w1,
     int64_t P, int32_t d, int mala, const unsigned* flags, unsigned long long* count,
-    uint64_t seed, uint64_t zstream) {
+    uint64_t seed, uint64_t zstream, int32_t ll2n) {
     __shared__ unsigned nacc[256 / kAccLanes];
     const int sub = threadIdx.x & (kAccLanes - 1);
     const int slot = threadIdx.x / kAccLanes;
@@ -667,7 +684,9 @@ __global__ __launch_bounds__(256) void accept_kernel(
         }
         q0 = sum16(q0);
         q1 = sum16(q1);
-        double la = (ll2[p] - 0.5 * q1) - (ll[p] - 0.5 * q0);
+        double l2 = 0.0;  // the proposal's log-likelihood: ll2n observation-split slices, in order
+        for (int32_t q = 0; q < ll2n; ++q) l2 += ll2[(int64_t)q * P + p];
+        double la = (l2 - 0.5 * q1) - (ll[p] - 0.5 * q0);
         if (mala) la += -0.5 * sum16(vv) + 0.5 * sum16(zz);
         if (isnan(la)) la = -INFINITY;
         double up;
@@ -683,7 +702,7 @@ __global__ __launch_bounds__(256) void accept_kernel(
                 theta[p * d + i] = b[i];
                 if (mala) grad[p * d + i] = grad2[p * d + i];
             }
-            if (sub == 0) ll[p] = ll2[p];
+            if (sub == 0) ll[p] = l2;
             taken = 1;
         }
     }
@@ -756,7 +775,10 @@ static int mutate_launch(sps_ctx* c, const char* who, double* theta, double* ll,
     double* ll2 = (double*)c->ll2.p;
     unsigned* flags = (unsigned*)c->small.p;
     unsigned long long* count = (unsigned long long*)((char*)c->small.p + 8);
-    SPS_CHECK(fill(c, (double*)c->small.p, 2, 0.0));
+    // status flags and accepted count start at zero: cleared by the first kernel
+    // of the step on the d <= 64 covariance path, by a fill otherwise
+    const bool clear_in_cov = small && !Sigma_in;
+    if (!clear_in_cov) SPS_CHECK(fill(c, (double*)c->small.p, 2, 0.0));
 
     // Normals and uniforms that are not given come from Philox streams
     // (seed, stream) and (seed, stream + 1).  The d <= 64 proposal kernels and
@@ -775,8 +797,11 @@ static int mutate_launch(sps_ctx* c, const char* who, double* theta, double* ll,
         if (Sigma_in) {
             SPS_HIP(c, hipMemcpyAsync(Sg, Sigma_in, sizeof(double) * d * d, hipMemcpyDeviceToDevice, c->stream));
         } else {
-            if (d <= 32) cov_partial_small_kernel<2><<<nchunk, 256, 0, c->stream>>>(theta, P, d, chunk, part, psum);
-            else cov_partial_small_kernel<4><<<nchunk, 256, 0, c->stream>>>(theta, P, d, chunk, part, psum);
+            unsigned long long* z2 = (unsigned long long*)c->small.p;
+            if (d <= 32)
+                cov_partial_small_kernel<2><<<nchunk, 256, 0, c->stream>>>(theta, P, d, chunk, part, psum, z2);
+            else
+                cov_partial_small_kernel<4><<<nchunk, 256, 0, c->stream>>>(theta, P, d, chunk, part, psum, z2);
             SPS_CHECK(launched(c, "cov_partial_small_kernel"));
             cov_final_kernel<<<(unsigned)(((int64_t)d * d + 3) / 4), 256, 0, c->stream>>>(part, psum, nchunk, d,
                                                                                           P, h, Sg);
@@ -825,6 +850,10 @@ static int mutate_launch(sps_ctx* c, const char* who, double* theta, double* ll,
         grad_logpost_kernel<<<nblk(Pd), 256, 0, c->stream>>>(gl, th, c->prior_mean, c->prior_isd, P, d, out);
         return launched(c, "grad_logpost_kernel");
     };
+    // The proposal's log-likelihood as the MH test reads it: ll2, or the
+    // likelihood kernel's observation-split slices when the sum is left to it.
+    const double* ll2s = ll2;
+    int32_t ll2n = 1;
     if (!mala) {
         // theta' = theta + L z
         if (zgen) {
@@ -842,7 +871,10 @@ static int mutate_launch(sps_ctx* c, const char* who, double* theta, double* ll,
         } else {
             SPS_CHECK(gemm_abt(c, z, L, theta, th2, P, d, 1.0));
         }
-        SPS_CHECK(loglik_launch(c, th2, P, 0, t, prec, ll2, nullptr));
+        LoglikSplit sp;
+        SPS_CHECK(loglik_launch_split(c, th2, P, 0, t, prec, ll2, nullptr, &sp));
+        ll2s = sp.ll;
+        ll2n = sp.n;
         if (c->prior_full) SPS_CHECK(prior_whiten(c, th2, P, wtmp, R1));
     } else if (small && !c->prior_full) {
         // theta' = mu(theta) + L z through u = z + L^T g(theta) / 2 (theta' = theta + L u);
@@ -864,10 +896,15 @@ static int mutate_launch(sps_ctx* c, const char* who, double* theta, double* ll,
         f.seed = seed;
         f.zstream = stream;
         SPS_CHECK(gemm_small<GM_MALA_FWD>(c, f));
-        SPS_CHECK(loglik_launch(c, th2, P, 0, t, prec, ll2, g2));
+        LoglikSplit sp;
+        SPS_CHECK(loglik_launch_split(c, th2, P, 0, t, prec, ll2, g2, &sp));
+        ll2s = sp.ll;
+        ll2n = sp.n;
         SmallGemm r{};
         r.th2 = th2;
-        r.g = g2;
+        r.g = sp.g;          // the gradient slices, summed while staged
+        r.gsplit = sp.n;
+        r.gout = g2;         // the summed gradient at theta' (the MH test copies it)
         r.mu = c->prior_mean;
         r.isd = c->prior_isd;
         r.L = L;
@@ -907,9 +944,9 @@ static int mutate_launch(sps_ctx* c, const char* who, double* theta, double* ll,
         SPS_CHECK(gemm_abt(c, work, W, nullptr, gpi, P, d, 1.0));
     }
     accept_kernel<<<(unsigned)((P + kAccPerBlock - 1) / kAccPerBlock), 256, 0, c->stream>>>(
-        theta, ll, grad, th2, ll2, mala ? (const double*)c->grad2.p : nullptr, z,
+        theta, ll, grad, th2, ll2s, mala ? (const double*)c->grad2.p : nullptr, z,
         mala ? (const double*)c->pstat.p : nullptr, u, c->prior_mean, c->prior_isd, R0, R1, P, d,
-        mala ? 1 : 0, flags, count, seed, stream);
+        mala ? 1 : 0, flags, count, seed, stream, ll2n);
     SPS_CHECK(launched(c, "accept_kernel"));
     c->has_sigma = true;
     return SPS_OK;

@@ -84,7 +84,7 @@ constexpr int kScanRun = 8;
 
 __device__ __forceinline__ double chunk_base(const double* __restrict__ carry, const double* __restrict__ tot,
                                              int64_t P, int64_t p, int32_t q) {
-    double acc = carry[p];
+    double acc = carry ? carry[p] : 0.0;  // null carry: the first block (w = 1 before it)
 #pragma unroll 8
     for (int32_t r = 0; r < q; ++r) acc += tot[(int64_t)r * P + p];
     return acc;
@@ -703,7 +703,6 @@ extern "C" int sps_correct(sps_ctx* c, const double* theta, double* ll, int32_t 
     const double thr = ess_frac * (double)P;
 
     SPS_CHECK(fill(c, hdr, kHdr, 0.0));
-    SPS_CHECK(fill(c, log_w, P, 0.0));  // w = 1 after observation s0
     const unsigned* done = (const unsigned*)hdr + kDoneWord;
     // Blocks of observations double in size.  The host queues block i + 1
     // before it reads block i's outcome; a block queued after the crossing
@@ -740,7 +739,7 @@ extern "C" int sps_correct(sps_ctx* c, const double* theta, double* ll, int32_t 
         return b;
     };
     int32_t B = std::min<int32_t>(64, kMaxBlock);
-    Block cur = make_block(s0, B, log_w, spare);
+    Block cur = make_block(s0, B, nullptr, spare);  // w = 1 after observation s0
     SPS_CHECK(launch_block(cur));
     for (;;) {
         const int64_t s1 = cur.s + cur.nb;
@@ -748,7 +747,7 @@ extern "C" int sps_correct(sps_ctx* c, const double* theta, double* ll, int32_t 
         Block nxt{};
         const bool ahead = s1 < c->T;
         if (ahead) {
-            nxt = make_block(s1, B1, cur.next, cur.carry);
+            nxt = make_block(s1, B1, cur.next, cur.carry ? cur.carry : log_w);
             SPS_CHECK(launch_block(nxt));
         }
         const void* hv = nullptr;

@@ -133,6 +133,18 @@ inline int launched(sps_ctx* c, const char* what) {
 // Writes ll (and grad when non-null) for observations [t0, t1).
 int loglik_launch(sps_ctx* c, const double* theta, int64_t P, int64_t t0, int64_t t1,
                   int prec, double* ll, double* grad);
+// As loglik_launch, but when the kernel leaves observation-split partials and
+// no term is added after the sum (C = 2 or FP64), the sum is left to the
+// caller: out->ll holds out->n slices of P, out->g (grad given) out->n
+// slices of P x d, valid until the next likelihood launch on the context.
+// Otherwise out = {ll, grad, 1}.
+struct LoglikSplit {
+    const double* ll;
+    const double* g;
+    int32_t n;
+};
+int loglik_launch_split(sps_ctx* c, const double* theta, int64_t P, int64_t t0, int64_t t1,
+                        int prec, double* ll, double* grad, LoglikSplit* out);
 // Per-observation terms l_{p,t} for t0 <= t < t1 into perobs[(t - t0) * P + p]:
 // FP64 natural-log values in SPS_FP64 mode, otherwise the kernel's FP32
 // base-2 values (read them with perobs_value).  chunk_tot (optional):
