@@ -438,8 +438,10 @@ __global__ __launch_bounds__(256) void gemm_small_kernel(SmallGemm g) {
                 v1[l] = ok ? g.th[base + e] : 0.0;
             } else {
                 double gs = 0.0;
-                if (ok)
+                if (ok) {
+#pragma unroll 4
                     for (int32_t q = 0; q < g.gsplit; ++q) gs += g.g[(int64_t)q * g.P * d + base + e];
+                }
                 v0[l] = gs;
                 v1[l] = ok ? g.th2[base + e] : 0.0;
             }
@@ -671,6 +673,7 @@ __global__ __launch_bounds__(256) void accept_kernel(
         const double* a = theta + p * d;
         const double* b = theta2 + p * d;
         double q0 = 0.0, q1 = 0.0, vv = 0.0, zz = 0.0;
+#pragma unroll 4
         for (int32_t i = sub; i < d; i += kAccLanes) {
             const double za = w0 ? w0[p * d + i] : (a[i] - mu[i]) * isd[i];
             const double zb = w0 ? w1[p * d + i] : (b[i] - mu[i]) * isd[i];
@@ -685,6 +688,7 @@ __global__ __launch_bounds__(256) void accept_kernel(
         q0 = sum16(q0);
         q1 = sum16(q1);
         double l2 = 0.0;  // the proposal's log-likelihood: ll2n observation-split slices, in order
+#pragma unroll 8
         for (int32_t q = 0; q < ll2n; ++q) l2 += ll2[(int64_t)q * P + p];
         double la = (l2 - 0.5 * q1) - (ll[p] - 0.5 * q0);
         if (mala) la += -0.5 * sum16(vv) + 0.5 * sum16(zz);
