@@ -451,8 +451,7 @@ __global__ __launch_bounds__(256) void gemm_small_kernel(SmallGemm g) {
         for (int l = 0; l < kStagePer; ++l) {
             if (r < kGemmRows) {
                 if constexpr (MODE == GM_PLAIN) {
-                    As[r * ld + q] = !g.zgen ? v0[l]
-                                   : (p0 + r < g.P ? philox_normal(g.seed, g.zstream, p0 + r, q, d) : 0.0);
+                    if (!g.zgen) As[r * ld + q] = v0[l];
                 } else {
                     As[r * ld + q] = v0[l] - (v1[l] - g.mu[q]) * g.isd[q] * g.isd[q];
                     if constexpr (MODE == GM_MALA_REV) {
@@ -465,6 +464,22 @@ __global__ __launch_bounds__(256) void gemm_small_kernel(SmallGemm g) {
             if (q >= d) {
                 q -= d;
                 ++r;
+            }
+        }
+    }
+    // Drawn normals (PLAIN: the A operand; MALA_FWD: z of u = z + ...), one
+    // Box-Muller pair per thread and element pair, into the A block or Zs.
+    double* Zs = B2 + (MODE == GM_MALA_FWD ? d * ld : 0);  // [kGemmRows][ld], MALA_FWD only
+    if constexpr (MODE != GM_MALA_REV) {
+        if (g.zgen) {
+            const int hd = (d + 1) / 2;
+            double* dst = MODE == GM_PLAIN ? As : Zs;
+            for (int e = t; e < kGemmRows * hd; e += 256) {
+                const int r = e / hd, j = e % hd;
+                double z0 = 0.0, z1 = 0.0;
+                if (p0 + r < g.P) philox_normal_pair(g.seed, g.zstream, p0 + r, j, d, z0, z1);
+                dst[r * ld + 2 * j] = z0;
+                if (2 * j + 1 < d) dst[r * ld + 2 * j + 1] = z1;
             }
         }
     }
@@ -527,8 +542,7 @@ __global__ __launch_bounds__(256) void gemm_small_kernel(SmallGemm g) {
                 const int row = 16 * w + kg + 4 * i, col = 16 * n + m;
                 const int64_t p = p0 + row;
                 if (n < NT && col < d) {
-                    const double zz = p >= g.P ? 0.0
-                                    : (g.zgen ? philox_normal(g.seed, g.zstream, p, col, d) : g.z[p * d + col]);
+                    const double zz = p >= g.P ? 0.0 : (g.zgen ? Zs[row * ld + col] : g.z[p * d + col]);
                     const double u = zz + acc[n][i];
                     As[row * ld + col] = u;
                     if (p < g.P) g.U[p * d + col] = u;
@@ -571,14 +585,15 @@ __global__ __launch_bounds__(256) void gemm_small_kernel(SmallGemm g) {
 template <int MODE>
 static int gemm_small(sps_ctx* c, const SmallGemm& g) {
     constexpr int KM = MODE == GM_MALA_FWD ? 2 : 1;  // B matrices staged
-    const size_t bytes = sizeof(double) * (size_t)(kGemmRows + KM * g.d) * (g.d + 1);
+    constexpr int AM = MODE == GM_MALA_FWD ? 2 : 1;  // row blocks staged (MALA_FWD: A and the normals)
+    const size_t bytes = sizeof(double) * (size_t)(AM * kGemmRows + KM * g.d) * (g.d + 1);
     // the kernel's dynamic LDS limit (above the default for large d), set once per device
     constexpr int kMaxDev = 64;
     static bool attr_set[kMaxDev] = {};
     if (c->device < 0 || c->device >= kMaxDev || !attr_set[c->device]) {
         SPS_HIP(c, hipFuncSetAttribute(reinterpret_cast<const void*>(&gemm_small_kernel<MODE>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)(sizeof(double) * (kGemmRows + KM * kSmallD) * (kSmallD + 1))));
+                                       (int)(sizeof(double) * (AM * kGemmRows + KM * kSmallD) * (kSmallD + 1))));
         if (c->device >= 0 && c->device < kMaxDev) attr_set[c->device] = true;
     }
     gemm_small_kernel<MODE><<<(unsigned)((g.P + kGemmRows - 1) / kGemmRows), 256, bytes, c->stream>>>(g);

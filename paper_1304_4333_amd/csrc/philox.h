@@ -57,4 +57,19 @@ __device__ __forceinline__ double philox_normal(uint64_t seed, uint64_t stream, 
     return (i & 1) ? r * s : r * c;
 }
 
+// Elements 2 j and 2 j + 1 of row p of a P x d array (the two values of one
+// Box-Muller pair, as philox_normal gives them); z1 is meaningless when
+// 2 j + 1 = d.
+__device__ __forceinline__ void philox_normal_pair(uint64_t seed, uint64_t stream, int64_t p, int32_t j,
+                                                   int32_t d, double& z0, double& z1) {
+    const int64_t half = (d + 1) / 2;
+    uint64_t a, b;
+    philox_u53x2(seed, stream, (uint64_t)(p * half + j), a, b);
+    const double r = sqrt(-2.0 * log(u53_to_uniform(a)));
+    double s, c;
+    sincospi(2.0 * u53_to_uniform(b), &s, &c);
+    z0 = r * c;
+    z1 = r * s;
+}
+
 }  // namespace sps
