@@ -110,13 +110,12 @@ int publish_wait(sps_ctx* c, const PubTicket& t, const void** host) {
         if ((n & 1023) == 0) {
             const hipError_t e = hipStreamQuery(c->stream);
             if (e == hipSuccess) {
-                if (*flag == t.seq) break;
-                // the stream drained without the number: read it the plain way
-                SPS_CHECK(ensure_host(c, c->hostbuf, t.bytes));
-                SPS_HIP(c, hipMemcpyAsync(c->hostbuf.p, t.dsrc, t.bytes, hipMemcpyDeviceToHost, c->stream));
+                // The stream has run the publishing kernel, whose system-scope stores
+                // are visible once it completes.  (The device source cannot be read
+                // again instead: launches queued after the publish may have changed it.)
                 SPS_HIP(c, hipStreamSynchronize(c->stream));
-                *host = c->hostbuf.p;
-                return SPS_OK;
+                if (*flag == t.seq) break;
+                return fail(c, SPS_ERR_HIP, "read-back: the published bytes did not arrive");
             }
             if (e != hipErrorNotReady) return hip_fail(c, e, "read-back");
         }

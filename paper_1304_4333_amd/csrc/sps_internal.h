@@ -165,8 +165,9 @@ __device__ __forceinline__ double perobs_value(const void* lw, int f32, int64_t 
 // launch on the context stream has finished, without a stream
 // synchronisation: a one-wave kernel copies the bytes into fine-grained
 // pinned host memory and then writes a sequence number there, on which the
-// host spins (checking the stream for errors, and falling back to a copy and
-// a synchronisation if the stream drains without the number appearing).
+// host spins (checking the stream for errors every 1024 spins; a stream that
+// drains without the number appearing is an SPS_ERR_HIP failure).  Reads
+// above kPublishBytes use a copy and a stream synchronisation instead.
 // *host points at the bytes until the next read-back on the context.
 int readback(sps_ctx* c, const void* dsrc, size_t bytes, const void** host);
 // The same in two halves, for reads that overlap later launches: the copy is
