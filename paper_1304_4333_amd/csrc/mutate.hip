@@ -687,6 +687,19 @@ __global__ __launch_bounds__(256) void accept_kernel(
     if (ok && p < P) {  // the 16 lanes of a particle share p: no divergence inside a group
         const double* a = theta + p * d;
         const double* b = theta2 + p * d;
+        // per-particle scalars first, so their loads overlap the loop's
+        double l2 = 0.0;  // the proposal's log-likelihood: ll2n observation-split slices, in order
+#pragma unroll 8
+        for (int32_t q = 0; q < ll2n; ++q) l2 += ll2[(int64_t)q * P + p];
+        const double l1 = ll[p];
+        double up;
+        if (u) {
+            up = u[p];
+        } else {  // the uniform of stream zstream + 1, as sps_random kind 1
+            uint64_t ua, ub;
+            philox_u53x2(seed, zstream + 1, (uint64_t)p, ua, ub);
+            up = u53_to_uniform(ua);
+        }
         double q0 = 0.0, q1 = 0.0, vv = 0.0, zz = 0.0;
 #pragma unroll 4
         for (int32_t i = sub; i < d; i += kAccLanes) {
@@ -702,20 +715,9 @@ __global__ __launch_bounds__(256) void accept_kernel(
         }
         q0 = sum16(q0);
         q1 = sum16(q1);
-        double l2 = 0.0;  // the proposal's log-likelihood: ll2n observation-split slices, in order
-#pragma unroll 8
-        for (int32_t q = 0; q < ll2n; ++q) l2 += ll2[(int64_t)q * P + p];
-        double la = (l2 - 0.5 * q1) - (ll[p] - 0.5 * q0);
+        double la = (l2 - 0.5 * q1) - (l1 - 0.5 * q0);
         if (mala) la += -0.5 * sum16(vv) + 0.5 * sum16(zz);
         if (isnan(la)) la = -INFINITY;
-        double up;
-        if (u) {
-            up = u[p];
-        } else {  // the uniform of stream zstream + 1, as sps_random kind 1
-            uint64_t ua, ub;
-            philox_u53x2(seed, zstream + 1, (uint64_t)p, ua, ub);
-            up = u53_to_uniform(ua);
-        }
         if (log(up) < la) {
             for (int32_t i = sub; i < d; i += kAccLanes) {
                 theta[p * d + i] = b[i];
