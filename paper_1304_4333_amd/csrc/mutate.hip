@@ -14,6 +14,18 @@ namespace sps {
 constexpr unsigned kFlagNotPD = 1u;
 constexpr int kSmallD = 64;  // d at or below this: the matrices of the M step fit one workgroup's LDS
 
+// Status of an M step in the context's small buffer: the flags word at byte 0,
+// the aggregate RNE at byte 16 (sps_mphase), and the accepted count split over
+// kCountSlots 64-bit slots, kCountStride words apart from byte kCountOff.  One
+// atomic per workgroup into a single address serialises over about a thousand
+// workgroups (some 11 us at 16384 particles); spread over separate 128-byte
+// lines the adds proceed in parallel.  The host sums the slots.
+constexpr int kCountSlots = 28;
+constexpr int kCountStride = 16;
+constexpr size_t kCountOff = 512;
+constexpr size_t kStatusBytes = kCountOff + (size_t)kCountSlots * kCountStride * 8;  // read back per step
+static_assert(kStatusBytes <= 4096, "the status block fits the small buffer and one publish");
+
 // Sample variance in one pass, shifted by the first particle c = theta[0]
 // for stability: over each chunk of particles
 //   part[chunk][a][b] = sum_p (theta_pa - c_a)(theta_pb - c_b),
@@ -241,15 +253,20 @@ __global__ __launch_bounds__(256) void gemm_abt_kernel(const double* __restrict_
 // are loaded into registers.  Thread (ty, tx) of a 16 x 16 grid owns the
 // TILE x TILE block (a, b) = (ty TILE + i, tx TILE + j); every (a, b) and
 // (b, a) run the same products in the same order (V exactly symmetric).
-// zero2 (optional): two words cleared by workgroup 0 (the step's status
-// flags and accepted count, which later kernels of the step update).
+// zero2 (optional): the step's status block, cleared by workgroup 0 (the
+// flags word and the accepted-count slots, which later kernels of the step
+// update).
 template <int TILE>
 __global__ __launch_bounds__(256) void cov_partial_small_kernel(const double* __restrict__ theta, int64_t P,
                                                                 int32_t d, int64_t chunk,
                                                                 double* __restrict__ part,
                                                                 double* __restrict__ psum,
                                                                 unsigned long long* zero2) {
-    if (zero2 != nullptr && blockIdx.x == 0 && threadIdx.x < 2) zero2[threadIdx.x] = 0ull;
+    if (zero2 != nullptr && blockIdx.x == 0) {
+        if (threadIdx.x == 0) zero2[0] = 0ull;
+        else if (threadIdx.x <= kCountSlots)
+            zero2[kCountOff / 8 + (threadIdx.x - 1) * kCountStride] = 0ull;
+    }
     constexpr int kSub = 64;
     constexpr int kW = 16 * TILE;           // covered width: 32 or 64 parameters
     constexpr int kPer = kSub * kW / 256;   // staged values per thread
@@ -658,7 +675,8 @@ __global__ void sub_kernel(const double* __restrict__ a, const double* __restric
 // accept iff log u < log alpha; accepted particles take theta', ll' (grad').
 // The prior terms use the whitened particles w0, w1 when given (full prior),
 // else (theta - mu) / sd.  Sums over the 16 lanes are fixed butterflies.
-// Accepted particles are counted per workgroup and added with one atomic.
+// Accepted particles are counted per workgroup and added with one atomic into
+// count slot blockIdx mod kCountSlots.
 // ll2 holds ll2n slices of P (the likelihood kernel's observation splits),
 // summed here in slice order.
 // z / u null: the normals (MALA) and uniforms are drawn here from Philox
@@ -732,7 +750,7 @@ __global__ __launch_bounds__(256) void accept_kernel(
     if (threadIdx.x == 0 && ok) {
         unsigned tot = 0;
         for (int q = 0; q < kAccPerBlock; ++q) tot += nacc[q];
-        if (tot) atomicAdd(count, (unsigned long long)tot);
+        if (tot) atomicAdd(count + (blockIdx.x % kCountSlots) * kCountStride, (unsigned long long)tot);
     }
 }
 
@@ -742,8 +760,8 @@ static inline unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
 // h V from the particles (Algorithm 2); otherwise the given matrix
 // (Algorithm 3, second pass).  The Sigma used stays in the context for
 // sps_last_sigma.
-// All launches of one M step; the accepted count and the status flags are
-// left in c->small (flags at byte 0, count at byte 8).  No synchronisation.
+// All launches of one M step; the status flags and the accepted-count slots
+// are left in the status block of c->small.  No synchronisation.
 static int mutate_launch(sps_ctx* c, const char* who, double* theta, double* ll, double* grad, int32_t J,
                          int32_t N, int64_t t, double h, const double* Sigma_in, int kind, int prec,
                          const double* z, const double* u, uint64_t seed, uint64_t stream) {
@@ -795,11 +813,11 @@ static int mutate_launch(sps_ctx* c, const char* who, double* theta, double* ll,
     double* th2 = (double*)c->theta2.p;
     double* ll2 = (double*)c->ll2.p;
     unsigned* flags = (unsigned*)c->small.p;
-    unsigned long long* count = (unsigned long long*)((char*)c->small.p + 8);
-    // status flags and accepted count start at zero: cleared by the first kernel
-    // of the step on the d <= 64 covariance path, by a fill otherwise
+    unsigned long long* count = (unsigned long long*)((char*)c->small.p + kCountOff);
+    // status flags and accepted-count slots start at zero: cleared by the first
+    // kernel of the step on the d <= 64 covariance path, by a fill otherwise
     const bool clear_in_cov = small && !Sigma_in;
-    if (!clear_in_cov) SPS_CHECK(fill(c, (double*)c->small.p, 2, 0.0));
+    if (!clear_in_cov) SPS_CHECK(fill(c, (double*)c->small.p, (int64_t)(kStatusBytes / 8), 0.0));
 
     // Normals and uniforms that are not given come from Philox streams
     // (seed, stream) and (seed, stream + 1).  The d <= 64 proposal kernels and
@@ -973,14 +991,17 @@ static int mutate_launch(sps_ctx* c, const char* who, double* theta, double* ll,
     return SPS_OK;
 }
 
-// Read back `bytes` of c->small (flags, accepted count, ...) and check the flags.
-static int mutate_readback(sps_ctx* c, const char* who, int64_t P, size_t bytes, double* accept_rate,
+// Read back the step's status block (flags, aggregate RNE, accepted-count
+// slots) and check the flags.
+static int mutate_readback(sps_ctx* c, const char* who, int64_t P, double* accept_rate,
                            const void** host_out = nullptr) {
     const void* h = nullptr;
-    SPS_CHECK(readback(c, c->small.p, bytes, &h));
+    SPS_CHECK(readback(c, c->small.p, kStatusBytes, &h));
     if (host_out) *host_out = h;
     const unsigned f = *(const unsigned*)h;
-    const unsigned long long n_acc = *(const unsigned long long*)((const char*)h + 8);
+    const unsigned long long* slots = (const unsigned long long*)((const char*)h + kCountOff);
+    unsigned long long n_acc = 0;
+    for (int q = 0; q < kCountSlots; ++q) n_acc += slots[q * kCountStride];
     if (f & kFlagNotPD)
         return fail(c, SPS_ERR_NOT_PD, "%s: the proposal covariance is not positive definite", who);
     if (accept_rate) *accept_rate = (double)n_acc / (double)P;
@@ -992,7 +1013,7 @@ static int mutate_impl(sps_ctx* c, const char* who, double* theta, double* ll, d
                        const double* z, const double* u, uint64_t seed, uint64_t stream,
                        double* accept_rate) {
     SPS_CHECK(mutate_launch(c, who, theta, ll, grad, J, N, t, h, Sigma_in, kind, prec, z, u, seed, stream));
-    return mutate_readback(c, who, (int64_t)J * N, 16, accept_rate);
+    return mutate_readback(c, who, (int64_t)J * N, accept_rate);
 }
 
 }  // namespace sps
@@ -1063,7 +1084,7 @@ extern "C" int sps_mphase(sps_ctx* c, double* theta, double* ll, double* grad, i
         SPS_CHECK(moments_launch(c, g_work, J, N, m, &mom));
         SPS_CHECK(rne_aggregate(c, mom, m, rne_rule, (double*)((char*)c->small.p + 16)));
         const void* rec = nullptr;
-        SPS_CHECK(mutate_readback(c, "sps_mphase", P, 24, &rate, &rec));
+        SPS_CHECK(mutate_readback(c, "sps_mphase", P, &rate, &rec));
         agg = *(const double*)((const char*)rec + 16);
         hh = rate > acc_target ? std::min(hh + h_step, h_max) : std::max(hh - h_step, h_min);
         if (agg >= K || r >= R_max) break;

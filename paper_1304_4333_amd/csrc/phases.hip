@@ -199,19 +199,12 @@ __global__ __launch_bounds__(256) void correct_scan_ess_kernel(const void* __res
     }
 }
 
-// ESS(u) = S1^2 / S2 from the per-workgroup partials.  One wave per
-// observation: lane l merges partials l, l + 64, ... in order, then the lanes
-// merge in a fixed butterfly (the same result on every run).
-__device__ __forceinline__ void merge_ms(double& m, double& s1, double& s2, double m2, double t1, double t2) {
-    const double M = fmax(m, m2);
-    if (M == -INFINITY) return;
-    const double fa = m > -INFINITY ? exp(m - M) : 0.0;
-    const double fb = m2 > -INFINITY ? exp(m2 - M) : 0.0;
-    s1 = s1 * fa + t1 * fb;
-    s2 = s2 * fa * fa + t2 * fb * fb;
-    m = M;
-}
-
+// ESS(u) = S1^2 / S2 from the per-workgroup partials (max m, S1, S2 of
+// exp(lw - m)).  One wave per observation.  Lane l loads partials l, l + 64,
+// ... four at a time (all loads in flight together) and rescales them to its
+// running maximum; the wave then takes the maximum over lanes and sums the
+// lanes' rescaled S1, S2 in a fixed butterfly.  The exponentials of a lane are
+// independent, so their latencies overlap.
 __global__ __launch_bounds__(256) void correct_ess_combine_kernel(const double* __restrict__ part, int32_t npb,
                                                                   int32_t nb, double* __restrict__ ess,
                                                                   const unsigned* skip) {
@@ -219,23 +212,49 @@ __global__ __launch_bounds__(256) void correct_ess_combine_kernel(const double* 
     const int lane = threadIdx.x & 63;
     if (u >= nb || *skip) return;
     const double* q = part + (int64_t)u * npb * 3;
+    constexpr int kAhead = 4;
     double m = -INFINITY, s1 = 0.0, s2 = 0.0;
-    for (int32_t b = lane; b < npb; b += 64) merge_ms(m, s1, s2, q[3 * b], q[3 * b + 1], q[3 * b + 2]);
+    for (int32_t b0 = lane; b0 < npb; b0 += 64 * kAhead) {
+        double mk[kAhead], ak[kAhead], bk[kAhead];
 #pragma unroll
-    for (int sh = 1; sh < 64; sh <<= 1) {
-        const double m2 = __shfl_xor(m, sh, 64);
-        const double t1 = __shfl_xor(s1, sh, 64);
-        const double t2 = __shfl_xor(s2, sh, 64);
-        // merge in lane order so both partners compute the same value
-        if (lane & sh) {
-            double mm = m2, a1 = t1, a2 = t2;
-            merge_ms(mm, a1, a2, m, s1, s2);
-            m = mm; s1 = a1; s2 = a2;
-        } else {
-            merge_ms(m, s1, s2, m2, t1, t2);
+        for (int k = 0; k < kAhead; ++k) {
+            const int32_t b = b0 + 64 * k;
+            const bool in = b < npb;
+            mk[k] = in ? q[3 * b] : -INFINITY;
+            ak[k] = in ? q[3 * b + 1] : 0.0;
+            bk[k] = in ? q[3 * b + 2] : 0.0;
         }
+        double M = m;
+#pragma unroll
+        for (int k = 0; k < kAhead; ++k) M = fmax(M, mk[k]);
+        if (M == -INFINITY) continue;
+        const double f = m > -INFINITY ? exp(m - M) : 0.0;
+        s1 *= f;
+        s2 *= f * f;
+#pragma unroll
+        for (int k = 0; k < kAhead; ++k) {
+            const double g = mk[k] > -INFINITY ? exp(mk[k] - M) : 0.0;
+            s1 += ak[k] * g;
+            s2 += bk[k] * g * g;
+        }
+        m = M;
     }
-    if (lane == 0) ess[u] = (m > -INFINITY) ? s1 * s1 / s2 : 0.0;
+    double W = m;
+#pragma unroll
+    for (int sh = 1; sh < 64; sh <<= 1) W = fmax(W, __shfl_xor(W, sh, 64));
+    if (W == -INFINITY) {
+        if (lane == 0) ess[u] = 0.0;
+        return;
+    }
+    const double f = m > -INFINITY ? exp(m - W) : 0.0;
+    s1 *= f;
+    s2 *= f * f;
+#pragma unroll
+    for (int sh = 1; sh < 64; sh <<= 1) {  // a + b = b + a: every lane ends with the same sums
+        s1 += __shfl_xor(s1, sh, 64);
+        s2 += __shfl_xor(s2, sh, 64);
+    }
+    if (lane == 0) ess[u] = s1 * s1 / s2;
 }
 
 // C-phase header (doubles): [0] flags word (bit 0: NaN or +inf log-weight),
@@ -680,8 +699,10 @@ extern "C" int sps_correct(sps_ctx* c, const double* theta, double* ll, int32_t 
     if (prec != SPS_FP64 && prec != SPS_FP32 && prec != SPS_BF16X3)
         return fail(c, SPS_ERR_ARG, "sps_correct: unknown precision %d", prec);
     const int64_t P = (int64_t)J * N;
-    // Observations per block: doubling from 64 up to 2048, the block buffer
-    // (P x block FP64) capped at 256 MiB.
+    // Observations per block: growing fourfold from 64 up to 2048, the block
+    // buffer (P x block FP64) capped at 256 MiB.  A block's launches and
+    // read-back cost more than evaluating a few hundred observations past the
+    // crossing, so fewer, larger blocks win once a cycle outlasts the first.
     const int32_t kMaxBlock =
         (int32_t)std::max<int64_t>(kScanChunk, std::min<int64_t>(2048, (int64_t(32) << 20) / P / kScanChunk * kScanChunk));
     const int32_t nchmax = (kMaxBlock + 2 * kScanChunk - 1) / kScanChunk;  // chunks of a block at any alignment
@@ -704,7 +725,7 @@ extern "C" int sps_correct(sps_ctx* c, const double* theta, double* ll, int32_t 
 
     SPS_CHECK(fill(c, hdr, kHdr, 0.0));
     const unsigned* done = (const unsigned*)hdr + kDoneWord;
-    // Blocks of observations double in size.  The host queues block i + 1
+    // Blocks of observations grow fourfold.  The host queues block i + 1
     // before it reads block i's outcome; a block queued after the crossing
     // (or after a NaN) finds the done word set and its launches do nothing.
     // The running log-weights carried from one block to the next alternate
@@ -743,7 +764,7 @@ extern "C" int sps_correct(sps_ctx* c, const double* theta, double* ll, int32_t 
     SPS_CHECK(launch_block(cur));
     for (;;) {
         const int64_t s1 = cur.s + cur.nb;
-        const int32_t B1 = std::min(2 * B, kMaxBlock);
+        const int32_t B1 = std::min(4 * B, kMaxBlock);
         Block nxt{};
         const bool ahead = s1 < c->T;
         if (ahead) {

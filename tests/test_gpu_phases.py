@@ -79,7 +79,7 @@ def test_correct_matches_oracle(orc, prec, C, k, J, N, s0, scale):
 def test_correct_full_size_binary30(orc, prec, scale):
     """The C phase at the binary30 shape (16384 particles, k = 30) from
     observation 9000 (not 32-aligned): scale 0.02 crosses the ESS threshold in
-    the fourth block (t_end 9524 in the oracle), scale 0.01 runs to T."""
+    the third block (t_end 9524 in the oracle), scale 0.01 runs to T."""
     need_gpu()
     sps = _sps()
     w = synth.workload("binary30")
