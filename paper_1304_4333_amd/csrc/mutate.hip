@@ -325,14 +325,18 @@ __global__ __launch_bounds__(256) void cov_partial_small_kernel(const double* __
     }
 }
 
-// d <= 64: right-looking Cholesky in LDS with 256 threads.  Per column j the
-// pivot's square root and reciprocal are formed by every thread (same value),
-// the column is scaled, and thread (ty, tx) of a 16 x 16 grid updates the
-// trailing entries (j + 1 + ty + 16 a, j + 1 + tx + 16 b) on or below the
-// diagonal.  A non-positive or non-finite pivot sets kFlagNotPD.
+// d <= 64: right-looking Cholesky in LDS with 256 threads, one barrier per
+// column.  Column j stays unscaled in LDS: every thread forms the pivot's
+// square root and reciprocal (same value), and thread (ty, tx) of a 16 x 16
+// grid updates the trailing entries (j + 1 + ty + 16 a, j + 1 + tx + 16 b) on
+// or below the diagonal with the scaled values A[r][j] / l_jj, A[q][j] / l_jj
+// formed on the fly.  The update writes only columns above j, so no thread
+// waits for the scaling; L takes the scaled columns at the end.  A
+// non-positive or non-finite pivot sets kFlagNotPD.
 __global__ __launch_bounds__(256) void cholesky_small_kernel(const double* __restrict__ V, int32_t d,
                                                              double* __restrict__ L, unsigned* flags) {
     __shared__ double A[kSmallD][kSmallD + 1];
+    __shared__ double dl[kSmallD], di[kSmallD];
     const int t = threadIdx.x, tx = t & 15, ty = t >> 4;
     for (int r = ty; r < d; r += 16)
         for (int q = tx; q < d; q += 16) A[r][q] = (q <= r) ? V[r * d + q] : 0.0;
@@ -345,18 +349,19 @@ __global__ __launch_bounds__(256) void cholesky_small_kernel(const double* __res
         }
         const double ljj = sqrt(piv);
         const double inv = 1.0 / ljj;
-        __syncthreads();  // every thread has read the pivot
-        if (t == j) A[j][j] = ljj;
-        else if (t > j && t < d) A[t][j] *= inv;
-        __syncthreads();
+        if (t == 0) {
+            dl[j] = ljj;
+            di[j] = inv;
+        }
         for (int r = j + 1 + ty; r < d; r += 16) {
-            const double lr = A[r][j];
-            for (int q = j + 1 + tx; q <= r; q += 16) A[r][q] -= lr * A[q][j];
+            const double lr = A[r][j] * inv;
+            for (int q = j + 1 + tx; q <= r; q += 16) A[r][q] -= lr * (A[q][j] * inv);
         }
         __syncthreads();
     }
     for (int r = ty; r < d; r += 16)
-        for (int q = tx; q < d; q += 16) L[r * d + q] = A[r][q];
+        for (int q = tx; q < d; q += 16)
+            L[r * d + q] = q < r ? A[r][q] * di[q] : (q == r ? dl[q] : 0.0);
 }
 
 // d <= 64: W = L^-1 by forward substitution, one column per thread (the
@@ -725,10 +730,20 @@ __global__ __launch_bounds__(256) void accept_kernel(
             const double zb = w0 ? w1[p * d + i] : (b[i] - mu[i]) * isd[i];
             q0 += za * za;
             q1 += zb * zb;
-            if (mala) {
-                vv += v[p * d + i] * v[p * d + i];
-                const double zi = z ? z[p * d + i] : philox_normal(seed, zstream, p, i, d);
-                zz += zi * zi;
+            if (mala) vv += v[p * d + i] * v[p * d + i];
+        }
+        if (mala) {  // |z|^2 by Box-Muller pairs (elements 2 j, 2 j + 1), read or drawn alike
+            for (int32_t j = sub; 2 * j < d; j += kAccLanes) {
+                double z0, z1;
+                if (z) {
+                    z0 = z[p * d + 2 * j];
+                    z1 = 2 * j + 1 < d ? z[p * d + 2 * j + 1] : 0.0;
+                } else {
+                    philox_normal_pair(seed, zstream, p, j, d, z0, z1);
+                    if (2 * j + 1 >= d) z1 = 0.0;
+                }
+                zz += z0 * z0;
+                zz += z1 * z1;
             }
         }
         q0 = sum16(q0);
