@@ -239,6 +239,46 @@ def test_mutate_matches_oracle(orc, kind, prec, C, k, J, N, t):
 
 
 @pytest.mark.parametrize("kind", [0, 1])
+def test_mutate_full_size_binary30(orc, kind):
+    """One M step at the binary30 shape in the bench's precision (FP32
+    likelihood over all 10000 observations, 16384 particles: 1024 MH
+    workgroups, so every accepted-count slot takes several of them), against
+    the oracle on the same normals and uniforms."""
+    need_gpu()
+    sps = _sps()
+    w = synth.workload("binary30")
+    X, y, B = synth.make_data(w)
+    P, d, t, h, prec = w.J * w.N, w.d, w.T, 0.3, 1
+    th = synth.make_particles(P, d, scale=0.02, seed=71, center=B.reshape(-1))
+    ll, gr = orc.loglik(X, y, 2, th, 0, t, grad=True)
+    z = synth.make_normals(P, d, seed=72)
+    u = synth.make_uniforms(P, seed=73)
+    print(f"mutate binary30 full size kind={kind}", flush=True)
+    ctx = make_ctx(X, y, 2, prior_sd=w.prior_sd)
+    thg, llg = to_gpu(th), to_gpu(ll)
+    grg = to_gpu(gr) if kind == 1 else None
+    rate = sps.sps_mutate(ctx, thg, llg, grg, w.J, w.N, t, h, kind, prec, z=to_gpu(z), u=to_gpu(u))
+    th_o, ll_o, gr_o, rate_o, la_o, acc_o = orc.mutate(X, y, 2, 0.0, w.prior_sd, th, ll,
+                                                       gr if kind else None, w.J, w.N, t, h, kind, z, u)
+    th_g = thg.cpu().numpy()
+    acc_g = np.any(th_g != th, axis=1)
+    assert 0.0 < acc_g.mean() < 1.0
+    assert rate == acc_g.sum() / P  # the host's sum of the count slots
+    bound = 2e-4 * max(1.0, np.abs(ll_o).max())
+    margin = np.abs(np.log(u) - la_o)
+    diff = acc_g != acc_o
+    assert np.all(margin[diff] < bound), f"{diff.sum()} decisions differ beyond the error bound"
+    assert diff.sum() <= P // 1000
+    same = ~diff
+    assert rel_err(th_g[same], th_o[same]).max() <= 1e-9
+    assert rel_err(llg.cpu().numpy()[same], ll_o[same]).max() <= 1e-4
+    if kind == 1:
+        g_g = grg.cpu().numpy()[same]
+        nrm = np.linalg.norm(g_g - gr_o[same], axis=1) / np.maximum(1.0, np.linalg.norm(gr_o[same], axis=1))
+        assert nrm.max() <= 1e-3
+
+
+@pytest.mark.parametrize("kind", [0, 1])
 @pytest.mark.parametrize("C,k", [(2, 30), (2, 80)])
 def test_mutate_drawn_variates_match_explicit(orc, kind, C, k):
     """Without z and u the M step draws them from Philox (seed, stream) and
