@@ -718,8 +718,9 @@ extern "C" int sps_correct(sps_ctx* c, const double* theta, double* ll, int32_t 
     const int64_t P = (int64_t)J * N;
     // Observations per block: growing fourfold from 64 up to 2048, the block
     // buffer (P x block FP64) capped at 256 MiB.  A block's launches and
-    // read-back cost more than evaluating a few hundred observations past the
-    // crossing, so fewer, larger blocks win once a cycle outlasts the first.
+    // read-back cost about as much as a few hundred observations of
+    // per-observation work, so fewer, larger blocks win once a cycle outlasts
+    // the first.
     const int32_t kMaxBlock =
         (int32_t)std::max<int64_t>(kScanChunk, std::min<int64_t>(2048, (int64_t(32) << 20) / P / kScanChunk * kScanChunk));
     const int32_t nchmax = (kMaxBlock + 2 * kScanChunk - 1) / kScanChunk;  // chunks of a block at any alignment
