@@ -284,23 +284,29 @@ constexpr int kDoneWord = 2;  // the done word as an unsigned index (byte 8)
 // turns the launches of any later block into no-ops.
 __global__ __launch_bounds__(256) void correct_find_kernel(const double* __restrict__ ess, int32_t nb, double thr,
                                                            int64_t s, int64_t T, double* hdr) {
-    __shared__ int32_t red[256];
+    __shared__ int32_t red[4];
     unsigned* words = (unsigned*)hdr;
     if (words[kDoneWord] != 0u) return;  // the same value for the whole workgroup
+    // thread t tests u = t, t + 256, ... with eight loads in flight (a block has
+    // at most 2048 rows: one round); the first hit is its smallest u
+    constexpr int kAhead = 8;
     int32_t first = INT32_MAX;
-    for (int32_t u = threadIdx.x; u < nb; u += 256)
-        if (ess[u] < thr || s + u + 1 == T) {
-            first = u;
-            break;
+    for (int32_t u0 = threadIdx.x; u0 < nb && first == INT32_MAX; u0 += 256 * kAhead) {
+        double e[kAhead];
+#pragma unroll
+        for (int k = 0; k < kAhead; ++k) e[k] = u0 + 256 * k < nb ? ess[u0 + 256 * k] : INFINITY;
+#pragma unroll
+        for (int k = 0; k < kAhead; ++k) {
+            const int32_t u = u0 + 256 * k;
+            if (first == INT32_MAX && u < nb && (e[k] < thr || s + u + 1 == T)) first = u;
         }
-    red[threadIdx.x] = first;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) red[threadIdx.x] = min(red[threadIdx.x], red[threadIdx.x + w]);
-        __syncthreads();
     }
+#pragma unroll
+    for (int sh = 32; sh > 0; sh >>= 1) first = min(first, __shfl_xor(first, sh, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = first;
+    __syncthreads();
     if (threadIdx.x == 0) {
-        const int32_t f = red[0];
+        const int32_t f = min(min(red[0], red[1]), min(red[2], red[3]));
         hdr[2] = f == INT32_MAX ? -1.0 : (double)f;
         hdr[3] = f == INT32_MAX ? 0.0 : ess[f];
         if (f != INT32_MAX || (words[0] & 1u)) words[kDoneWord] = 1u;
