@@ -10,26 +10,24 @@
 namespace sps {
 
 // ------------------------------------------------------------------ block reductions
-// 256-thread block sum / max in FP64 with a fixed tree order (deterministic).
+// 256-thread block sum / max in FP64 in a fixed order (deterministic): a
+// butterfly inside each wave (a + b = b + a, so every lane ends with the same
+// value), then (w0 + w1) + (w2 + w3) over the four waves; two barriers.
 __device__ double block_sum256(double v, double* red) {
-    red[threadIdx.x] = v;
+#pragma unroll
+    for (int sh = 32; sh > 0; sh >>= 1) v += __shfl_xor(v, sh, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
     __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-        __syncthreads();
-    }
-    double r = red[0];
+    const double r = (red[0] + red[1]) + (red[2] + red[3]);
     __syncthreads();
     return r;
 }
 __device__ double block_max256(double v, double* red) {
-    red[threadIdx.x] = v;
+#pragma unroll
+    for (int sh = 32; sh > 0; sh >>= 1) v = fmax(v, __shfl_xor(v, sh, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
     __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
-        __syncthreads();
-    }
-    double r = red[0];
+    const double r = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
     __syncthreads();
     return r;
 }
@@ -390,18 +388,38 @@ constexpr int kResMaxN = 4096;
 constexpr int kResPer = kResMaxN / kResThreads;  // elements per thread
 
 // Inclusive block scan of one uint64 per thread (1024 threads).
+__device__ __forceinline__ uint64_t shfl_up_u64(uint64_t v, int off) {
+    const unsigned lo = __shfl_up((unsigned)v, off, 64);
+    const unsigned hi = __shfl_up((unsigned)(v >> 32), off, 64);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Inclusive scan over the block's kResThreads threads (exact integers, so the
+// grouping does not matter): a shuffle scan inside each wave, a scan of the
+// 16 wave totals by wave 0, two barriers.  tmp holds at least 32 entries.
+constexpr int kResWaves = kResThreads / 64;
 __device__ uint64_t block_scan_u64(uint64_t v, uint64_t* tmp) {
-    const int t = threadIdx.x;
-    tmp[t] = v;
-    __syncthreads();
-    for (int off = 1; off < kResThreads; off <<= 1) {
-        const uint64_t add = t >= off ? tmp[t - off] : 0;
-        __syncthreads();
-        tmp[t] += add;
-        __syncthreads();
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    uint64_t x = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint64_t y = shfl_up_u64(x, off);
+        if (lane >= off) x += y;
     }
-    const uint64_t r = tmp[t];
+    if (lane == 63) tmp[wv] = x;
     __syncthreads();
+    if (wv == 0) {
+        uint64_t s = lane < kResWaves ? tmp[lane] : 0;
+#pragma unroll
+        for (int off = 1; off < kResWaves; off <<= 1) {
+            const uint64_t y = shfl_up_u64(s, off);
+            if (lane >= off) s += y;
+        }
+        if (lane < kResWaves) tmp[kResWaves + lane] = s;
+    }
+    __syncthreads();
+    const uint64_t r = x + (wv > 0 ? tmp[kResWaves + wv - 1] : 0);
+    __syncthreads();  // tmp is free for the next call
     return r;
 }
 
@@ -450,15 +468,14 @@ __global__ __launch_bounds__(kResThreads) void resample_kernel(
             m = fmax(m, lw[n]);
         }
         if (bad) atomicOr(flags, 2u);
-        // block max over the 1024 threads, fixed tree order
-        __shared__ double dred[kResThreads];
-        dred[t] = m;
+        // block max over the 1024 threads (fmax is exact: any order gives it)
+        __shared__ double dred[kResWaves];
+#pragma unroll
+        for (int sh = 32; sh > 0; sh >>= 1) m = fmax(m, __shfl_xor(m, sh, 64));
+        if ((t & 63) == 0) dred[t >> 6] = m;
         __syncthreads();
-        for (int ww = kResThreads / 2; ww > 0; ww >>= 1) {
-            if (t < ww) dred[t] = fmax(dred[t], dred[t + ww]);
-            __syncthreads();
-        }
-        m = dred[0];
+#pragma unroll
+        for (int q = 0; q < kResWaves; ++q) m = fmax(m, dred[q]);
         __syncthreads();
         if (!(m > -INFINITY) || bad) {
             if (t == 0) atomicOr(flags, 1u);
