@@ -342,17 +342,33 @@ __global__ void logml_group_kernel(const double* __restrict__ log_w, int32_t N,
                                    double* __restrict__ logml_j, unsigned* flags) {
     __shared__ double red[256];
     const double* lw = log_w + (int64_t)blockIdx.x * N;
+    // thread t takes n = t, t + 256, ... in that order, four loads in flight
+    constexpr int kAhead = 4;
     double m = -INFINITY;
     bool bad = false;
-    for (int32_t n = threadIdx.x; n < N; n += 256) {
-        bad |= isnan(lw[n]) || lw[n] == INFINITY;
-        m = fmax(m, lw[n]);
+    for (int32_t n0 = threadIdx.x; n0 < N; n0 += 256 * kAhead) {
+        double v[kAhead];
+#pragma unroll
+        for (int k = 0; k < kAhead; ++k) v[k] = n0 + 256 * k < N ? lw[n0 + 256 * k] : -INFINITY;
+#pragma unroll
+        for (int k = 0; k < kAhead; ++k) {
+            bad |= isnan(v[k]) || v[k] == INFINITY;
+            m = fmax(m, v[k]);
+        }
     }
     if (bad) atomicOr(flags, 2u);
     m = block_max256(m, red);
     double s = 0.0;
-    if (m > -INFINITY)
-        for (int32_t n = threadIdx.x; n < N; n += 256) s += exp(lw[n] - m);
+    if (m > -INFINITY) {
+        for (int32_t n0 = threadIdx.x; n0 < N; n0 += 256 * kAhead) {
+            double v[kAhead];
+#pragma unroll
+            for (int k = 0; k < kAhead; ++k) v[k] = n0 + 256 * k < N ? lw[n0 + 256 * k] : -INFINITY;
+#pragma unroll
+            for (int k = 0; k < kAhead; ++k)
+                if (n0 + 256 * k < N) s += exp(v[k] - m);
+        }
+    }
     s = block_sum256(s, red);
     if (threadIdx.x == 0) {
         if (m > -INFINITY && !bad) logml_j[blockIdx.x] += m + log(s) - log((double)N);
