@@ -220,7 +220,8 @@ def _call_times(ctx, w, precision, reps=5):
 
 
 PREC_SOURCES = {"fp64": ("loglik_fp64.hip",), "fp32": ("loglik_fp32.hip",),
-                "bf16x3": ("loglik_bf16.hip", "loglik_bf16_wide.hip", "loglik_bf16_c8.hip")}
+                "bf16x3": ("loglik_pipe.h", "loglik_pipe_grad.hip", "loglik_bf16.hip", "loglik_bf16_wide.hip",
+                           "loglik_bf16_c8.hip") + tuple(f"loglik_pipe_fwd_{g}.hip" for g in "abcd")}
 
 
 def kernel_digest(precision):
@@ -260,35 +261,97 @@ def measured_traffic(workload, kernel, precision):
         return None
 
 
+# MI355X published peaks: dense MFMA per input type (TFLOP/s), HBM3E (GB/s),
+# and the FP32 vector rate, 157.3 TFLOP/s = 78.6 T lane FMAs/s.  The
+# transcendental unit (exp2, log2, rcp) runs at a quarter of the FP32 lane
+# rate: 78.6 / 4 = 19.66 T ops/s (a microbenchmark of v_exp_f32 on one
+# MI355X measured 19.2 T/s).
+PEAK_HBM_GBS = 8000.0
+PEAK_TRANS_TOPS = 157.3 / 2 / 4
+MFMA_MULT = {"fp64": 1, "fp32": 1, "bf16x3": 3}  # MFMA products per multiply-add
+
+
+def work_per_po(w, grad):
+    """Algorithmic work per particle x observation of one likelihood launch:
+    MFMA flops as issued (the BF16x3 split issues three products per
+    multiply-add; 2 k (C-1) flops per product, twice with the adjoint), and
+    transcendentals (C - 1 exponentials and one logarithm, one reciprocal
+    more with the adjoint)."""
+    flops = MFMA_MULT[w.precision] * 2 * w.k * (w.C - 1) * (2 if grad else 1)
+    trans = w.C + (1 if grad else 0)
+    return flops, trans
+
+
+def alg_bytes(w, t_end, grad):
+    """Algorithmic HBM bytes of one full-range launch: X (and X^T for the
+    adjoint) once in the kernel's format, theta once, ll (and grad) out."""
+    xb = {"fp64": 8, "fp32": 4, "bf16x3": 4}[w.precision]
+    x = t_end * w.k * xb * (2 if grad else 1)
+    return x + w.P * w.d * 8 + w.P * 8 + (w.P * w.d * 8 if grad else 0)
+
+
 def roofline(w, res):
-    """Dominant likelihood kernel: algorithmic MFMA flops per launch over its
-    average HIP-event duration.  Forward: 2 k (C-1) flops per particle x
-    observation; forward + adjoint: twice that."""
+    """Dominant likelihood kernel: its per-launch time bounds from the MFMA
+    peak of its input type, the transcendental rate and HBM, over its
+    average HIP-event duration; `bound` is the largest of the three."""
     kt = res["kt"]
     name = max(("loglik", "loglik_grad"), key=lambda n: kt[n][1])
     n, ms = kt[name]
     if n == 0:
         return None, None
-    per_po = 2 * w.k * (w.C - 1) * (2 if name == "loglik_grad" else 1)
+    grad = name == "loglik_grad"
     t_end = int(np.median(res["t_ends"]))
-    flops = per_po * res["P"] * t_end
+    units = res["P"] * t_end
+    flops_po, trans_po = work_per_po(w, grad)
+    flops, trans, nbytes = flops_po * units, trans_po * units, alg_bytes(w, t_end, grad)
     avg_s = ms / n * 1e-3
-    achieved = flops / avg_s / 1e12
-    dt = DTYPE[w.precision]
-    peak = PEAK_TFLOPS[dt]
-    return dict(bound="mfma", achieved=round(achieved, 3), peak=peak, unit="TFLOP/s",
-                frac=round(achieved / peak, 4), traffic=measured_traffic(w.name, name, w.precision)), \
-        dict(kernel=name, launches=n, avg_us=round(ms / n * 1e3, 2), flops_per_launch=flops)
+    peak_mfma = PEAK_TFLOPS[DTYPE[w.precision]]
+    bounds = {"mfma": flops / (peak_mfma * 1e12), "alu": trans / (PEAK_TRANS_TOPS * 1e12),
+              "hbm": nbytes / (PEAK_HBM_GBS * 1e9)}
+    bound = max(bounds, key=bounds.get)
+    if bound == "mfma":
+        achieved, peak, unit = flops / avg_s / 1e12, peak_mfma, "TFLOP/s"
+    elif bound == "alu":
+        achieved, peak, unit = trans / avg_s / 1e12, PEAK_TRANS_TOPS, "TFLOP/s"
+    else:
+        achieved, peak, unit = nbytes / avg_s / 1e9, PEAK_HBM_GBS, "GB/s"
+    info = dict(kernel=name, launches=n, avg_us=round(ms / n * 1e3, 2), units_per_launch=units,
+                mfma_flops_per_po=flops_po, transcendentals_per_po=trans_po,
+                alg_bytes_per_launch=nbytes,
+                time_bounds_us={k: round(v * 1e6, 1) for k, v in bounds.items()})
+    return dict(bound=bound, achieved=round(achieved, 3), peak=peak, unit=unit,
+                frac=round(achieved / peak, 4), traffic=measured_traffic(w.name, name, w.precision)), info
 
 
-def cpu_baseline(w, seconds, seed=1):
-    """The FP64 oracle on the same step, on a particle subsample of 16 groups
-    of 32 (512 particles), repeated for about `seconds`."""
+def cpu_info():
+    """CPU model, sockets x cores x threads per core and online CPUs of this host."""
+    info = {"nproc": os.cpu_count()}
+    try:
+        import subprocess
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        kv = {}
+        for line in out.splitlines():
+            if ":" in line:
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+        info.update(model=kv.get("Model name"), sockets=kv.get("Socket(s)"),
+                    cores_per_socket=kv.get("Core(s) per socket"), threads_per_core=kv.get("Thread(s) per core"))
+    except Exception as e:  # lscpu missing: report what os gives
+        info["lscpu"] = f"unavailable ({e.__class__.__name__})"
+    try:
+        info["affinity"] = len(os.sched_getaffinity(0))
+    except AttributeError:
+        pass
+    return info
+
+
+def _oracle_steps(w, J, N, seconds, seed):
+    """The oracle on the benchmark step for J groups of N particles, repeated
+    for about `seconds` (at least once); returns (evals, elapsed, steps)."""
     from oracle import oracle as O
     from paper_1304_4333_amd import synth
 
     X, y, B = synth.make_data(w)
-    J, N = 16, 32
     P, d, T = J * N, w.d, w.T
     s0 = max(0, T - C_BLOCK)
     th0 = synth.make_particles(w.P, d, scale=0.02, seed=seed, center=B.reshape(-1))[:P]
@@ -312,11 +375,52 @@ def cpu_baseline(w, seconds, seed=1):
         steps += 1
         el = time.perf_counter() - t0
         if el >= seconds:
-            break
-    cores = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1)
-    return dict(value=round(evals / el, 1), unit="particle-obs evals/s", cores=cores, kind="oracle",
-                sample=f"{steps} steps of the same cycle on 512 of the {w.P} particles "
-                       f"(16 groups x 32), {el:.1f} s, OpenMP over particles")
+            return evals, el, steps
+
+
+def _oracle_loglik_rate(w, P, seconds, seed):
+    """Full-data oracle log-likelihood evaluations on P particles, repeated
+    for about `seconds` (at least once): particle-obs evals per second."""
+    from oracle import oracle as O
+    from paper_1304_4333_amd import synth
+
+    X, y, B = synth.make_data(w)
+    th = synth.make_particles(w.P, w.d, scale=0.02, seed=seed, center=B.reshape(-1))[:P]
+    n = 0
+    t0 = time.perf_counter()
+    while True:
+        O.loglik(X, y, w.C, th, 0, w.T)
+        n += 1
+        el = time.perf_counter() - t0
+        if el >= seconds:
+            return n * P * w.T / el, n, el
+
+
+def cpu_baseline(w, seconds, seed=1):
+    """The FP64 oracle on the same step as the GPU benchmark, on a particle
+    subsample (its cost is linear in the particle count), timed on all cores
+    of this host; and, on one core, its full-data log-likelihood evaluation
+    (the step's dominant part) on 16 particles."""
+    from oracle import oracle as O
+
+    # the subsample's pooled covariance must stay positive definite after
+    # resampling (which repeats particles): at least four particles per
+    # parameter, in 16 groups of 32, or 4 groups of a multiple of 32 for large d
+    if 16 * 32 >= 4 * w.d:
+        J_all, N_all = 16, 32
+    else:
+        J_all, N_all = 4, -(-w.d // 32) * 32
+    cores_all = O.threads(int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1))
+    e_all, t_all, s_all = _oracle_steps(w, J_all, N_all, seconds, seed)
+    O.threads(1)
+    r_one, n_one, t_one = _oracle_loglik_rate(w, 16, seconds / 3, seed)
+    O.threads(cores_all)
+    return dict(value=round(e_all / t_all, 1), unit="particle-obs evals/s", cores=cores_all, kind="oracle",
+                sample=f"{s_all} steps of the benchmark step on {J_all * N_all} of the {w.P} particles "
+                       f"({J_all} groups x {N_all}), {t_all:.1f} s, OpenMP over particles on {cores_all} "
+                       f"threads; one thread: {n_one} full-data log-likelihood evaluations of 16 particles, "
+                       f"{r_one:.4g} evals/s, {t_one:.1f} s",
+                one_thread_loglik_value=round(r_one, 1), host=cpu_info())
 
 
 def kernel_table(names, reps=5):
@@ -377,13 +481,16 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="binary30")
+    ap.add_argument("--workload", default="multi6")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sps", action="store_true", help="skip the fixed-NSE SPS comparison")
-    ap.add_argument("--sps-seeds", type=int, default=2)
-    ap.add_argument("--rw-hmin", type=float, default=0.1,
-                    help="lower bound of the RW step-size factor in the fixed-NSE comparison")
+    ap.add_argument("--sps-workload", default="ar100",
+                    help="workload of the fixed-NSE SPS comparison (FP64 RW against BF16x3 MALA)")
+    ap.add_argument("--sps-seeds", type=int, default=1)
+    ap.add_argument("--rw-hmin", type=float, default=0.01,
+                    help="lower bound of the RW step-size factor in the fixed-NSE comparison "
+                         "(the paper's 0.1 is above the RW optimum 2.38^2/d at d = 100)")
     ap.add_argument("--kernel-table", default=None,
                     help="comma-separated workloads: print full-data loglik/grad rates instead")
     ap.add_argument("--design-sweep", action="store_true",
@@ -406,7 +513,7 @@ def main():
         return
     if args.sps_only:
         from paper_1304_4333_amd import synth
-        print(json.dumps(sps_fixed_nse(synth.workload(args.workload), list(range(1, 1 + args.sps_seeds)),
+        print(json.dumps(sps_fixed_nse(synth.workload(args.sps_workload), list(range(1, 1 + args.sps_seeds)),
                                        rw_hmin=args.rw_hmin)))
         return
     if args.gpus != 1:
@@ -418,7 +525,11 @@ def main():
     res = gpu_bench(w, args.steps, args.warmup)
     value = res["evals"] / res["elapsed"]
     roof, kinfo = roofline(w, res)
-    sps_cmp = None if args.no_sps else sps_fixed_nse(w, list(range(1, 1 + args.sps_seeds)))
+    sps_cmp = None
+    if not args.no_sps:
+        ws = synth.workload(args.sps_workload)
+        sps_cmp = dict(sps_fixed_nse(ws, list(range(1, 1 + args.sps_seeds)), rw_hmin=args.rw_hmin),
+                       workload=_workload_desc(ws))
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(w, args.cpu_seconds)

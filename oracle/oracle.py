@@ -95,8 +95,15 @@ def lib():
         L.orc_sps_run_fixed.argtypes = [_d, _i32, ct.c_int64, ct.c_int32, ct.c_int32, _d, _d,
                                         ct.POINTER(Config), ct.c_int32, _i64, _i32, _d, _d, _d,
                                         _d, _d, _d, _d, ct.POINTER(Summary)]
+        L.orc_threads.argtypes = [ct.c_int]
+        L.orc_threads.restype = ct.c_int
         _lib = L
     return _lib
+
+
+def threads(n: int = 0) -> int:
+    """Set the oracle's OpenMP thread count (n > 0); return the count in use."""
+    return int(lib().orc_threads(int(n)))
 
 
 def _p(a, typ):

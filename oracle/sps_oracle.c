@@ -16,6 +16,7 @@
 #include "sps_oracle.h"
 
 #include <math.h>
+#include <omp.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -927,4 +928,12 @@ out:
     free(th2); free(grad); free(ll2); free(lw); free(z); free(u); free(u53); free(anc); free(g);
     free(logml_j); free(xbar);
     return status;
+}
+
+/* Threads of the OpenMP loops over particles: n > 0 sets the count; the
+ * count in use is returned.  (Used to time the oracle on one core and on
+ * all cores; no arithmetic of the method depends on it.) */
+int orc_threads(int n) {
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
 }

@@ -30,6 +30,9 @@ enum { ORC_RESIDUAL = 0, ORC_MULTINOMIAL = 1 };
 
 /* Counter-based random numbers (Philox4x32-10, Salmon et al. SC'11). */
 void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+
+/* OpenMP thread count: n > 0 sets it; returns the count in use. */
+int orc_threads(int n);
 void orc_u53(uint64_t seed, uint64_t stream, int64_t count, uint64_t* out);
 void orc_uniforms(uint64_t seed, uint64_t stream, int64_t count, double* out);
 void orc_normals(uint64_t seed, uint64_t stream, int64_t P, int32_t d, double* out);

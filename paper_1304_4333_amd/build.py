@@ -33,10 +33,18 @@ CFLAGS = [
 # the default heuristic inserts around the epilogue.  Measured faster for the
 # FP32 and BF16 kernels; the FP64 unit stays on the default assignment (the
 # compiler fails on some FP64 instantiations with the flag).
+# The pipelined BF16x3 kernels take it where it measured faster: the forward
+# kernels for C >= 4 (multi6 17.3 against 19.0 ms) and the binary adjoint
+# kernel (ar100 3.03 against 3.15 ms), not the binary forward kernel (ar100
+# 1.41 ms without, 1.60 ms with).
 FILE_FLAGS = {
     "loglik_fp32.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
     "loglik_bf16.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
     "loglik_bf16_wide.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+    "loglik_pipe_fwd_b.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+    "loglik_pipe_fwd_c.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+    "loglik_pipe_fwd_d.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+    "loglik_pipe_grad.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
 }
 
 
@@ -63,13 +71,9 @@ def _compile(src: str, incremental: bool) -> str:
     if incremental and os.path.exists(obj):
         return obj
     tmp = obj + ".tmp"
+    # one set of flags per unit: a failure is a build error, never a silent
+    # rebuild with other options (the object digest names the flags used)
     r = subprocess.run([HIPCC] + _flags(src) + ["-c", src, "-o", tmp], capture_output=True, text=True)
-    if r.returncode != 0 and FILE_FLAGS.get(os.path.basename(src)):
-        # the register-assignment option has crashed this compiler on some
-        # heavily spilling instantiations: build the unit without it instead
-        sys.stderr.write(f"warning: {os.path.basename(src)} failed with {FILE_FLAGS[os.path.basename(src)]}; "
-                         "compiling it with the default options\n")
-        r = subprocess.run([HIPCC] + CFLAGS + ["-c", src, "-o", tmp], capture_output=True, text=True)
     err = "\n".join(l for l in r.stderr.splitlines() if "not a recognized feature" not in l)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed on {src}:\n{err}")

@@ -3,6 +3,7 @@
 #include <algorithm>
 
 #include "loglik_kernel.h"
+#include "loglik_pipe.h"
 
 namespace sps {
 
@@ -95,11 +96,14 @@ int fill(sps_ctx* c, double* p, int64_t n, double v) {
     return launched(c, "fill_kernel");
 }
 
+// BF16x3 full-range calls of the shapes in bf16_pipe_shape run the pipelined
+// kernel (loglik_pipe.h); every other call runs loglik_kernel.h.
 static LoglikEntry lookup(int prec, int nc, int ks, int mode) {
     switch (prec) {
         case SPS_FP64: return lookup_fp64(nc, ks, mode);
         case SPS_FP32: return lookup_fp32(nc, ks, mode);
-        case SPS_BF16X3: return lookup_bf16(nc, ks, mode);
+        case SPS_BF16X3:
+            return bf16_pipe_shape(nc, ks, mode) ? lookup_pipe(nc, ks, mode == MODE_GRAD) : lookup_bf16(nc, ks, mode);
         default: return LoglikEntry{};
     }
 }

@@ -8,9 +8,9 @@ namespace sps {
 LoglikEntry lookup_bf16_wide(int nc, int ks, int mode) {
 #define SPS_E(NC, KS)                                                                          \
     if (nc == NC && ks == KS)                                                                  \
-        return mode == MODE_GRAD     ? loglik_entry<SPS_BF16X3, NC, KS, MODE_GRAD>()                  \
-               : mode == MODE_PEROBS ? loglik_entry<SPS_BF16X3, NC, KS, MODE_PEROBS>()                \
-                                     : loglik_entry<SPS_BF16X3, NC, KS, MODE_FWD>();
+        return mode == MODE_GRAD     ? loglik_entry_bf16<NC, KS, MODE_GRAD>()                         \
+               : mode == MODE_PEROBS ? loglik_entry_bf16<NC, KS, MODE_PEROBS>()                       \
+                                     : loglik_entry_bf16<NC, KS, MODE_FWD>();
     SPS_E(5, 1)
     SPS_E(5, 2)
     SPS_E(5, 4)

@@ -595,15 +595,25 @@ __global__ __launch_bounds__(256) void loglik_kernel(LoglikArgs a) {
                         for (int b = 0; b < PW; ++b)
     #pragma unroll
                             for (int c = 0; c < NC; ++c) {
-                                // hi/lo split with the hardware round-to-nearest-even conversion
-                                bf16x8 Rh, Rl;
-    #pragma unroll
-                                for (int j = 0; j < 8; ++j) {
-                                    const float v = rres[j >> 2][j & 3][b][c];
-                                    const __bf16 hb = (__bf16)v;
-                                    Rh[j] = hb;
-                                    Rl[j] = (__bf16)(v - (float)hb);
+                                // hi = the upper 16 bits (truncation, one byte permute per
+                                // pair); lo = v - hi, exact in FP32, rounded in one packed
+                                // conversion per pair: hi + bf16(lo) is within 2^-16 |v| of v
+                                typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+                                typedef float f32x2 __attribute__((ext_vector_type(2)));
+                                typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+                                u32x4 wh, wl;
+#pragma unroll
+                                for (int w = 0; w < 4; ++w) {
+                                    const float v0 = rres[(2 * w) >> 2][(2 * w) & 3][b][c];
+                                    const float v1 = rres[(2 * w + 1) >> 2][(2 * w + 1) & 3][b][c];
+                                    const unsigned u0 = __float_as_uint(v0), u1 = __float_as_uint(v1);
+                                    wh[w] = __builtin_amdgcn_perm(u1, u0, 0x07060302u);
+                                    const float l0 = v0 - __uint_as_float(u0 & 0xFFFF0000u);
+                                    const float l1 = v1 - __uint_as_float(u1 & 0xFFFF0000u);
+                                    wl[w] = __builtin_bit_cast(unsigned, __builtin_convertvector((f32x2){l0, l1}, bf16x2));
                                 }
+                                const bf16x8 Rh = __builtin_bit_cast(bf16x8, wh);
+                                const bf16x8 Rl = __builtin_bit_cast(bf16x8, wl);
                                 gacc[b][c][q] = mfma(th8, Rh, gacc[b][c][q]);
                                 gacc[b][c][q] = mfma(th8, Rl, gacc[b][c][q]);
                                 gacc[b][c][q] = mfma(tl8, Rh, gacc[b][c][q]);
@@ -697,6 +707,23 @@ LoglikEntry loglik_entry() {
     e.ppb = particles_per_block<PREC, NC, KS, MODE>();
     e.target = Shape<PREC, NC, KS, MODE>::TARGET;
     return e;
+}
+
+// Full-range BF16x3 shapes run by the software-pipelined kernel
+// (loglik_pipe.h) instead of this one: the forward kernel at k > 32 (KS >= 2)
+// and the adjoint kernel for C = 2 at k > 32.  Measured on MI355X, the
+// pipelined kernel is faster there (multi6 forward 17.3 against 21.7 ms,
+// ar100 forward 1.4 against 2.8 ms and adjoint 3.0 against 5.6 ms); with
+// C > 2 the adjoint's registers exceed one wave's budget and this kernel is
+// faster (multi6 45.9 against 56.8 ms), as it is at k <= 32 (multi4,
+// binary30), where a step is too short for the per-step LDS staging.
+constexpr bool bf16_pipe_shape(int nc, int ks, int mode) {
+    return mode == MODE_FWD ? ks >= 2 : mode == MODE_GRAD ? (nc == 1 && ks >= 2) : false;
+}
+template <int NC, int KS, int MODE>
+LoglikEntry loglik_entry_bf16() {
+    if constexpr (bf16_pipe_shape(NC, KS, MODE)) return LoglikEntry{};
+    else return loglik_entry<SPS_BF16X3, NC, KS, MODE>();
 }
 
 // One lookup per precision, each defined in its own translation unit.

@@ -357,9 +357,11 @@ __global__ void logml_group_kernel(const double* __restrict__ log_w, int32_t N,
         }
     }
     if (bad) atomicOr(flags, 2u);
+    // any thread's bad weight voids the whole group's increment
+    const bool any_bad = __syncthreads_or(bad) != 0;
     m = block_max256(m, red);
     double s = 0.0;
-    if (m > -INFINITY) {
+    if (m > -INFINITY && !any_bad) {
         for (int32_t n0 = threadIdx.x; n0 < N; n0 += 256 * kAhead) {
             double v[kAhead];
 #pragma unroll
@@ -371,7 +373,7 @@ __global__ void logml_group_kernel(const double* __restrict__ log_w, int32_t N,
     }
     s = block_sum256(s, red);
     if (threadIdx.x == 0) {
-        if (m > -INFINITY && !bad) logml_j[blockIdx.x] += m + log(s) - log((double)N);
+        if (m > -INFINITY && !any_bad) logml_j[blockIdx.x] += m + log(s) - log((double)N);
         else if (!(m > -INFINITY)) atomicOr(flags, 1u);
     }
 }
@@ -484,6 +486,8 @@ __global__ __launch_bounds__(kResThreads) void resample_kernel(
             m = fmax(m, lw[n]);
         }
         if (bad) atomicOr(flags, 2u);
+        // a bad weight anywhere in the group sends it down the identity path
+        const bool any_bad = __syncthreads_or(bad) != 0;
         // block max over the 1024 threads (fmax is exact: any order gives it)
         __shared__ double dred[kResWaves];
 #pragma unroll
@@ -493,14 +497,17 @@ __global__ __launch_bounds__(kResThreads) void resample_kernel(
 #pragma unroll
         for (int q = 0; q < kResWaves; ++q) m = fmax(m, dred[q]);
         __syncthreads();
-        if (!(m > -INFINITY) || bad) {
+        if (!(m > -INFINITY) || any_bad) {
             if (t == 0) atomicOr(flags, 1u);
             if (t == 0) bad_s = 1;
         }
+        // weights only from a finite group maximum and no NaN / +inf anywhere
+        // (exp of those would be converted to an integer below)
+        const bool ok = m > -INFINITY && !any_bad;
 #pragma unroll
         for (int q = 0; q < kResPer; ++q) {
             const int32_t n = t * kResPer + q;
-            w[q] = (n < N && m > -INFINITY) ? (uint64_t)floor(exp(lw[n] - m) * 0x1p40) : 0;
+            w[q] = (n < N && ok) ? (uint64_t)floor(exp(lw[n] - m) * 0x1p40) : 0;
         }
     } else {
 #pragma unroll
