@@ -264,7 +264,15 @@ __global__ __launch_bounds__(256) void loglik_kernel(LoglikArgs a) {
     constexpr bool kNegRes = (NC == 1) && !F64;
     double* const g_out = GRAD ? a.out_g + (int64_t)split * a.P * a.d : nullptr;
     bool g_first = true;
-    // Add the FP32/FP64 adjoint tiles into the wave's slice of the output.
+    // The FP32 adjoint tiles are added into an FP64 copy every kFoldSteps
+    // steps.  That copy lives in LDS (one slot per lane and value, private to
+    // the wave) when the four waves' copies fit, and the gradient is written
+    // to HBM once at the end; otherwise it is the wave's slice of the output
+    // itself, read and written at every fold.
+    constexpr int kFoldVals = GRAD ? PW * NC * KBT * 4 : 1;
+    constexpr bool LFOLD = GRAD && !F64 && 4 * kFoldVals * 64 * 8 <= 160 * 1024;
+    __shared__ double fold_lds[LFOLD ? 4 * kFoldVals * 64 : 1];
+    double* const fold_w = fold_lds + (LFOLD ? wave * kFoldVals * 64 + lane : 0);
     auto fold = [&]() __attribute__((always_inline)) {
         if constexpr (GRAD) {
 #pragma unroll
@@ -276,17 +284,41 @@ __global__ __launch_bounds__(256) void loglik_kernel(LoglikArgs a) {
                     for (int q = 0; q < KBT; ++q) {
 #pragma unroll
                         for (int i = 0; i < 4; ++i) {
-                            const int kk = q * 16 + (F64 ? g + 4 * i : 4 * g + i);
-                            if (p < a.P && kk < a.k) {
-                                double* dst = g_out + p * a.d + c * a.k + kk;
-                                const double gv = (double)gacc[b][c][q][i];
-                                *dst = (g_first ? 0.0 : *dst) + (kNegRes ? -gv : gv);
+                            const double gv = (double)gacc[b][c][q][i];
+                            if constexpr (LFOLD) {
+                                double* sl = fold_w + (((b * NC + c) * KBT + q) * 4 + i) * 64;
+                                *sl = (g_first ? 0.0 : *sl) + gv;
+                            } else {
+                                const int kk = q * 16 + (F64 ? g + 4 * i : 4 * g + i);
+                                if (p < a.P && kk < a.k) {
+                                    double* dst = g_out + p * a.d + c * a.k + kk;
+                                    *dst = (g_first ? 0.0 : *dst) + (kNegRes ? -gv : gv);
+                                }
                             }
                         }
                         gacc[b][c][q] = Acc{0, 0, 0, 0};
                     }
             }
             g_first = false;
+        }
+    };
+    // LDS copy -> output, once (the binary residual's sign applied here)
+    auto fold_out = [&]() __attribute__((always_inline)) {
+        if constexpr (LFOLD) {
+#pragma unroll
+            for (int b = 0; b < PW; ++b) {
+                const int64_t p = pbase + b * 16 + r16;
+#pragma unroll
+                for (int c = 0; c < NC; ++c)
+#pragma unroll
+                    for (int q = 0; q < KBT; ++q)
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            const int kk = q * 16 + 4 * g + i;
+                            const double v = fold_w[(((b * NC + c) * KBT + q) * 4 + i) * 64];
+                            if (p < a.P && kk < a.k) g_out[p * a.d + c * a.k + kk] = kNegRes ? -v : v;
+                        }
+            }
         }
     };
 
@@ -660,6 +692,7 @@ __global__ __launch_bounds__(256) void loglik_kernel(LoglikArgs a) {
     }
     if constexpr (GRAD) {
         if (g_first || ((st_end - st_begin) % kFoldSteps) != 0) fold();
+        fold_out();
     }
 
     // ---- write the log-likelihood partial ----
