@@ -188,7 +188,10 @@ void orc_logprior(const double* theta, int64_t P, int32_t d, const double* mean,
 {
     double logdet = 0.0;
     for (int32_t i = 0; i < d; ++i) logdet += log(L[i * d + i]);
+#pragma omp parallel
+    {
     double* r = (double*)malloc(sizeof(double) * (d > 0 ? d : 1));
+#pragma omp for schedule(static)
     for (int64_t p = 0; p < P; ++p) {
         const double* th = theta + p * d;
         /* forward substitution L r = theta - mean */
@@ -212,6 +215,7 @@ void orc_logprior(const double* theta, int64_t P, int32_t d, const double* mean,
         }
     }
     free(r);
+    }
 }
 
 /* Algorithm 1 step 1: particles iid from the prior, theta = mean + L z. */
@@ -220,6 +224,7 @@ void orc_init_prior(const double* mean, const double* L, int32_t d, int64_t P,
 {
     double* z = (double*)malloc(sizeof(double) * (size_t)(P > 0 ? P : 1) * (d > 0 ? d : 1));
     orc_normals(seed, stream, P, d, z);
+#pragma omp parallel for schedule(static)
     for (int64_t p = 0; p < P; ++p)
         for (int32_t i = 0; i < d; ++i) {
             double s = mean[i];
@@ -488,11 +493,13 @@ void orc_gather(const int32_t* ancestor, int64_t P, int32_t m, const double* src
  * P - 1 (READING). */
 void orc_cov(const double* theta, int64_t P, int32_t d, double* mean, double* V)
 {
+#pragma omp parallel for schedule(static)
     for (int32_t i = 0; i < d; ++i) {
         double s = 0.0;
         for (int64_t p = 0; p < P; ++p) s += theta[p * d + i];
         mean[i] = s / (double)P;
     }
+#pragma omp parallel for schedule(dynamic)
     for (int32_t a = 0; a < d; ++a)
         for (int32_t b = 0; b < d; ++b) {
             double s = 0.0;
@@ -579,6 +586,7 @@ int orc_mutate_cov(const double* X, const int32_t* y, int64_t T, int32_t k, int3
     status = orc_cholesky(Sigma, d, L);
     if (status != ORC_OK) goto done;
     orc_logprior(theta, P, d, prior_mean, prior_L, lp0, glp0);
+#pragma omp parallel for schedule(static)
     for (int64_t p = 0; p < P; ++p) {
         const double* th = theta + p * d;
         double* q = prop + p * d;
@@ -603,6 +611,7 @@ int orc_mutate_cov(const double* X, const int32_t* y, int64_t T, int32_t k, int3
     if (status != ORC_OK) goto done;
     orc_logprior(prop, P, d, prior_mean, prior_L, lp1, glp1);
     int64_t acc = 0;
+#pragma omp parallel for schedule(static) reduction(+ : acc)
     for (int64_t p = 0; p < P; ++p) {
         double la = (llp[p] + lp1[p]) - (ll[p] + lp0[p]);
         if (kind == ORC_MALA) {
@@ -684,7 +693,10 @@ void orc_moments(const double* g, int32_t J, int32_t N, int32_t m,
                  double* mean, double* sd, double* nse, double* rne)
 {
     int64_t P = (int64_t)J * N;
+#pragma omp parallel
+    {
     double* gm = (double*)malloc(sizeof(double) * (size_t)J);
+#pragma omp for schedule(dynamic)
     for (int32_t f = 0; f < m; ++f) {
         for (int32_t j = 0; j < J; ++j) {
             double s = 0.0;
@@ -706,6 +718,7 @@ void orc_moments(const double* g, int32_t J, int32_t N, int32_t m,
         if (rne) rne[f] = vhat > 0.0 ? var / vhat : INFINITY;
     }
     free(gm);
+    }
 }
 
 /* ------------------------------------------------------------------------ */
@@ -726,6 +739,7 @@ static void monitored(const double* theta, int64_t P, int32_t k, int32_t C,
                       const double* xbar, double* g)
 {
     int32_t d = k * (C - 1), m = d + C - 1;
+#pragma omp parallel for schedule(static)
     for (int64_t p = 0; p < P; ++p) {
         for (int32_t i = 0; i < d; ++i) g[p * m + i] = theta[p * d + i];
         for (int32_t c = 1; c < C; ++c) {

@@ -1,0 +1,93 @@
+"""End-to-end parity at the benchmark shapes: the adaptive SPS on the GPU
+against the FP64 oracle's own adaptive SPS (stored by
+tests/golden/make_sps_goldens.py from the oracle only; seeds 1000+ there,
+2000+ here, so the runs are independent).
+
+The bar is 3 numerical standard errors (eq. (NSE_def) with the group
+structure of Section 2.1), per monitored moment:
+  z = (mean_gpu - mean_oracle) / sqrt(NSE_gpu^2 + NSE_oracle^2),
+where each side's mean and NSE pool its R independent runs
+(NSE^2 = mean of the runs' NSE^2 / R).
+- Multiplicity: with m moments and df = R (J - 1) on each side, P(|z| > 3)
+  is about 0.003-0.004 per moment, so at most one exceedance is allowed
+  (two or more at no fault has probability below 1% for m <= 31).
+- Calibration: all z together must pass a KS test against t(df) at
+  p > 0.001 (eq. (gbar_tstat)).
+- logML: the delta-method NSE of one run understates the spread over seeds,
+  so its bar uses the spread: |difference| <= 3 sqrt(s_g^2 / R_g + s_o^2 / R_o)
+  with s the sd of the per-run logML over seeds.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy import stats
+
+from gpu_common import need_gpu
+from paper_1304_4333_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+# golden case -> (GPU likelihood precision, GPU runs)
+CASES = {
+    "small_rw": ("fp64", 24),
+    "binary30_T200_rw": ("fp32", 6),
+    "binary30_T200_mala": ("bf16x3", 6),
+    "multi4_T200_rw": ("bf16x3", 4),
+}
+
+
+def _load(name):
+    path = os.path.join(GOLDEN, f"sps_{name}.json")
+    if not os.path.exists(path):
+        pytest.skip(f"golden {path} not written (tests/golden/make_sps_goldens.py)")
+    with open(path) as fh:
+        return json.load(fh)
+
+
+def _pool(runs):
+    mean = np.mean([r["mean"] for r in runs], axis=0)
+    nse = np.sqrt(np.mean([np.square(r["nse"]) for r in runs], axis=0) / len(runs))
+    lm = np.array([r["logml"] for r in runs])
+    return mean, nse, lm
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_sps_vs_oracle_at_benchmark_shape(name):
+    need_gpu()
+    import time
+    from paper_1304_4333_amd import driver
+    gold = _load(name)
+    prec, R = CASES[name]
+    w = synth.workload(gold["workload"], **gold["overrides"])
+    assert (w.C, w.T, w.k, w.J, w.N) == (gold["C"], gold["T"], gold["k"], gold["J"], gold["N"])
+    X, y, _ = synth.make_data(w)
+    ctx = driver.setup(X, y, w.C, 0.0, w.prior_sd)
+    runs, walls = [], []
+    for i in range(R):
+        seed = 2000 + i
+        print(f"sps parity {name} prec={prec} kind={gold['kind']} seed={seed}", flush=True)
+        base = dict(J=w.J, N=w.N, precision=prec, seed=seed)
+        cfg = driver.SpsConfig.mala_defaults(**base) if gold["kind"] == "mala" else driver.SpsConfig(**base)
+        t0 = time.perf_counter()
+        r = driver.run_sps(ctx, cfg)
+        walls.append(time.perf_counter() - t0)
+        assert r["hit_R_max"] == 0
+        runs.append(dict(mean=r["mean"], nse=r["nse"], logml=r["logml"]))
+    mg, ng, lg = _pool(runs)
+    mo, no, lo = _pool(gold["runs"])
+    z = (mg - mo) / np.sqrt(ng ** 2 + no ** 2)
+    df = min(R, len(gold["runs"])) * (w.J - 1)
+    ks = stats.kstest(z, "t", args=(df,))
+    sg, so = lg.std(ddof=1), lo.std(ddof=1)
+    zl = (lg.mean() - lo.mean()) / math.sqrt(sg ** 2 / len(lg) + so ** 2 / len(lo))
+    print(f"{name}: {len(z)} moments, max |z| {np.abs(z).max():.2f}, exceedances {int((np.abs(z) > 3).sum())}, "
+          f"KS p {ks.pvalue:.3f}; logML gpu {lg.mean():.4f} oracle {lo.mean():.4f} z {zl:.2f}; "
+          f"wall per run gpu {np.mean(walls):.3f} s oracle {np.mean([r['wall_s'] for r in gold['runs']]):.2f} s")
+    assert int((np.abs(z) > 3).sum()) <= 1, np.round(z, 2)
+    assert ks.pvalue > 1e-3
+    assert abs(zl) <= 3.0
