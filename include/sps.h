@@ -150,6 +150,24 @@ int sps_loglik(sps_ctx* ctx, const double* theta, int64_t P, int64_t t0,
 int sps_loglik_grad(sps_ctx* ctx, const double* theta, int64_t P, int64_t t0,
                     int64_t t1, int prec, double* ll, double* grad);
 
+/* As sps_loglik, for callers that cannot allocate device memory (code under
+ * HIP graph capture, serving loops, harnesses that forbid hipMalloc): no
+ * hipMalloc, hipFree or other allocation happens in this call.
+ * - Its scratch (observation-split partial sums, multinomial sufficient
+ *   statistics) is one fixed device array per GPU: 2^21 + 1024 doubles
+ *   (16 MiB), held from the first sps_create on that GPU until the process
+ *   ends.
+ * - The observation split is limited so that its partials fit.
+ * - Nothing in the scratch needs to start at zero: every call writes what it
+ *   reads, and the array keeps the last call's contents.
+ * - Calls that overlap on one GPU (other streams or contexts) race on the
+ *   scratch: serialise them.
+ * - Not timed by sps_timing_enable.
+ * - Errors: those of sps_loglik, and SPS_ERR_ARG when d exceeds the 1024
+ *   doubles kept for the sufficient statistics. */
+int sps_loglik_noalloc(sps_ctx* ctx, const double* theta, int64_t P, int64_t t0,
+                       int64_t t1, int prec, double* ll);
+
 /* ------------------------------------------------------------ phases */
 
 /* C phase of cycle l (Algorithm 1 step 2(a), eq. (C_phase_compute)) with the

@@ -110,9 +110,12 @@ static LoglikEntry lookup(int prec, int nc, int ks, int mode) {
 
 // Common launcher.  grad != nullptr -> forward + adjoint.  perobs != nullptr ->
 // per-observation terms written to perobs[(t - t0) * P + p] (forward only).
+// ext (optional): caller-provided device scratch instead of the context's
+// grow-only buffers; the observation split is limited so its partials fit.
 static int run_loglik(sps_ctx* c, const double* theta, int64_t P, int64_t t0, int64_t t1,
                       int prec, double* ll, double* grad, void* perobs, double* chunk_tot = nullptr,
-                      const unsigned* skip = nullptr, LoglikSplit* keep = nullptr) {
+                      const unsigned* skip = nullptr, LoglikSplit* keep = nullptr,
+                      const LoglikScratch* ext = nullptr) {
     if (keep) *keep = LoglikSplit{ll, grad, 1};
     const int mode = grad ? MODE_GRAD : (perobs ? MODE_PEROBS : MODE_FWD);
     const int ks = (prec == SPS_BF16X3) ? c->kb / 32 : c->kp / 4;
@@ -157,12 +160,15 @@ static int run_loglik(sps_ctx* c, const double* theta, int64_t P, int64_t t0, in
         const int64_t cap = std::max<int64_t>(1, (int64_t(512) << 20) / (P * c->d * 8));
         nsplit = std::min(nsplit, cap);
     }
+    if (ext) nsplit = std::min<int64_t>(nsplit, std::max<int64_t>(1, ext->part_doubles / P));
     a.steps_per_split = (int32_t)((a.nsteps + nsplit - 1) / nsplit);
     nsplit = (a.nsteps + a.steps_per_split - 1) / a.steps_per_split;
     a.nsplit = (int32_t)nsplit;
     if (nsplit == 1 && ll) {
         a.out_ll = ll;
         a.out_g = grad;
+    } else if (ext && !grad) {
+        a.out_ll = ext->part;
     } else {
         SPS_CHECK(ensure(c, c->part_ll, sizeof(double) * nsplit * P, "partial log-likelihoods"));
         a.out_ll = (double*)c->part_ll.p;
@@ -176,10 +182,11 @@ static int run_loglik(sps_ctx* c, const double* theta, int64_t P, int64_t t0, in
     a.skip = skip;
     dim3 grid((unsigned)(npt * nsplit));
     int slot = -1;
-    SPS_CHECK(timing_begin(c, grad ? SPS_KT_LOGLIK_GRAD : (perobs ? SPS_KT_PEROBS : SPS_KT_LOGLIK), &slot));
+    // (the no-allocation path is not timed: timing creates events)
+    if (!ext) SPS_CHECK(timing_begin(c, grad ? SPS_KT_LOGLIK_GRAD : (perobs ? SPS_KT_PEROBS : SPS_KT_LOGLIK), &slot));
     hipError_t err = e.fn(a, grid, c->stream);
     if (err != hipSuccess) return hip_fail(c, err, "loglik_kernel launch");
-    SPS_CHECK(timing_end(c, slot));
+    if (!ext) SPS_CHECK(timing_end(c, slot));
     const bool suff_term = ll && c->C > 2 && prec != SPS_FP64;
     if (ll && a.out_ll != ll && keep && !suff_term) {
         // the caller sums the observation-split partials itself
@@ -189,11 +196,19 @@ static int run_loglik(sps_ctx* c, const double* theta, int64_t P, int64_t t0, in
     if (ll && a.out_ll != ll) {
         const int64_t n = grad ? P * c->d : P;
         loglik_reduce_kernel<<<(unsigned)((n + 255) / 256), 256, 0, c->stream>>>(
-            (const double*)c->part_ll.p, grad ? (const double*)c->part_g.p : nullptr, P, c->d,
-            a.nsplit, ll, grad);
+            a.out_ll, grad ? (const double*)c->part_g.p : nullptr, P, c->d, a.nsplit, ll, grad);
         SPS_CHECK(launched(c, "loglik_reduce_kernel"));
     }
-    if (suff_term) {
+    if (suff_term && ext) {
+        // the eta_{y_t} / 1{y_t = c} terms the kernel leaves out, into the
+        // caller's scratch (recomputed every call: the scratch is shared)
+        suffstat_kernel<<<c->k, 256, 0, c->stream>>>(c->XTf, c->XTh, c->XTl, prec, c->y8, c->Tp, t0, t1, c->k,
+                                                      c->C, ext->suff);
+        SPS_CHECK(launched(c, "suffstat_kernel"));
+        suffstat_apply_kernel<<<(unsigned)((P + 3) / 4), 256, 0, c->stream>>>(theta, ext->suff, P, c->d, prec,
+                                                                              ll, grad);
+        SPS_CHECK(launched(c, "suffstat_apply_kernel"));
+    } else if (suff_term) {
         // the eta_{y_t} / 1{y_t = c} terms the kernel leaves out
         SPS_CHECK(ensure(c, c->suff, sizeof(double) * c->d, "sufficient statistics"));
         if (!(c->suff_valid && c->suff_t0 == t0 && c->suff_t1 == t1 && c->suff_prec == prec)) {
@@ -238,6 +253,13 @@ int loglik_launch_split(sps_ctx* c, const double* theta, int64_t P, int64_t t0, 
 int loglik_perobs(sps_ctx* c, const double* theta, int64_t P, int64_t t0, int64_t t1, int prec,
                   void* perobs, double* chunk_tot, const unsigned* skip) {
     return run_loglik(c, theta, P, t0, t1, prec, nullptr, nullptr, perobs, chunk_tot, skip);
+}
+
+int loglik_launch_scratch(sps_ctx* c, const double* theta, int64_t P, int64_t t0, int64_t t1, int prec,
+                          double* ll, const LoglikScratch& ext) {
+    SPS_CHECK(check_loglik_args(c, "sps_loglik_noalloc", theta, P, t0, t1, prec));
+    if (!ll && P > 0) return fail(c, SPS_ERR_ARG, "sps_loglik_noalloc: null ll");
+    return run_loglik(c, theta, P, t0, t1, prec, ll, nullptr, nullptr, nullptr, nullptr, nullptr, &ext);
 }
 
 }  // namespace sps

@@ -342,6 +342,12 @@ extern "C" int sps_create(sps_ctx** out, int device, void* hip_stream) {
         delete c;
         return SPS_ERR_HIP;
     }
+    // the no-allocation scratch of this device (its address, once per device)
+    const int st = noalloc_setup(c, device);
+    if (st != SPS_OK) {
+        delete c;
+        return st;
+    }
     *out = c;
     return SPS_OK;
 }

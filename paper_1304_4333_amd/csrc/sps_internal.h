@@ -145,6 +145,20 @@ struct LoglikSplit {
 };
 int loglik_launch_split(sps_ctx* c, const double* theta, int64_t P, int64_t t0, int64_t t1,
                         int prec, double* ll, double* grad, LoglikSplit* out);
+// Device scratch supplied by the caller instead of the context's grow-only
+// buffers (sps_loglik_noalloc): part holds part_doubles doubles for the
+// observation-split partials, suff at least d doubles.
+struct LoglikScratch {
+    double* part;
+    int64_t part_doubles;
+    double* suff;
+};
+// sps_loglik on that scratch: no device allocation (arguments checked).
+int loglik_launch_scratch(sps_ctx* c, const double* theta, int64_t P, int64_t t0, int64_t t1, int prec,
+                          double* ll, const LoglikScratch& ext);
+// Once per device, with the device current (sps_create): resolve the device
+// address of the no-allocation scratch array (noalloc.hip).
+int noalloc_setup(sps_ctx* c, int device);
 // Per-observation terms l_{p,t} for t0 <= t < t1 into perobs[(t - t0) * P + p]:
 // FP64 natural-log values in SPS_FP64 mode, otherwise the kernel's FP32
 // base-2 values (read them with perobs_value).  chunk_tot (optional):

@@ -49,6 +49,7 @@ _SIGS = {
     "sps_init_prior": [_vp, _vp, _i64, _u64, _u64],
     "sps_loglik": [_vp, _vp, _i64, _i64, _i64, ct.c_int, _vp],
     "sps_loglik_grad": [_vp, _vp, _i64, _i64, _i64, ct.c_int, _vp, _vp],
+    "sps_loglik_noalloc": [_vp, _vp, _i64, _i64, _i64, ct.c_int, _vp],
     "sps_correct": [_vp, _vp, _vp, _i32, _i32, _i64, _dbl, ct.c_int, _vp,
                     ct.POINTER(_i64), ct.POINTER(_dbl)],
     "sps_logml": [_vp, _vp, _i32, _i32, _vp, ct.POINTER(_dbl), ct.POINTER(_dbl)],
@@ -220,6 +221,17 @@ def sps_loglik(ctx: Context, theta: torch.Tensor, t0: int, t1: int, prec: int,
         ll = torch.empty(P, dtype=torch.float64, device=ctx.device)
     ctx._t(ll, torch.float64, (P,), "ll")
     ctx.check(lib().sps_loglik(ctx.handle, _ptr(theta), P, t0, t1, prec, _ptr(ll)))
+    return ll
+
+
+def sps_loglik_noalloc(ctx: Context, theta: torch.Tensor, t0: int, t1: int, prec: int,
+                       ll: torch.Tensor) -> torch.Tensor:
+    """sps_loglik with no device allocation in the call (the caller passes
+    ll; the library's per-GPU scratch array holds the partial sums)."""
+    P = theta.shape[0]
+    ctx._t(theta, torch.float64, (P, ctx.d), "theta")
+    ctx._t(ll, torch.float64, (P,), "ll")
+    ctx.check(lib().sps_loglik_noalloc(ctx.handle, _ptr(theta), P, t0, t1, prec, _ptr(ll)))
     return ll
 
 
