@@ -187,7 +187,8 @@ int sps_correct(sps_ctx* ctx, const double* theta, double* ll, int32_t J,
  * The combined estimate log(J^-1 sum_j exp(logml_j)) and its delta-method
  * NSE, sd_j(exp(logml_j - logml)) / sqrt(J), are returned in *logml, *nse
  * (host, each may be NULL).  Waits.  SPS_ERR_DEGENERATE if a group has
- * every log_w = -inf, SPS_ERR_NONFINITE on NaN or +inf. */
+ * every log_w = -inf, SPS_ERR_NONFINITE on NaN or +inf; such a group's
+ * logml_j is left unchanged (the other groups' are updated). */
 int sps_logml(sps_ctx* ctx, const double* log_w, int32_t J, int32_t N,
               double* logml_j, double* logml, double* nse);
 
@@ -199,7 +200,9 @@ int sps_logml(sps_ctx* ctx, const double* log_w, int32_t J, int32_t N,
  * from seed, stream).  ancestor: device P int32, global index j N + a.
  * The gathers dst[p] = src[ancestor[p]] are done for each non-NULL pair
  * (theta P x d, ll P, grad P x d); a destination must not alias its source.
- * N <= 4096. */
+ * N <= 4096.  Waits (for the error flags).  SPS_ERR_NONFINITE on a NaN or
+ * +inf log_w, SPS_ERR_DEGENERATE if a group has every log_w = -inf: such a
+ * group's ancestors are its own indices, and no gather is done. */
 int sps_resample(sps_ctx* ctx, const double* log_w, int32_t J, int32_t N,
                  int scheme, const uint64_t* u53, uint64_t seed, uint64_t stream,
                  int32_t* ancestor, const double* theta_in, double* theta_out,

@@ -123,10 +123,8 @@ template <> struct Prec<SPS_BF16X3> {
     static constexpr int KPS = 32;
 };
 
-// Two compile-time choices: PW, the particle blocks (of 16) per wave, and
-// whether the step loop is software-pipelined (two sets of forward
-// accumulators and A fragments).  The register counts (32-bit registers per
-// lane) bound PW.
+// PW, the particle blocks (of 16) per wave, chosen at compile time; the
+// register counts (32-bit registers per lane) bound it.
 template <int PREC, int NC, int KS, int MODE>
 struct Shape {
     static constexpr bool BF = PREC == SPS_BF16X3;
@@ -149,9 +147,6 @@ struct Shape {
         MODE == MODE_PEROBS ? 1
         : (NC == 1 && PREC != SPS_FP64 && afrag + 4 * per1 <= 160) ? 4
         : (NC == 1 && !(PREC == SPS_FP64 && MODE == MODE_GRAD) && afrag + 2 * per1 <= 256) ? 2 : 1;
-    // Double-buffering the X fragments measured slower or equal everywhere
-    // (it doubles the live fragments and accumulators): off by default.
-    static constexpr bool PIPE = false;
     // Workgroups per launch the observation split aims at.  Measured: the
     // FP32/BF16 kernels run fastest with few, long workgroups (about one or
     // two waves per SIMD; fewer split partials and prologues), the gradient
@@ -170,15 +165,14 @@ constexpr int pick_pw() {
 
 template <bool V> using bconst = std::integral_constant<bool, V>;
 
-// PWO / PIPEO override the register-estimate choices (0 / -1: use Shape).
-template <int PREC, int NC, int KS, int MODE, int PWO = 0, int PIPEO = -1>
+template <int PREC, int NC, int KS, int MODE>
 __global__ __launch_bounds__(256) void loglik_kernel(LoglikArgs a) {
     using P_ = Prec<PREC>;
     using E = typename P_::E;
     using Acc = typename P_::Acc;
     constexpr bool BF = (PREC == SPS_BF16X3);
     constexpr bool F64 = (PREC == SPS_FP64);
-    constexpr int PW = PWO ? PWO : Shape<PREC, NC, KS, MODE>::PW;
+    constexpr int PW = Shape<PREC, NC, KS, MODE>::PW;
     constexpr int KBT = BF ? 2 * KS : KS / 4;  // adjoint k blocks of 16 (rows of XT)
     constexpr bool GRAD = (MODE == MODE_GRAD);
     // Multinomial FP32/BF16: the eta_{y_t} term of the log-likelihood is
@@ -328,18 +322,12 @@ __global__ __launch_bounds__(256) void loglik_kernel(LoglikArgs a) {
     // D row r = 4g+i (f32/bf16) or r = g+4i (f64) must map to o + 8g + i.
     const int arow = F64 ? 8 * (r16 & 3) + (r16 >> 2) : 8 * (r16 >> 2) + (r16 & 3);
 
-    // A fragments and forward accumulators come in two sets: while the
-    // epilogue of step st reads set CUR, the MFMAs of step st+1 fill set
-    // 1 - CUR in the same basic block, so the scheduler can interleave the
-    // matrix-core work of one step with the VALU work of the previous one.
-    constexpr bool PIPE = PIPEO < 0 ? Shape<PREC, NC, KS, MODE>::PIPE : PIPEO != 0;
-    constexpr int NSET = PIPE ? 2 : 1;
+    // A fragments (loaded one step ahead) and forward accumulators
     using AReg = typename std::conditional<BF, bf16x8, E>::type;
-    AReg ah[NSET][2][KS];                       // [set][tile][k-step]
-    AReg al[NSET][BF ? 2 : 1][BF ? KS : 1];
-    Acc acc[NSET][2][PW][NC];                   // [set][tile][block][outcome]
-    auto load_a = [&](auto set_c, int64_t o) __attribute__((always_inline)) {
-        constexpr int S_ = decltype(set_c)::value;
+    AReg ah[2][KS];                       // [tile][k-step]
+    AReg al[BF ? 2 : 1][BF ? KS : 1];
+    Acc acc[2][PW][NC];                   // [tile][block][outcome]
+    auto load_a = [&](int64_t o) __attribute__((always_inline)) {
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int64_t row = o + arow + 4 * h;
@@ -348,25 +336,24 @@ __global__ __launch_bounds__(256) void loglik_kernel(LoglikArgs a) {
                 const unsigned short* xl = (const unsigned short*)a.Xlo + row * a.ldx + g * 8 * KS;
 #pragma unroll
                 for (int s = 0; s < KS; ++s) {
-                    ah[S_][h][s] = __builtin_bit_cast(bf16x8, *(const u16x8*)(xh + 8 * s));
-                    al[S_][h][s] = __builtin_bit_cast(bf16x8, *(const u16x8*)(xl + 8 * s));
+                    ah[h][s] = __builtin_bit_cast(bf16x8, *(const u16x8*)(xh + 8 * s));
+                    al[h][s] = __builtin_bit_cast(bf16x8, *(const u16x8*)(xl + 8 * s));
                 }
             } else {
                 const E* xr = (const E*)a.X + row * a.ldx + g * KS;
 #pragma unroll
-                for (int s = 0; s < KS; ++s) ah[S_][h][s] = xr[s];
+                for (int s = 0; s < KS; ++s) ah[h][s] = xr[s];
             }
         }
     };
-    // forward contraction of one step into set S_, independent chains interleaved
-    auto mfma_fwd = [&](auto set_c) __attribute__((always_inline)) {
-        constexpr int S_ = decltype(set_c)::value;
+    // forward contraction of one step, independent chains interleaved
+    auto mfma_fwd = [&]() __attribute__((always_inline)) {
 #pragma unroll
         for (int h = 0; h < 2; ++h)
 #pragma unroll
             for (int b = 0; b < PW; ++b)
 #pragma unroll
-                for (int c = 0; c < NC; ++c) acc[S_][h][b][c] = Acc{0, 0, 0, 0};
+                for (int c = 0; c < NC; ++c) acc[h][b][c] = Acc{0, 0, 0, 0};
 #pragma unroll
         for (int s = 0; s < KS; ++s)
 #pragma unroll
@@ -376,32 +363,25 @@ __global__ __launch_bounds__(256) void loglik_kernel(LoglikArgs a) {
 #pragma unroll
                     for (int c = 0; c < NC; ++c) {
                         if constexpr (BF) {
-                            acc[S_][h][b][c] = mfma(ah[S_][h][s], bh[b][c][s], acc[S_][h][b][c]);
-                            acc[S_][h][b][c] = mfma(ah[S_][h][s], bl[b][c][s], acc[S_][h][b][c]);
-                            acc[S_][h][b][c] = mfma(al[S_][h][s], bh[b][c][s], acc[S_][h][b][c]);
+                            acc[h][b][c] = mfma(ah[h][s], bh[b][c][s], acc[h][b][c]);
+                            acc[h][b][c] = mfma(ah[h][s], bl[b][c][s], acc[h][b][c]);
+                            acc[h][b][c] = mfma(al[h][s], bh[b][c][s], acc[h][b][c]);
                         } else {
-                            acc[S_][h][b][c] = mfma(ah[S_][h][s], bh[b][c][s], acc[S_][h][b][c]);
+                            acc[h][b][c] = mfma(ah[h][s], bh[b][c][s], acc[h][b][c]);
                         }
                     }
     };
 
-    // One step: epilogue (and adjoint) of step st from set CUR, overlapped
-    // with the forward MFMAs of step st + 1 into the other set.
+    // One step: forward MFMAs, epilogue and adjoint of step st.
     // interior_c: the step is known to lie inside [t0, t1) with a successor,
     // so the unmasked epilogue is chosen at compile time (given one body with
     // both epilogues behind a runtime test, the compiler merges them into one
     // path that pays the masking selects on every step).
-    auto body = [&](auto cur_c, int st, bool has_next, auto interior_c) __attribute__((always_inline)) {
+    auto body = [&](int st, bool has_next, auto interior_c) __attribute__((always_inline)) {
         constexpr bool INTERIOR = decltype(interior_c)::value;
-        constexpr int CUR = decltype(cur_c)::value;
-        constexpr int NXT = PIPE ? 1 - CUR : CUR;
         const int64_t o = a.t0a + (int64_t)st * 32;
-        if constexpr (PIPE) {
-            if (st + 2 < st_end) load_a(cur_c, o + 64);  // set CUR is free again: prefetch step st + 2
-        } else {
-            mfma_fwd(cur_c);
-            if (has_next) load_a(cur_c, o + 32);  // the MFMAs have read this step's fragments
-        }
+        mfma_fwd();
+        if (has_next) load_a(o + 32);  // the MFMAs have read this step's fragments
         // A operand of the adjoint (rows of the transposed X for this step),
         // requested before the epilogue so the load latency hides behind it.
         using XtReg = typename std::conditional<BF, bf16x8, E>::type;
@@ -437,8 +417,7 @@ __global__ __launch_bounds__(256) void loglik_kernel(LoglikArgs a) {
 #pragma unroll
         for (int b = 0; b < (MODE == MODE_PEROBS ? PW : 1); ++b) csum[b] = 0.0;
 
-            auto epilogue = [&](auto set_c, auto masked_c, auto perobs_c, auto fast_c) __attribute__((always_inline)) {
-                constexpr int CS = decltype(set_c)::value;
+            auto epilogue = [&](auto masked_c, auto perobs_c, auto fast_c) __attribute__((always_inline)) {
                 constexpr bool MASKED = decltype(masked_c)::value;
                 constexpr bool PEROBS = decltype(perobs_c)::value;
                 constexpr bool FAST = decltype(fast_c)::value;  // unshifted form, checked after the step
@@ -465,7 +444,7 @@ __global__ __launch_bounds__(256) void loglik_kernel(LoglikArgs a) {
                                 // -log2 of the product of the factors (below).  Exact in
                                 // range while the product is finite; otherwise tsum turns
                                 // -inf or NaN and the step is redone with the shifted form.
-                                const E z = acc[CS][h][b][0][i];
+                                const E z = acc[h][b][0][i];
                                 const float e = fexp2(z);
                                 const float sfac = 1.f + e;
                                 prod[b] *= (MASKED && !ov) ? 1.f : sfac;
@@ -474,7 +453,7 @@ __global__ __launch_bounds__(256) void loglik_kernel(LoglikArgs a) {
                                 if constexpr (GRAD) rres[h][i][b][0] = ov ? e * frcp(sfac) : 0.f;
                             } else if constexpr (NC == 1) {
                                 // Binary with sign folding: l = -softplus(z), z = x~' theta.
-                                const E z = acc[CS][h][b][0][i];
+                                const E z = acc[h][b][0][i];
                                 if constexpr (F64) {
                                     const double e = exp(-fabs(z));
                                     const double q = 1.0 + e;
@@ -494,7 +473,7 @@ __global__ __launch_bounds__(256) void loglik_kernel(LoglikArgs a) {
                                 E s = E(1);
     #pragma unroll
                                 for (int c = 0; c < NC; ++c) {
-                                    ec[c] = fexp2(acc[CS][h][b][c][i]);
+                                    ec[c] = fexp2(acc[h][b][c][i]);
                                     s += ec[c];
                                 }
                                 bad |= !(s < 0x1p126f);
@@ -509,7 +488,7 @@ __global__ __launch_bounds__(256) void loglik_kernel(LoglikArgs a) {
                                 E ey = E(0);
     #pragma unroll
                                 for (int c = 0; c < NC; ++c) {
-                                    const E v = acc[CS][h][b][c][i];
+                                    const E v = acc[h][b][c][i];
                                     if constexpr (F64) m = v > m ? v : m;
                                     else m = __int_as_float(max(__float_as_int(v), __float_as_int(m)));  // m >= 0
                                     if constexpr (!NOY) ey = (yt == c + 1) ? v : ey;
@@ -520,7 +499,7 @@ __global__ __launch_bounds__(256) void loglik_kernel(LoglikArgs a) {
                                     s = exp(-m);
     #pragma unroll
                                     for (int c = 0; c < NC; ++c) {
-                                        ec[c] = exp(acc[CS][h][b][c][i] - m);
+                                        ec[c] = exp(acc[h][b][c][i] - m);
                                         s += ec[c];
                                     }
                                     lp = ey - (m + log(s));
@@ -528,7 +507,7 @@ __global__ __launch_bounds__(256) void loglik_kernel(LoglikArgs a) {
                                     s = fexp2(-m);
     #pragma unroll
                                     for (int c = 0; c < NC; ++c) {
-                                        ec[c] = fexp2(acc[CS][h][b][c][i] - m);
+                                        ec[c] = fexp2(acc[h][b][c][i] - m);
                                         s += ec[c];
                                     }
                                     lp = ey - (m + flog2(s));
@@ -563,17 +542,14 @@ __global__ __launch_bounds__(256) void loglik_kernel(LoglikArgs a) {
             };
 
         const bool full = (o >= a.t0) && (o + 32 <= a.t1);
-        const std::integral_constant<int, NXT> nxt_c{};
         // Non-per-observation steps; the per-observation output exists only in
         // the MODE_PEROBS instantiation, so the other kernels carry none of it.
         auto regular = [&]() __attribute__((always_inline)) {
             if constexpr (FASTOK) {
                 if (INTERIOR || (full && has_next)) {
-                    if constexpr (PIPE) mfma_fwd(nxt_c);
-                    epilogue(cur_c, bconst<false>{}, bconst<false>{}, bconst<true>{});
+                    epilogue(bconst<false>{}, bconst<false>{}, bconst<true>{});
                 } else {
-                    if (PIPE && has_next) mfma_fwd(nxt_c);
-                    epilogue(cur_c, bconst<true>{}, bconst<false>{}, bconst<true>{});
+                    epilogue(bconst<true>{}, bconst<false>{}, bconst<true>{});
                 }
                 if constexpr (NC == 1) {
     #pragma unroll
@@ -582,20 +558,17 @@ __global__ __launch_bounds__(256) void loglik_kernel(LoglikArgs a) {
                 if (__any(bad)) {  // wave-uniform: redo this step with the max shift
     #pragma unroll
                     for (int b = 0; b < PW; ++b) tsum[b] = E(0);
-                    epilogue(cur_c, bconst<true>{}, bconst<false>{}, bconst<false>{});
+                    epilogue(bconst<true>{}, bconst<false>{}, bconst<false>{});
                 }
             } else if (INTERIOR || (full && has_next)) {
-                if constexpr (PIPE) mfma_fwd(nxt_c);
-                epilogue(cur_c, bconst<false>{}, bconst<false>{}, bconst<false>{});
+                epilogue(bconst<false>{}, bconst<false>{}, bconst<false>{});
             } else {
-                if (PIPE && has_next) mfma_fwd(nxt_c);
-                epilogue(cur_c, bconst<true>{}, bconst<false>{}, bconst<false>{});
+                epilogue(bconst<true>{}, bconst<false>{}, bconst<false>{});
             }
         };
         if constexpr (MODE == MODE_PEROBS) {
             if (a.perobs != nullptr) {
-                if (PIPE && has_next) mfma_fwd(nxt_c);
-                epilogue(cur_c, bconst<true>{}, bconst<true>{}, bconst<false>{});
+                epilogue(bconst<true>{}, bconst<true>{}, bconst<false>{});
                 if (a.chunk_tot != nullptr) {
                     // lane group g holds rows 8g .. 8g + 7 of the step: total = ((s0 + s1) + s2) + s3
     #pragma unroll
@@ -667,28 +640,16 @@ __global__ __launch_bounds__(256) void loglik_kernel(LoglikArgs a) {
     };
 
     if (st_begin < st_end) {
-        const std::integral_constant<int, 0> set0{};
-        load_a(set0, a.t0a + (int64_t)st_begin * 32);
-        if constexpr (PIPE) {
-            const std::integral_constant<int, 1> set1{};
-            if (st_begin + 1 < st_end) load_a(set1, a.t0a + (int64_t)(st_begin + 1) * 32);
-            mfma_fwd(set0);
-            for (int st = st_begin; st < st_end; st += 2) {
-                body(set0, st, st + 1 < st_end, bconst<false>{});
-                if (st + 1 >= st_end) break;
-                body(set1, st + 1, st + 2 < st_end, bconst<false>{});
-            }
-        } else {
-            // steps whose 32 rows all lie in [t0, t1) and that have a successor run
-            // a body without the masked epilogue; the others (at most one at each
-            // end of the split) run the general body
-            const int lo = max(st_begin, a.t0 > a.t0a ? 1 : 0);
-            const int hi = min(st_end - 1, (int)((a.t1 - a.t0a) / 32));
-            int st = st_begin;
-            for (; st < st_end && st < lo; ++st) body(set0, st, st + 1 < st_end, bconst<false>{});
-            for (; st < hi; ++st) body(set0, st, true, bconst<true>{});
-            for (; st < st_end; ++st) body(set0, st, st + 1 < st_end, bconst<false>{});
-        }
+        load_a(a.t0a + (int64_t)st_begin * 32);
+        // steps whose 32 rows all lie in [t0, t1) and that have a successor run
+        // a body without the masked epilogue; the others (at most one at each
+        // end of the split) run the general body
+        const int lo = max(st_begin, a.t0 > a.t0a ? 1 : 0);
+        const int hi = min(st_end - 1, (int)((a.t1 - a.t0a) / 32));
+        int st = st_begin;
+        for (; st < st_end && st < lo; ++st) body(st, st + 1 < st_end, bconst<false>{});
+        for (; st < hi; ++st) body(st, true, bconst<true>{});
+        for (; st < st_end; ++st) body(st, st + 1 < st_end, bconst<false>{});
     }
     if constexpr (GRAD) {
         if (g_first || ((st_end - st_begin) % kFoldSteps) != 0) fold();

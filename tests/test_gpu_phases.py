@@ -178,6 +178,34 @@ def test_resample_log_weights_and_gather(orc, scheme):
     assert np.array_equal(anc2, ref2)
 
 
+@pytest.mark.parametrize("bad", [np.nan, np.inf])
+def test_nonfinite_weight_outside_thread_zero(bad):
+    """A NaN or +inf log-weight held by a thread other than thread 0 of the
+    group's workgroup (n = 300 and n = 513, not multiples of 256): logML
+    reports it and leaves that group's logml_j unchanged; the S phase reports
+    it and gives the group the identity ancestry."""
+    need_gpu()
+    import torch
+    sps = _sps()
+    X, y, _ = dataset(20, 2, 2, seed=17)
+    ctx = make_ctx(X, y, 2)
+    J, N = 3, 700
+    for n in (300, 513):
+        lw = synth.make_log_weights(J * N, seed=18, spread=2.0)
+        lw[N + n] = bad
+        lj0 = synth.make_normals(J, 1, seed=19)[:, 0]
+        lj = to_gpu(lj0.copy())
+        with pytest.raises(sps.SpsError) as e:
+            sps.sps_logml(ctx, to_gpu(lw), J, N, lj)
+        assert e.value.status == sps.SPS_ERR_NONFINITE
+        assert lj.cpu().numpy()[1] == lj0[1]
+        anc = torch.full((J * N,), -1, dtype=torch.int32, device="cuda")
+        with pytest.raises(sps.SpsError) as e:
+            sps.sps_resample(ctx, to_gpu(lw), J, N, 0, seed=1, ancestor=anc)
+        assert e.value.status == sps.SPS_ERR_NONFINITE
+        assert np.array_equal(anc.cpu().numpy()[N:2 * N], np.arange(N, 2 * N))
+
+
 def test_resample_errors():
     need_gpu()
     sps = _sps()
