@@ -249,17 +249,22 @@ int sps_mutate_cov(sps_ctx* ctx, double* theta, double* ll, double* grad,
  * r = 1, 2, ... is the step of sps_mutate with the current h and Philox
  * streams stream0 + r stream_step (normals) and that + 1 (uniforms); after it
  * the monitored functions (sps_monitor) and their RNEs (sps_moments) are
- * formed on the device and aggregated (rne_rule 0: mean, 1: minimum).  The
- * host reads back one small record per step and applies the step-size rule
- * (h += h_step if the acceptance rate exceeds acc_target, else h -= h_step,
- * kept in [h_min, h_max]) and the stopping rule (aggregate RNE >= K, or
- * R_max steps).  theta, ll, grad: as sps_mutate.  h: host, in: the step-size
- * factor of the first step, out: after the last update.  g_work: device
- * scratch of P x (d + C - 1) FP64.  sigma_out: device, R_max x d x d FP64, or
- * NULL; receives the proposal covariance of every step (the record of
- * Algorithm 3's first pass).  *R_out: steps taken; *rne_out, *rate_out (host,
- * may be NULL): aggregate RNE and acceptance rate of the last step.  Errors
- * as sps_mutate (SPS_ERR_NOT_PD stops the loop; the steps before it stand). */
+ * formed on the device and aggregated (rne_rule 0: mean, 1: minimum).  A
+ * control kernel applies the step-size rule (h += h_step if the acceptance
+ * rate exceeds acc_target, else h -= h_step, kept in [h_min, h_max]) and the
+ * stopping rule (aggregate RNE >= K, or R_max steps) on the device; h and the
+ * stop word stay in device memory.  The host reads each step's small state
+ * record asynchronously, with the next step already queued when the steps
+ * are short, so the device does not wait for the host between steps; a step
+ * queued after the stop leaves every output unchanged.  theta, ll, grad: as
+ * sps_mutate.  h: host, in: the step-size factor of the first step, out:
+ * after the last update.  g_work: device scratch of P x (d + C - 1) FP64.
+ * sigma_out: device, R_max x d x d FP64, or NULL; rows 0 .. R_out - 1
+ * receive the proposal covariance of every step taken (the record of
+ * Algorithm 3's first pass), later rows are unspecified.  *R_out: steps
+ * taken; *rne_out, *rate_out (host, may be NULL): aggregate RNE and
+ * acceptance rate of the last step.  Errors as sps_mutate (SPS_ERR_NOT_PD
+ * stops the loop; the steps before it stand). */
 int sps_mphase(sps_ctx* ctx, double* theta, double* ll, double* grad, int32_t J,
                int32_t N, int64_t t, int kind, int prec, double* h, double h_step,
                double h_min, double h_max, double acc_target, double K, int32_t R_max,

@@ -150,20 +150,26 @@ static int run_loglik(sps_ctx* c, const double* theta, int64_t P, int64_t t0, in
     a.d = c->d;
     a.binary = c->C == 2;
     a.nsteps = (int32_t)((t1 - a.t0a + kObsStep - 1) / kObsStep);
-    const int64_t npt = (P + e.ppb - 1) / e.ppb;
     // Observation splits: the kernel's workgroup target (measured per kernel
-    // shape), at least 4 steps of work per wave, bounded partial-gradient storage.
-    const int64_t target_blocks = e.target;
-    int64_t nsplit = std::max<int64_t>(1, (target_blocks + npt - 1) / npt);
-    nsplit = std::min<int64_t>(nsplit, std::max<int64_t>(1, a.nsteps / 4));
+    // shape), at least 4 steps of work per wave.  Up to four parts are taken
+    // by the waves of one workgroup (a particle group per 1, 2 or 4 waves),
+    // whose sums meet in LDS; further parts go to separate workgroups and
+    // leave partial slices in memory (bounded storage), summed afterwards.
+    const int64_t npt0 = (P + e.ppb - 1) / e.ppb;
+    int64_t parts = std::max<int64_t>(1, (e.target + npt0 - 1) / npt0);
+    parts = std::min<int64_t>(parts, std::max<int64_t>(1, a.nsteps / 4));
+    const int ws = (!e.wsplit || perobs) ? 1 : parts >= 4 ? 4 : parts >= 2 ? 2 : 1;
+    int64_t nsplit = (parts + ws - 1) / ws;
     if (grad) {
         const int64_t cap = std::max<int64_t>(1, (int64_t(512) << 20) / (P * c->d * 8));
         nsplit = std::min(nsplit, cap);
     }
     if (ext) nsplit = std::min<int64_t>(nsplit, std::max<int64_t>(1, ext->part_doubles / P));
-    a.steps_per_split = (int32_t)((a.nsteps + nsplit - 1) / nsplit);
-    nsplit = (a.nsteps + a.steps_per_split - 1) / a.steps_per_split;
+    a.steps_per_split = (int32_t)((a.nsteps + nsplit * ws - 1) / (nsplit * ws));
+    nsplit = ((a.nsteps + a.steps_per_split - 1) / a.steps_per_split + ws - 1) / ws;
     a.nsplit = (int32_t)nsplit;
+    a.wsplit = ws;
+    const int64_t npt = (P + e.ppb / ws - 1) / (e.ppb / ws);
     if (nsplit == 1 && ll) {
         a.out_ll = ll;
         a.out_g = grad;
@@ -241,13 +247,13 @@ static int check_loglik_args(sps_ctx* c, const char* who, const double* theta, i
 }
 
 int loglik_launch(sps_ctx* c, const double* theta, int64_t P, int64_t t0, int64_t t1, int prec,
-                  double* ll, double* grad) {
-    return run_loglik(c, theta, P, t0, t1, prec, ll, grad, nullptr);
+                  double* ll, double* grad, const unsigned* skip) {
+    return run_loglik(c, theta, P, t0, t1, prec, ll, grad, nullptr, nullptr, skip);
 }
 
 int loglik_launch_split(sps_ctx* c, const double* theta, int64_t P, int64_t t0, int64_t t1, int prec,
-                        double* ll, double* grad, LoglikSplit* out) {
-    return run_loglik(c, theta, P, t0, t1, prec, ll, grad, nullptr, nullptr, nullptr, out);
+                        double* ll, double* grad, LoglikSplit* out, const unsigned* skip) {
+    return run_loglik(c, theta, P, t0, t1, prec, ll, grad, nullptr, nullptr, skip, out);
 }
 
 int loglik_perobs(sps_ctx* c, const double* theta, int64_t P, int64_t t0, int64_t t1, int prec,

@@ -79,6 +79,12 @@ struct LoglikArgs {
     int32_t k, d, ldx;    // covariates, parameters, row stride of X
     int32_t nsteps, steps_per_split, nsplit;
     int32_t binary;       // C == 2: rows of X are sign-folded
+    // Waves of a workgroup that share one particle group and split its
+    // observations (1, 2 or 4; kernels with Shape::WSPLIT only): the
+    // observation range has nsplit * wsplit parts, part (block split) * wsplit
+    // + (wave % wsplit); the waves' sums are added in LDS in part order and
+    // written once, to slice (block split) of the outputs.
+    int32_t wsplit;
 };
 
 __device__ __forceinline__ f32x4 mfma(float a, float b, f32x4 c) {
@@ -156,6 +162,15 @@ struct Shape {
     static constexpr int TARGET =
         (PREC == SPS_FP64 || MODE == MODE_PEROBS || (NC > 1 && MODE == MODE_FWD)) ? 2048
         : NC > 1 ? 1024 : (MODE == MODE_GRAD ? 256 : 512);
+    // The FP32/BF16 adjoint keeps each wave's FP64 gradient copy in LDS when
+    // the four waves' copies fit (FP64 adds into the output slice instead).
+    static constexpr int FOLDVALS = MODE == MODE_GRAD ? PW * NC * kbt * 4 : 1;
+    static constexpr bool LFOLD = MODE == MODE_GRAD && PREC != SPS_FP64 && 4 * FOLDVALS * 64 * 8 <= 160 * 1024;
+    // Whether waves may split a particle group's observations inside the
+    // workgroup (wsplit > 1): the forward kernel, and the adjoint with its
+    // gradient copy in LDS when the log-likelihood sums fit beside it.
+    static constexpr bool WSPLIT =
+        MODE == MODE_FWD || (LFOLD && 4 * FOLDVALS * 64 * 8 + 4 * PW * 16 * 8 <= 160 * 1024);
 };
 
 template <int PREC, int NC, int KS, int MODE>
@@ -197,10 +212,16 @@ __global__ __launch_bounds__(256) void loglik_kernel(LoglikArgs a) {
     const int wave = threadIdx.x >> 6;
     const int g = lane >> 4;
     const int r16 = lane & 15;
-    const int split = blockIdx.x % a.nsplit;
+    constexpr bool WS = Shape<PREC, NC, KS, MODE>::WSPLIT;
+    const int ws = WS ? a.wsplit : 1;     // waves per particle group
+    const int wpart = WS ? wave % ws : 0; // this wave's part of the group's observations
+    const int oslice = blockIdx.x % a.nsplit;
+    const int split = oslice * ws + wpart;
     const int64_t ptile = blockIdx.x / a.nsplit;
-    const int64_t pbase = (ptile * 4 + wave) * (16 * PW);
-    if (pbase >= a.P) return;  // whole wave beyond the last particle (no barriers below)
+    const int64_t pbase = (ptile * (4 / ws) + wave / ws) * (16 * PW);
+    // whole wave beyond the last particle: the waves of its group leave with
+    // it, so the one barrier below (ws > 1) waits only for groups with work
+    if (pbase >= a.P) return;
 
     // ---- B operand: theta of this wave's particles, kept in registers ----
     // f32/f64: step s, lane group g covers covariate g*KS + s.
@@ -256,15 +277,15 @@ __global__ __launch_bounds__(256) void loglik_kernel(LoglikArgs a) {
     // The binary FP32/BF16 epilogue hands the adjoint +sigmoid instead of the
     // residual -sigmoid (saves a sign flip per element); the sign is applied here.
     constexpr bool kNegRes = (NC == 1) && !F64;
-    double* const g_out = GRAD ? a.out_g + (int64_t)split * a.P * a.d : nullptr;
+    double* const g_out = GRAD ? a.out_g + (int64_t)oslice * a.P * a.d : nullptr;
     bool g_first = true;
     // The FP32 adjoint tiles are added into an FP64 copy every kFoldSteps
     // steps.  That copy lives in LDS (one slot per lane and value, private to
     // the wave) when the four waves' copies fit, and the gradient is written
     // to HBM once at the end; otherwise it is the wave's slice of the output
     // itself, read and written at every fold.
-    constexpr int kFoldVals = GRAD ? PW * NC * KBT * 4 : 1;
-    constexpr bool LFOLD = GRAD && !F64 && 4 * kFoldVals * 64 * 8 <= 160 * 1024;
+    constexpr int kFoldVals = Shape<PREC, NC, KS, MODE>::FOLDVALS;
+    constexpr bool LFOLD = Shape<PREC, NC, KS, MODE>::LFOLD;
     __shared__ double fold_lds[LFOLD ? 4 * kFoldVals * 64 : 1];
     double* const fold_w = fold_lds + (LFOLD ? wave * kFoldVals * 64 + lane : 0);
     auto fold = [&]() __attribute__((always_inline)) {
@@ -296,9 +317,11 @@ __global__ __launch_bounds__(256) void loglik_kernel(LoglikArgs a) {
             g_first = false;
         }
     };
-    // LDS copy -> output, once (the binary residual's sign applied here)
+    // LDS copy -> output, once (the binary residual's sign applied here); with
+    // ws > 1 the first wave of each group adds its group's copies in part order
     auto fold_out = [&]() __attribute__((always_inline)) {
         if constexpr (LFOLD) {
+            if (wpart != 0) return;
 #pragma unroll
             for (int b = 0; b < PW; ++b) {
                 const int64_t p = pbase + b * 16 + r16;
@@ -309,7 +332,9 @@ __global__ __launch_bounds__(256) void loglik_kernel(LoglikArgs a) {
 #pragma unroll
                         for (int i = 0; i < 4; ++i) {
                             const int kk = q * 16 + 4 * g + i;
-                            const double v = fold_w[(((b * NC + c) * KBT + q) * 4 + i) * 64];
+                            const int idx = (((b * NC + c) * KBT + q) * 4 + i) * 64;
+                            double v = fold_w[idx];
+                            for (int w2 = 1; w2 < ws; ++w2) v += fold_w[w2 * kFoldVals * 64 + idx];
                             if (p < a.P && kk < a.k) g_out[p * a.d + c * a.k + kk] = kNegRes ? -v : v;
                         }
             }
@@ -653,19 +678,48 @@ __global__ __launch_bounds__(256) void loglik_kernel(LoglikArgs a) {
     }
     if constexpr (GRAD) {
         if (g_first || ((st_end - st_begin) % kFoldSteps) != 0) fold();
-        fold_out();
     }
-
-    // ---- write the log-likelihood partial ----
     const double lscale = F64 ? 1.0 : kLn2;
-    double* ll_out = a.out_ll + (int64_t)split * a.P;
+    double* ll_out = a.out_ll + (int64_t)oslice * a.P;
+    if constexpr (WS) {
+        // ---- the log-likelihood partial: lane group sums, then (ws > 1) the
+        // group's waves in part order through LDS ----
+        __shared__ double ll_lds[4 * PW * 16];
 #pragma unroll
-    for (int b = 0; b < PW; ++b) {
-        double v = acc64[b];
-        v += __shfl_xor(v, 16, 64);
-        v += __shfl_xor(v, 32, 64);
-        const int64_t p = pbase + b * 16 + r16;
-        if (g == 0 && p < a.P) ll_out[p] = v * lscale;
+        for (int b = 0; b < PW; ++b) {
+            acc64[b] += __shfl_xor(acc64[b], 16, 64);
+            acc64[b] += __shfl_xor(acc64[b], 32, 64);
+        }
+        if (ws > 1) {
+            if (g == 0) {
+#pragma unroll
+                for (int b = 0; b < PW; ++b) ll_lds[(wave * PW + b) * 16 + r16] = acc64[b];
+            }
+            __syncthreads();  // also orders the waves' final folds before fold_out
+            if (wpart == 0) {
+#pragma unroll
+                for (int b = 0; b < PW; ++b)
+                    for (int w2 = 1; w2 < ws; ++w2) acc64[b] += ll_lds[((wave + w2) * PW + b) * 16 + r16];
+            }
+        }
+        if constexpr (GRAD) fold_out();
+        if (wpart != 0) return;
+#pragma unroll
+        for (int b = 0; b < PW; ++b) {
+            const int64_t p = pbase + b * 16 + r16;
+            if (g == 0 && p < a.P) ll_out[p] = acc64[b] * lscale;
+        }
+    } else {
+        if constexpr (GRAD) fold_out();
+        // ---- write the log-likelihood partial ----
+#pragma unroll
+        for (int b = 0; b < PW; ++b) {
+            double v = acc64[b];
+            v += __shfl_xor(v, 16, 64);
+            v += __shfl_xor(v, 32, 64);
+            const int64_t p = pbase + b * 16 + r16;
+            if (g == 0 && p < a.P) ll_out[p] = v * lscale;
+        }
     }
 }
 
@@ -692,6 +746,7 @@ struct LoglikEntry {
     LoglikLaunchFn fn = nullptr;
     int ppb = 0;     // particles per 256-thread block
     int target = 0;  // workgroups per launch the observation split aims at
+    bool wsplit = false;  // the kernel takes LoglikArgs::wsplit > 1
 };
 
 template <int PREC, int NC, int KS, int MODE>
@@ -700,6 +755,7 @@ LoglikEntry loglik_entry() {
     e.fn = &launch_loglik<PREC, NC, KS, MODE>;
     e.ppb = particles_per_block<PREC, NC, KS, MODE>();
     e.target = Shape<PREC, NC, KS, MODE>::TARGET;
+    e.wsplit = Shape<PREC, NC, KS, MODE>::WSPLIT;
     return e;
 }
 

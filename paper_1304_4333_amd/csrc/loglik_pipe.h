@@ -93,6 +93,7 @@ __global__ __launch_bounds__(256) void loglik_pipe_kernel(LoglikArgs a) {
     constexpr int kFoldSteps = 128;  // FP32 adjoint sums are added into FP64 every 4096 rows
     __shared__ __attribute__((aligned(16))) unsigned char lds[S::LDS];
 
+    if (a.skip != nullptr && *a.skip != 0u) return;  // the same value for every wave
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;

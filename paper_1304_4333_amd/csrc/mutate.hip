@@ -86,10 +86,15 @@ __global__ __launch_bounds__(256) void cov_partial_kernel(const double* __restri
 
 // Sigma = h V, V = (S - P m m') / (P - 1) with S, m the shifted sums over all
 // chunks.  One wave per matrix element, lanes over chunks, butterfly sums.
+// hdev (optional): h is read from device memory; stop (optional): nothing is
+// written when *stop is nonzero.
 __global__ __launch_bounds__(256) void cov_final_kernel(const double* __restrict__ part,
                                                         const double* __restrict__ psum, int32_t nchunk,
                                                         int32_t d, int64_t P, double h,
-                                                        double* __restrict__ V) {
+                                                        double* __restrict__ V, const double* hdev,
+                                                        const unsigned* stop) {
+    if (stop && *stop) return;  // the same value for the whole grid
+    if (hdev) h = *hdev;
     const int lane = threadIdx.x & 63;
     const int64_t e = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (e >= (int64_t)d * d) return;
@@ -700,8 +705,9 @@ __global__ __launch_bounds__(256) void accept_kernel(
     const double* __restrict__ u, const double* __restrict__ mu, const double* __restrict__ isd,
     const double* __restrict__ w0, const double* __restrict__ w1,
     int64_t P, int32_t d, int mala, const unsigned* flags, unsigned long long* count,
-    uint64_t seed, uint64_t zstream, int32_t ll2n) {
+    uint64_t seed, uint64_t zstream, int32_t ll2n, const unsigned* stop) {
     __shared__ unsigned nacc[256 / kAccLanes];
+    if (stop && *stop) return;  // the same value for the whole grid: theta, ll, grad stay
     const int sub = threadIdx.x & (kAccLanes - 1);
     const int slot = threadIdx.x / kAccLanes;
     const int64_t p = (int64_t)blockIdx.x * kAccPerBlock + slot;
@@ -777,14 +783,20 @@ static inline unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
 // sps_last_sigma.
 // All launches of one M step; the status flags and the accepted-count slots
 // are left in the status block of c->small.  No synchronisation.
+// h_dev (optional, device): the step size is read there when the covariance
+// is formed, and h is not used.  stop (optional, device): when *stop is
+// nonzero as the step runs, the step leaves theta, ll, grad and the context's
+// Sigma unchanged (the likelihood launches do no work either).
 static int mutate_launch(sps_ctx* c, const char* who, double* theta, double* ll, double* grad, int32_t J,
                          int32_t N, int64_t t, double h, const double* Sigma_in, int kind, int prec,
-                         const double* z, const double* u, uint64_t seed, uint64_t stream) {
+                         const double* z, const double* u, uint64_t seed, uint64_t stream,
+                         const double* h_dev = nullptr, const unsigned* stop = nullptr) {
     if (!c->has_data || !c->has_prior) return fail(c, SPS_ERR_STATE, "%s: set data and prior first", who);
     if (J < 1 || N < 1 || (int64_t)J * N < 2 || !theta || !ll)
         return fail(c, SPS_ERR_ARG, "%s: bad arguments (need J N >= 2, theta, ll)", who);
     if (t < 0 || t > c->T) return fail(c, SPS_ERR_ARG, "%s: t=%lld outside [0, T]", who, (long long)t);
-    if (!Sigma_in && (!(h > 0.0) || !std::isfinite(h))) return fail(c, SPS_ERR_ARG, "%s: h must be positive", who);
+    if (!Sigma_in && !h_dev && (!(h > 0.0) || !std::isfinite(h)))
+        return fail(c, SPS_ERR_ARG, "%s: h must be positive", who);
     if (kind != SPS_RW && kind != SPS_MALA) return fail(c, SPS_ERR_ARG, "%s: unknown kind %d", who, kind);
     if (kind == SPS_MALA && !grad) return fail(c, SPS_ERR_ARG, "%s: MALA needs grad", who);
     if (prec != SPS_FP64 && prec != SPS_FP32 && prec != SPS_BF16X3)
@@ -858,7 +870,7 @@ static int mutate_launch(sps_ctx* c, const char* who, double* theta, double* ll,
                 cov_partial_small_kernel<4><<<nchunk, 256, 0, c->stream>>>(theta, P, d, chunk, part, psum, z2);
             SPS_CHECK(launched(c, "cov_partial_small_kernel"));
             cov_final_kernel<<<(unsigned)(((int64_t)d * d + 3) / 4), 256, 0, c->stream>>>(part, psum, nchunk, d,
-                                                                                          P, h, Sg);
+                                                                                          P, h, Sg, h_dev, stop);
             SPS_CHECK(launched(c, "cov_final_kernel"));
         }
         cholesky_small_kernel<<<1, 256, 0, c->stream>>>(Sg, d, L, flags);
@@ -875,7 +887,7 @@ static int mutate_launch(sps_ctx* c, const char* who, double* theta, double* ll,
                 theta, P, d, chunk, part, psum);
             SPS_CHECK(launched(c, "cov_partial_kernel"));
             cov_final_kernel<<<(unsigned)(((int64_t)d * d + 3) / 4), 256, 0, c->stream>>>(part, psum, nchunk, d,
-                                                                                          P, h, Sg);
+                                                                                          P, h, Sg, h_dev, stop);
             SPS_CHECK(launched(c, "cov_final_kernel"));
         }
         if (d <= 512) cholesky_blocked_kernel<32, 512><<<1, 1024, 0, c->stream>>>(Sg, d, L, LT, flags);
@@ -926,7 +938,7 @@ static int mutate_launch(sps_ctx* c, const char* who, double* theta, double* ll,
             SPS_CHECK(gemm_abt(c, z, L, theta, th2, P, d, 1.0));
         }
         LoglikSplit sp;
-        SPS_CHECK(loglik_launch_split(c, th2, P, 0, t, prec, ll2, nullptr, &sp));
+        SPS_CHECK(loglik_launch_split(c, th2, P, 0, t, prec, ll2, nullptr, &sp, stop));
         ll2s = sp.ll;
         ll2n = sp.n;
         if (c->prior_full) SPS_CHECK(prior_whiten(c, th2, P, wtmp, R1));
@@ -951,7 +963,7 @@ static int mutate_launch(sps_ctx* c, const char* who, double* theta, double* ll,
         f.zstream = stream;
         SPS_CHECK(gemm_small<GM_MALA_FWD>(c, f));
         LoglikSplit sp;
-        SPS_CHECK(loglik_launch_split(c, th2, P, 0, t, prec, ll2, g2, &sp));
+        SPS_CHECK(loglik_launch_split(c, th2, P, 0, t, prec, ll2, g2, &sp, stop));
         ll2s = sp.ll;
         ll2n = sp.n;
         SmallGemm r{};
@@ -977,7 +989,7 @@ static int mutate_launch(sps_ctx* c, const char* who, double* theta, double* ll,
         SPS_CHECK(grad_logpost(grad, theta, R0, gpi));
         SPS_CHECK(gemm_abt(c, gpi, LT, z, uu, P, d, 0.5));
         SPS_CHECK(gemm_abt(c, uu, L, theta, th2, P, d, 1.0));
-        SPS_CHECK(loglik_launch(c, th2, P, 0, t, prec, ll2, g2));
+        SPS_CHECK(loglik_launch(c, th2, P, 0, t, prec, ll2, g2, stop));
         SPS_CHECK(grad_logpost(g2, th2, R1, gpi));
         SPS_CHECK(gemm_abt(c, gpi, LT, uu, v, P, d, 0.5));
     } else {
@@ -988,7 +1000,7 @@ static int mutate_launch(sps_ctx* c, const char* who, double* theta, double* ll,
         SPS_CHECK(grad_logpost(grad, theta, R0, gpi));
         SPS_CHECK(gemm_abt(c, gpi, Sg, theta, work, P, d, 0.5));
         SPS_CHECK(gemm_abt(c, z, L, work, th2, P, d, 1.0));
-        SPS_CHECK(loglik_launch(c, th2, P, 0, t, prec, ll2, g2));
+        SPS_CHECK(loglik_launch(c, th2, P, 0, t, prec, ll2, g2, stop));
         // v = L^-1 (theta - mu(theta'))
         if (c->prior_full) SPS_CHECK(prior_whiten(c, th2, P, wtmp, R1));
         SPS_CHECK(grad_logpost(g2, th2, R1, gpi));
@@ -1000,10 +1012,56 @@ static int mutate_launch(sps_ctx* c, const char* who, double* theta, double* ll,
     accept_kernel<<<(unsigned)((P + kAccPerBlock - 1) / kAccPerBlock), 256, 0, c->stream>>>(
         theta, ll, grad, th2, ll2s, mala ? (const double*)c->grad2.p : nullptr, z,
         mala ? (const double*)c->pstat.p : nullptr, u, c->prior_mean, c->prior_isd, R0, R1, P, d,
-        mala ? 1 : 0, flags, count, seed, stream, ll2n);
+        mala ? 1 : 0, flags, count, seed, stream, ll2n, stop);
     SPS_CHECK(launched(c, "accept_kernel"));
     c->has_sigma = true;
     return SPS_OK;
+}
+
+// Device-resident state of an M phase (sps_mphase).  The step size h is read
+// by the covariance kernel of the next step; the stop word by every launch
+// of a step that writes what the caller sees.
+struct MState {
+    double h;        // step size for the next step
+    double agg;      // aggregate RNE after the last step taken
+    double rate;     // acceptance rate of the last step taken
+    int32_t r;       // steps taken
+    unsigned stop;   // nonzero: the phase has ended; later queued steps do nothing
+    unsigned notpd;  // the last step's proposal covariance was not positive definite
+    unsigned pad;
+};
+
+__global__ void mstate_init_kernel(MState* s, double h) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *s = MState{h, 0.0, 0.0, 0, 0u, 0u, 0u};
+}
+
+// After each step: the acceptance rate from the count slots, the step-size
+// rule of Algorithm 2 (h up by h_step when the rate is above the target, else
+// down, within [h_min, h_max]) and the stopping rule (aggregate RNE at least
+// K, or R_max steps), with the same expressions and order as a host loop
+// would use, so the steps taken and the h they use do not change.
+__global__ __launch_bounds__(64) void mstep_control_kernel(MState* s, const unsigned* flags, const double* agg,
+                                                           const unsigned long long* count, int64_t P,
+                                                           double h_step, double h_min, double h_max,
+                                                           double acc_target, double K, int32_t R_max) {
+    if (threadIdx.x != 0 || s->stop) return;
+    const int32_t r = s->r + 1;
+    s->r = r;
+    if (*flags & kFlagNotPD) {
+        s->notpd = 1u;
+        s->stop = 1u;
+        return;
+    }
+    unsigned long long n_acc = 0;
+    for (int q = 0; q < kCountSlots; ++q) n_acc += count[q * kCountStride];
+    const double rate = (double)n_acc / (double)P;
+    const double a = *agg;
+    const double h = s->h;
+    const double up = h + h_step, dn = h - h_step;
+    s->h = rate > acc_target ? (h_max < up ? h_max : up) : (dn < h_min ? h_min : dn);
+    s->rate = rate;
+    s->agg = a;
+    if (a >= K || r >= R_max) s->stop = 1u;
 }
 
 // Read back the step's status block (flags, aggregate RNE, accepted-count
@@ -1066,10 +1124,15 @@ extern "C" int sps_last_sigma(sps_ctx* c, double* Sigma) {
 }
 
 // The M phase of one cycle (Algorithm 2 step 2(c)) in one call: steps
-// r = 1, 2, ... each take sps_mutate's step with h, then the monitored
-// functions, their NSE/RNE and the aggregate RNE on the device; one read-back
-// per step (flags, accepted count, aggregate) drives the step-size rule and
-// the stopping rule on the host.
+// r = 1, 2, ... each take sps_mutate's step, then the monitored functions,
+// their NSE/RNE and the aggregate RNE on the device, and a control kernel
+// applies the step-size and stopping rules on the device (h and the stop word
+// stay in device memory).  The host reads the state of step r
+// asynchronously while step r + 1 is already queued (lookahead 1), so the
+// GPU never waits for the host between steps; a step queued after the stop
+// does nothing (its launches test the stop word).  Steps whose non-likelihood
+// work is large (P d^2 above 2^28) are not queued ahead: there one read-back
+// per step costs less than a skipped step's covariance and proposal work.
 extern "C" int sps_mphase(sps_ctx* c, double* theta, double* ll, double* grad, int32_t J, int32_t N,
                           int64_t t, int kind, int prec, double* h, double h_step, double h_min,
                           double h_max, double acc_target, double K, int32_t R_max, int rne_rule,
@@ -1080,33 +1143,56 @@ extern "C" int sps_mphase(sps_ctx* c, double* theta, double* ll, double* grad, i
     if (!h || !g_work || !R_out || R_max < 1 || (rne_rule != 0 && rne_rule != 1) ||
         !(h_min > 0.0) || !(h_max >= h_min) || !(h_step >= 0.0) || !std::isfinite(K))
         return fail(c, SPS_ERR_ARG, "sps_mphase: bad arguments");
+    if (!(*h > 0.0) || !std::isfinite(*h)) return fail(c, SPS_ERR_ARG, "sps_mphase: h must be positive");
     if (J > 65535 || (N + 63) / 64 > 65535) return fail(c, SPS_ERR_ARG, "sps_mphase: J or N too large");
     const int64_t P = (int64_t)J * N;
     const int32_t d = c->d, m = c->d + c->C - 1;
-    double hh = *h;
-    int32_t r = 0;
-    double agg = 0.0, rate = 0.0;
+    SPS_CHECK(ensure(c, c->small, 4096, "small"));
+    SPS_CHECK(ensure(c, c->mstat, sizeof(MState), "M phase state"));
+    MState* ms = (MState*)c->mstat.p;
+    const unsigned* stop = &ms->stop;
+    mstate_init_kernel<<<1, 64, 0, c->stream>>>(ms, *h);
+    SPS_CHECK(launched(c, "mstate_init_kernel"));
+    const int look = (double)P * d * d <= (double)(1 << 28) ? 1 : 0;
+    PubTicket tk[2];
+    int head = 0, pending = 0;
+    int32_t queued = 0;
+    MState st{};
     for (;;) {
-        ++r;
-        const uint64_t st = stream0 + (uint64_t)r * stream_step;
-        SPS_CHECK(mutate_launch(c, "sps_mphase", theta, ll, grad, J, N, t, hh, nullptr, kind, prec, nullptr,
-                                nullptr, seed, st));
-        if (sigma_out)
-            SPS_HIP(c, hipMemcpyAsync(sigma_out + (size_t)(r - 1) * d * d, c->chol.p, sizeof(double) * d * d,
-                                      hipMemcpyDeviceToDevice, c->stream));
-        SPS_CHECK(monitor_launch(c, theta, P, g_work));
-        double* mom = nullptr;
-        SPS_CHECK(moments_launch(c, g_work, J, N, m, &mom));
-        SPS_CHECK(rne_aggregate(c, mom, m, rne_rule, (double*)((char*)c->small.p + 16)));
+        while (queued < R_max && pending <= look) {
+            ++queued;
+            const uint64_t sid = stream0 + (uint64_t)queued * stream_step;
+            SPS_CHECK(mutate_launch(c, "sps_mphase", theta, ll, grad, J, N, t, 0.0, nullptr, kind, prec, nullptr,
+                                    nullptr, seed, sid, &ms->h, stop));
+            if (sigma_out)
+                SPS_HIP(c, hipMemcpyAsync(sigma_out + (size_t)(queued - 1) * d * d, c->chol.p,
+                                          sizeof(double) * d * d, hipMemcpyDeviceToDevice, c->stream));
+            SPS_CHECK(monitor_launch(c, theta, P, g_work));
+            double* mom = nullptr;
+            SPS_CHECK(moments_launch(c, g_work, J, N, m, &mom));
+            double* agg = (double*)((char*)c->small.p + 16);
+            SPS_CHECK(rne_aggregate(c, mom, m, rne_rule, agg));
+            mstep_control_kernel<<<1, 64, 0, c->stream>>>(
+                ms, (const unsigned*)c->small.p, agg, (const unsigned long long*)((char*)c->small.p + kCountOff),
+                P, h_step, h_min, h_max, acc_target, K, R_max);
+            SPS_CHECK(launched(c, "mstep_control_kernel"));
+            SPS_CHECK(publish_async(c, ms, sizeof(MState), &tk[(head + pending) & 1]));
+            ++pending;
+        }
         const void* rec = nullptr;
-        SPS_CHECK(mutate_readback(c, "sps_mphase", P, &rate, &rec));
-        agg = *(const double*)((const char*)rec + 16);
-        hh = rate > acc_target ? std::min(hh + h_step, h_max) : std::max(hh - h_step, h_min);
-        if (agg >= K || r >= R_max) break;
+        SPS_CHECK(publish_wait(c, tk[head], &rec));
+        st = *(const MState*)rec;
+        head ^= 1;
+        --pending;
+        if (st.stop) break;
+        if (queued >= R_max && pending == 0)
+            return fail(c, SPS_ERR_HIP, "sps_mphase: the M phase did not stop after R_max steps");
     }
-    *h = hh;
-    *R_out = r;
-    if (rne_out) *rne_out = agg;
-    if (rate_out) *rate_out = rate;
+    if (st.notpd)
+        return fail(c, SPS_ERR_NOT_PD, "sps_mphase: the proposal covariance is not positive definite");
+    *h = st.h;
+    *R_out = st.r;
+    if (rne_out) *rne_out = st.agg;
+    if (rate_out) *rate_out = st.rate;
     return SPS_OK;
 }

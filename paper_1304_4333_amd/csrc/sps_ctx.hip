@@ -360,7 +360,7 @@ extern "C" void sps_destroy(sps_ctx* c) {
     free_prior(c);
     Buf* bufs[] = {&c->part_ll, &c->part_g, &c->theta2, &c->ll2, &c->grad2, &c->cov, &c->chol,
                    &c->mean, &c->pstat, &c->z, &c->u, &c->u53, &c->corr_lw, &c->corr_red,
-                   &c->small, &c->W, &c->gstat, &c->suff};
+                   &c->small, &c->mstat, &c->W, &c->gstat, &c->suff, &c->pw};
     for (Buf* b : bufs)
         if (b->p) (void)hipFree(b->p);
     if (c->hostbuf.p) (void)hipHostFree(c->hostbuf.p);

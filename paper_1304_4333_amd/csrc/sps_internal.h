@@ -78,6 +78,7 @@ struct sps_ctx {
     sps::Buf corr_lw;    // C phase block of running log-weights
     sps::Buf corr_red;   // C phase per-observation reductions
     sps::Buf small;      // small device results (status words, sums)
+    sps::Buf mstat;      // device-resident state of the M phase (step size, stop word)
     sps::Buf hostbuf;    // pinned host staging for scalar read-back
     void* pub = nullptr;       // fine-grained pinned host memory written by publish_kernel
     size_t pub_bytes = 0;
@@ -131,8 +132,10 @@ inline int launched(sps_ctx* c, const char* what) {
 
 // Likelihood entry used by the phases (defined in loglik.hip).
 // Writes ll (and grad when non-null) for observations [t0, t1).
+// skip (optional, device): the likelihood kernel does nothing when *skip is
+// nonzero at the time it runs (the outputs are then left as they were).
 int loglik_launch(sps_ctx* c, const double* theta, int64_t P, int64_t t0, int64_t t1,
-                  int prec, double* ll, double* grad);
+                  int prec, double* ll, double* grad, const unsigned* skip = nullptr);
 // As loglik_launch, but when the kernel leaves observation-split partials and
 // no term is added after the sum (C = 2 or FP64), the sum is left to the
 // caller: out->ll holds out->n slices of P, out->g (grad given) out->n
@@ -144,7 +147,8 @@ struct LoglikSplit {
     int32_t n;
 };
 int loglik_launch_split(sps_ctx* c, const double* theta, int64_t P, int64_t t0, int64_t t1,
-                        int prec, double* ll, double* grad, LoglikSplit* out);
+                        int prec, double* ll, double* grad, LoglikSplit* out,
+                        const unsigned* skip = nullptr);
 // Device scratch supplied by the caller instead of the context's grow-only
 // buffers (sps_loglik_noalloc): part holds part_doubles doubles for the
 // observation-split partials, suff at least d doubles.
