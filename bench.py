@@ -191,6 +191,95 @@ def design_sweep(w, seeds, ess_fracs=(0.3, 0.5, 0.7), k_mids=(0.35, 0.9), kind="
     return rows
 
 
+def _logodds_row(r, C):
+    """The log-odds moments theta_c' xbar (c = 1 .. C-1; the last C-1
+    monitored functions) with their NSE and RNE, and the logML with its NSE."""
+    q = slice(len(r["mean"]) - (C - 1), None)
+    return dict(logodds=[round(float(v), 5) for v in r["mean"][q]],
+                logodds_nse=[round(float(v), 5) for v in r["nse"][q]],
+                logodds_rne=[round(float(v), 3) for v in r["rne"][q]],
+                logml=round(float(r["logml"]), 4), logml_nse=round(float(r["logml_nse"]), 4))
+
+
+def reliability_study(w, g=0.25, sizes=((10, 1000), (40, 2500)), runs=("A", "B", "C")):
+    """The one- and two-pass reliability study (Section 4.1, Table 2) on a
+    synthetic data set: for each J x N, independent runs of Algorithm 3, with
+    the log-odds moments, the log marginal likelihood and their NSEs at the
+    end of each pass.  Summary per J x N and pass: the spread of each estimate
+    over the runs against the mean reported NSE, and the largest within-run
+    pass 1 / pass 2 difference in units of sqrt(NSE_1^2 + NSE_2^2).  One JSON
+    line per pass and one per summary."""
+    import torch
+    from paper_1304_4333_amd import driver
+    X, y, _ = synth_data(w)
+    ctx = driver.setup(X, y, w.C, 0.0, g=g)
+    rows = []
+    for J, N in sizes:
+        per = {1: [], 2: []}
+        for i, run in enumerate(runs):
+            cfg = driver.SpsConfig(J=J, N=N, precision=w.precision, kind=w.kernel, seed=300 + i)
+            p1, p2 = driver.run_two_pass(ctx, cfg)
+            for pas, r in ((1, p1), (2, p2)):
+                row = dict(study="reliability", workload=w.name, g=g, J=J, N=N, run=run, pass_=pas,
+                           cycles=r["cycles"], m_steps=r["m_iters"], wall_s=round(r["wall"], 3),
+                           **_logodds_row(r, w.C))
+                per[pas].append(row)
+                rows.append(row)
+                print(json.dumps(row), flush=True)
+        torch.cuda.synchronize()
+        summ = dict(study="reliability_summary", workload=w.name, g=g, J=J, N=N, runs=len(runs))
+        for pas in (1, 2):
+            est = np.array([r["logodds"] + [r["logml"]] for r in per[pas]])
+            nse = np.array([r["logodds_nse"] + [r["logml_nse"]] for r in per[pas]])
+            summ[f"pass{pas}_sd_over_runs"] = np.round(est.std(axis=0, ddof=1), 5).tolist()
+            summ[f"pass{pas}_mean_nse"] = np.round(nse.mean(axis=0), 5).tolist()
+        z = [(np.array(a["logodds"] + [a["logml"]]) - np.array(b["logodds"] + [b["logml"]])) /
+             np.hypot(np.array(a["logodds_nse"] + [a["logml_nse"]]), np.array(b["logodds_nse"] + [b["logml_nse"]]))
+             for a, b in zip(per[1], per[2])]
+        summ["max_abs_z_pass1_vs_pass2"] = round(float(np.abs(np.array(z)).max()), 3)
+        summ["wall_ratio_two_pass_over_one"] = round(
+            float(sum(r["wall_s"] for r in per[1] + per[2]) / sum(r["wall_s"] for r in per[1])), 3)
+        rows.append(summ)
+        print(json.dumps(summ), flush=True)
+    return rows
+
+
+def g_sweep(w, gs=(1 / 64, 1 / 16, 1 / 4, 1.0, 4.0), sizes=((10, 1000), (40, 2500)), seeds=(1, 2, 3)):
+    """Adaptation against prior tightness (Section 4.2, Table 3) on a
+    synthetic data set: for each g of the g-prior (eq. (g-prior_def)) and
+    each J x N, Algorithm 2's cycles, M iterations, wall time relative to the
+    tightest prior, RNE of the log-odds moments, the logML and its NSE
+    (means over the seeds; the logML spread over seeds beside the NSE).  One
+    JSON line per g and J x N."""
+    import torch
+    from paper_1304_4333_amd import driver
+    X, y, _ = synth_data(w)
+    rows = []
+    for J, N in sizes:
+        base_wall = None
+        for g in gs:
+            ctx = driver.setup(X, y, w.C, 0.0, g=g)
+            rs = [driver.run_sps(ctx, driver.SpsConfig(J=J, N=N, precision=w.precision, kind=w.kernel, seed=s))
+                  for s in seeds]
+            torch.cuda.synchronize()
+            q = slice(w.d, None)
+            wall = float(np.mean([r["wall"] for r in rs]))
+            base_wall = base_wall or wall
+            lm = np.array([r["logml"] for r in rs])
+            row = dict(study="g_sweep", workload=w.name, g=g, J=J, N=N, seeds=len(seeds),
+                       cycles=float(np.mean([r["cycles"] for r in rs])),
+                       m_steps=float(np.mean([r["m_iters"] for r in rs])),
+                       wall_s=round(wall, 4), relative_time=round(wall / base_wall, 3),
+                       logodds_rne=np.round(np.mean([r["rne"][q] for r in rs], axis=0), 3).tolist(),
+                       logml=round(float(lm.mean()), 4),
+                       logml_nse=round(float(np.mean([r["logml_nse"] for r in rs])), 4),
+                       logml_sd_over_seeds=round(float(lm.std(ddof=1)), 4) if len(rs) > 1 else None)
+            rows.append(row)
+            print(json.dumps(row), flush=True)
+            del ctx
+    return rows
+
+
 def synth_data(w):
     from paper_1304_4333_amd import synth
     return synth.make_data(w)
@@ -496,6 +585,10 @@ def main():
     ap.add_argument("--design-sweep", action="store_true",
                     help="run Algorithm 2 over ESS thresholds and RNE targets and print one line each")
     ap.add_argument("--sweep-kind", default="rw", choices=["rw", "mala"])
+    ap.add_argument("--reliability", action="store_true",
+                    help="one- and two-pass reliability study (Table 2 design) on the cars3 workload")
+    ap.add_argument("--g-sweep", action="store_true",
+                    help="prior-tightness study (Table 3 design) over g = 1/64 .. 4 on the cars3 workload")
     ap.add_argument("--sps-only", action="store_true",
                     help="run only the fixed-NSE SPS comparison and print it")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -506,6 +599,14 @@ def main():
         return
     if args.kernel_table:
         kernel_table(args.kernel_table.split(","))
+        return
+    if args.reliability or args.g_sweep:
+        from paper_1304_4333_amd import synth
+        w = synth.workload("cars3")
+        if args.reliability:
+            reliability_study(w)
+        if args.g_sweep:
+            g_sweep(w)
         return
     if args.design_sweep:
         from paper_1304_4333_amd import synth

@@ -21,6 +21,12 @@ stand in for them, scaled up from the sizes of Table 1):
   multi4      4  20 000   20   60   16 x 2048    5          bf16x3
   ar100       2  50 000  100  100   32 x 1024    1          bf16x3
   multi6      6 200 000   50  250   64 x 1024    1          bf16x3
+  cars3       3     263    4    8   10 x 1000    g-prior    fp64
+
+cars3 has the shape of the paper's smallest multinomial data set (Table 1:
+T = 263, k = 4, C = 3; an intercept, one continuous covariate and two
+indicators); the reliability and prior-tightness studies (Tables 2 and 3) run
+on it with the g-prior of eq. (g-prior_def), J x N = 10 x 1000 and 40 x 2500.
 """
 from __future__ import annotations
 
@@ -93,6 +99,9 @@ WORKLOADS: Dict[str, Workload] = {
                        prior_sd=1.0, design="gauss_dummy", beta_sd=0.5,
                        n_dummy=10, dummy_p=0.2, precision="bf16x3",
                        kernel="mala", data_seed=1005),
+    "cars3": Workload("cars3", C=3, T=263, k=4, J=10, N=1000, prior_sd=1.0,
+                      design="gauss_dummy", beta_sd=0.7, n_dummy=2, dummy_p=0.4,
+                      precision="fp64", kernel="rw", data_seed=1006),
 }
 
 

@@ -16,6 +16,14 @@ where each side's mean and NSE pool its R independent runs
 - logML: the delta-method NSE of one run understates the spread over seeds,
   so its bar uses the spread: |difference| <= 3 sqrt(s_g^2 / R_g + s_o^2 / R_o)
   with s the sd of the per-run logML over seeds.
+- The adaptive schedule: the mean numbers of cycles and of M steps per run
+  agree within 5% and 10% (they vary by about 1% and 3% over seeds at
+  binary30), or within 3 standard errors of the difference of the means when
+  that is larger (a few cycles at cars3), and so does the mean number of
+  cycles that end at the R_max step cap (the random walk at d = 30 reaches it
+  in the early cycles on both sides).
+- cars3: the g-prior of eq. (g-prior_def) at the five g of Table 3, and
+  Algorithm 3, whose second pass is compared with the oracle's second pass.
 """
 import json
 import math
@@ -38,6 +46,9 @@ CASES = {
     "binary30_T200_rw": ("fp32", 6),
     "binary30_T200_mala": ("bf16x3", 6),
     "multi4_T200_rw": ("bf16x3", 4),
+    # the cars3 shape under the g-prior at the five g of Table 3, and Algorithm 3
+    **{f"cars3_g{tag}_rw": ("fp64", 4) for tag in ("1_64", "1_16", "1_4", "1", "4")},
+    "cars3_g1_4_two_pass": ("fp64", 4),
 }
 
 
@@ -64,30 +75,51 @@ def test_sps_vs_oracle_at_benchmark_shape(name):
     gold = _load(name)
     prec, R = CASES[name]
     w = synth.workload(gold["workload"], **gold["overrides"])
-    assert (w.C, w.T, w.k, w.J, w.N) == (gold["C"], gold["T"], gold["k"], gold["J"], gold["N"])
+    J, N = gold["J"], gold["N"]
+    assert (w.C, w.T, w.k) == (gold["C"], gold["T"], gold["k"])
     X, y, _ = synth.make_data(w)
-    ctx = driver.setup(X, y, w.C, 0.0, w.prior_sd)
+    g = gold.get("g")
+    ctx = driver.setup(X, y, w.C, 0.0, w.prior_sd, g=g)
+    two_pass = bool(gold.get("two_pass"))
     runs, walls = [], []
     for i in range(R):
         seed = 2000 + i
-        print(f"sps parity {name} prec={prec} kind={gold['kind']} seed={seed}", flush=True)
-        base = dict(J=w.J, N=w.N, precision=prec, seed=seed)
+        print(f"sps parity {name} prec={prec} kind={gold['kind']} g={g} two_pass={two_pass} seed={seed}",
+              flush=True)
+        base = dict(J=J, N=N, precision=prec, seed=seed)
         cfg = driver.SpsConfig.mala_defaults(**base) if gold["kind"] == "mala" else driver.SpsConfig(**base)
         t0 = time.perf_counter()
-        r = driver.run_sps(ctx, cfg)
+        if two_pass:
+            r1, r = driver.run_two_pass(ctx, cfg)
+            r["hit_R_max"] = r1["hit_R_max"]
+        else:
+            r = driver.run_sps(ctx, cfg)
         walls.append(time.perf_counter() - t0)
-        assert r["hit_R_max"] == 0
-        runs.append(dict(mean=r["mean"], nse=r["nse"], logml=r["logml"]))
+        runs.append(dict(mean=r["mean"], nse=r["nse"], logml=r["logml"], cycles=r["cycles"],
+                         m_iters=r["m_iters"], hit_R_max=r["hit_R_max"]))
+    # Algorithm 3: the second pass (the nonadaptive algorithm, where the
+    # central limit theorem behind the NSE holds) against the oracle's
+    gruns = gold["pass2_runs"] if two_pass else gold["runs"]
     mg, ng, lg = _pool(runs)
-    mo, no, lo = _pool(gold["runs"])
+    mo, no, lo = _pool(gruns)
     z = (mg - mo) / np.sqrt(ng ** 2 + no ** 2)
-    df = min(R, len(gold["runs"])) * (w.J - 1)
+    df = min(R, len(gruns)) * (J - 1)
     ks = stats.kstest(z, "t", args=(df,))
     sg, so = lg.std(ddof=1), lo.std(ddof=1)
     zl = (lg.mean() - lo.mean()) / math.sqrt(sg ** 2 / len(lg) + so ** 2 / len(lo))
     print(f"{name}: {len(z)} moments, max |z| {np.abs(z).max():.2f}, exceedances {int((np.abs(z) > 3).sum())}, "
           f"KS p {ks.pvalue:.3f}; logML gpu {lg.mean():.4f} oracle {lo.mean():.4f} z {zl:.2f}; "
           f"wall per run gpu {np.mean(walls):.3f} s oracle {np.mean([r['wall_s'] for r in gold['runs']]):.2f} s")
+    def sched(key, rel, floor):
+        a = np.array([r[key] for r in runs], dtype=float)
+        b = np.array([r[key] for r in gruns], dtype=float)
+        se = math.sqrt(a.var(ddof=1) / len(a) + b.var(ddof=1) / len(b))
+        bar = max(rel * b.mean(), 3.0 * se, floor)
+        print(f"  {key}: gpu {a.mean():.2f} oracle {b.mean():.2f} bar {bar:.2f}")
+        return abs(a.mean() - b.mean()) <= bar
+    assert sched("cycles", 0.05, 1.0)
+    assert sched("m_iters", 0.10, 1.0)
+    assert sched("hit_R_max", 0.25, 1.0)
     assert int((np.abs(z) > 3).sum()) <= 1, np.round(z, 2)
     assert ks.pvalue > 1e-3
     assert abs(zl) <= 3.0
