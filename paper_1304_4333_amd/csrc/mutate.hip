@@ -1127,12 +1127,11 @@ extern "C" int sps_last_sigma(sps_ctx* c, double* Sigma) {
 // r = 1, 2, ... each take sps_mutate's step, then the monitored functions,
 // their NSE/RNE and the aggregate RNE on the device, and a control kernel
 // applies the step-size and stopping rules on the device (h and the stop word
-// stay in device memory).  The host reads the state of step r
-// asynchronously while step r + 1 is already queued (lookahead 1), so the
-// GPU never waits for the host between steps; a step queued after the stop
-// does nothing (its launches test the stop word).  Steps whose non-likelihood
-// work is large (P d^2 above 2^28) are not queued ahead: there one read-back
-// per step costs less than a skipped step's covariance and proposal work.
+// stay in device memory).  For launch-bound steps the host reads the state of
+// step r asynchronously while step r + 1 is already queued (lookahead 1); a
+// step queued after the stop leaves every output unchanged (its covariance,
+// likelihood and accept launches test the stop word).  Other steps are read
+// back one at a time.
 extern "C" int sps_mphase(sps_ctx* c, double* theta, double* ll, double* grad, int32_t J, int32_t N,
                           int64_t t, int kind, int prec, double* h, double h_step, double h_min,
                           double h_max, double acc_target, double K, int32_t R_max, int rne_rule,
@@ -1153,7 +1152,14 @@ extern "C" int sps_mphase(sps_ctx* c, double* theta, double* ll, double* grad, i
     const unsigned* stop = &ms->stop;
     mstate_init_kernel<<<1, 64, 0, c->stream>>>(ms, *h);
     SPS_CHECK(launched(c, "mstate_init_kernel"));
-    const int look = (double)P * d * d <= (double)(1 << 28) ? 1 : 0;
+    // Queue a step ahead only where steps are launch-bound (little GPU work
+    // per step): there the skipped step at the end of the phase runs while
+    // the host is still launching the next phase.  Where the GPU is the
+    // bottleneck, that step's covariance and proposal kernels would delay
+    // the next phase by more than the read-back waits cost (measured at
+    // binary30: 3.5 MALA steps per phase, 78 us lost per phase).
+    const double step_work = (double)P * (double)std::max<int64_t>(t, 1) * d;
+    const int look = (step_work <= (double)(1 << 26) && (double)P * d * d <= (double)(1 << 28)) ? 1 : 0;
     PubTicket tk[2];
     int head = 0, pending = 0;
     int32_t queued = 0;

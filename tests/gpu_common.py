@@ -45,3 +45,15 @@ def rel_err(a, b):
     a = np.asarray(a, dtype=np.float64)
     b = np.asarray(b, dtype=np.float64)
     return np.abs(a - b) / np.maximum(1.0, np.abs(b))
+
+
+def check_nse_bar(z, zl=None, what=""):
+    """The end-to-end bar of 3 numerical standard errors: every |z| of the
+    monitored moments within 3, with at most one exceedance (multiplicity over
+    up to 31 moments with t-distributed z), and the logML's |z| within 3."""
+    z = np.abs(np.asarray(z, dtype=float))
+    print(f"{what} max |z| {z.max():.2f}, exceedances {int((z > 3).sum())}"
+          + ("" if zl is None else f", logML |z| {abs(zl):.2f}"), flush=True)
+    assert int((z > 3.0).sum()) <= 1, np.round(z, 2)
+    if zl is not None:
+        assert abs(zl) <= 3.0

@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 from scipy import integrate, special, stats
 
-from gpu_common import need_gpu
+from gpu_common import check_nse_bar, need_gpu
 from paper_1304_4333_amd import synth
 
 pytestmark = pytest.mark.gpu
@@ -37,10 +37,9 @@ def test_sps_small_workload_vs_oracle(orc, prec, kind):
     assert g["hit_R_max"] == 0
     z = _z(g["mean"], o["mean"], g["nse"], o["nse"])
     print("z-scores of the monitored means:", np.round(z, 2))
-    assert z.max() < 4.0
     zl = abs(g["logml"] - o["logml"]) / math.hypot(g["logml_nse"], o["logml_nse"])
     print("logML gpu %.4f [%.4f] oracle %.4f [%.4f]" % (g["logml"], g["logml_nse"], o["logml"], o["logml_nse"]))
-    assert zl < 4.0
+    check_nse_bar(z, zl)
     assert np.allclose(g["sd"], o["sd"], rtol=0.1)
 
 
@@ -56,8 +55,8 @@ def test_sps_intercept_model_vs_quadrature():
     m1 = integrate.quad(lambda a: a * f(a), -12, 12, epsabs=0, epsrel=1e-12, limit=400)[0] / Z
     ctx = driver.setup(X, y, 2, 0.0, 5.0)
     r = driver.run_sps(ctx, driver.SpsConfig(J=16, N=1024, precision="fp64", seed=3))
-    assert abs(r["mean"][0] - m1) < 4 * r["nse"][0] + 1e-4
-    assert abs(r["logml"] - math.log(Z)) < 4 * r["logml_nse"] + 0.01
+    assert abs(r["mean"][0] - m1) < 3 * r["nse"][0] + 1e-4
+    assert abs(r["logml"] - math.log(Z)) < 3 * r["logml_nse"] + 0.01
 
 
 def test_sps_single_observation_logml():
@@ -69,7 +68,7 @@ def test_sps_single_observation_logml():
     ctx = driver.setup(X, y, 2, 0.0, 5.0)
     r = driver.run_sps(ctx, driver.SpsConfig(J=16, N=2048, precision="fp32", seed=4))
     assert r["cycles"] == 1
-    assert abs(r["logml"] + math.log(2.0)) < 4 * r["logml_nse"] + 1e-12
+    assert abs(r["logml"] + math.log(2.0)) < 3 * r["logml_nse"] + 1e-12
 
 
 def test_two_pass_vs_oracle_two_pass(orc):
@@ -87,9 +86,8 @@ def test_two_pass_vs_oracle_two_pass(orc):
     assert o2["cycles"] == o1["cycles"]
     z = _z(g2["mean"], o2["mean"], g2["nse"], o2["nse"])
     print("two-pass z-scores:", np.round(z, 2))
-    assert z.max() < 4.0
     zl = abs(g2["logml"] - o2["logml"]) / math.hypot(g2["logml_nse"], o2["logml_nse"])
-    assert zl < 4.0
+    check_nse_bar(z, zl)
 
 
 def test_predictive_likelihoods_vs_quadrature():
@@ -118,11 +116,10 @@ def test_predictive_likelihoods_vs_quadrature():
     for rec in r["records"]:
         exact = logZ(rec["t"]) - logZ(rec["t_prev"])
         err = abs(rec["pred"] - exact)
-        zs.append(err / max(rec["pred_nse"], 1e-12))
-        assert err < 4 * rec["pred_nse"] + 2e-3, (rec, exact)
-    print("cycles", len(zs), "max z", round(max(zs), 2))
+        zs.append(max(0.0, err - 2e-3) / max(rec["pred_nse"], 1e-12))
+    check_nse_bar(zs, what=f"{len(zs)} cycles:")
     # the predictive likelihoods chain to the marginal likelihood of all T observations
-    assert abs(sum(rec["pred"] for rec in r["records"]) - logZ(T)) < 4 * r["logml_nse"] * len(zs) ** 0.5 + 0.02
+    assert abs(sum(rec["pred"] for rec in r["records"]) - logZ(T)) < 3 * r["logml_nse"] * len(zs) ** 0.5 + 0.02
 
 
 @pytest.mark.parametrize("prec,kind", [("fp64", "rw"), ("bf16x3", "mala")])
@@ -167,6 +164,5 @@ def test_sps_multinomial_vs_oracle(orc, prec, kind):
     o = orc.sps_run(X, y, 3, 0.0, 5.0, J, N, seed=32, **okw)
     z = _z(g["mean"], o["mean"], g["nse"], o["nse"])
     print("z-scores:", np.round(z, 2))
-    assert z.max() < 4.0
     zl = abs(g["logml"] - o["logml"]) / math.hypot(g["logml_nse"], o["logml_nse"])
-    assert zl < 4.0
+    check_nse_bar(z, zl)
