@@ -512,7 +512,7 @@ def cpu_baseline(w, seconds, seed=1):
                 one_thread_loglik_value=round(r_one, 1), host=cpu_info())
 
 
-def kernel_table(names, reps=5):
+def kernel_table(names, reps=5, precisions=("fp64", "fp32", "bf16x3")):
     """Full-data sps_loglik and sps_loglik_grad throughput through the ABI
     (main kernel + split reduction + sufficient-statistic terms), per
     workload and precision, with particles at posterior scale."""
@@ -526,7 +526,7 @@ def kernel_table(names, reps=5):
         th = torch.from_numpy(synth.make_particles(w.P, w.d, scale=0.02, seed=1, center=B.reshape(-1))).cuda()
         ll = torch.empty(w.P, dtype=torch.float64, device="cuda")
         g = torch.empty(w.P, w.d, dtype=torch.float64, device="cuda")
-        for prec_name in ("fp64", "fp32", "bf16x3"):
+        for prec_name in precisions:
             prec = sps.PREC[prec_name]
             for grad in (False, True):
                 def call():
@@ -582,6 +582,9 @@ def main():
                          "(the paper's 0.1 is above the RW optimum 2.38^2/d at d = 100)")
     ap.add_argument("--kernel-table", default=None,
                     help="comma-separated workloads: print full-data loglik/grad rates instead")
+    ap.add_argument("--table-precisions", default="fp64,fp32,bf16x3",
+                    help="precisions of the kernel table (comma-separated)")
+    ap.add_argument("--table-reps", type=int, default=5, help="timed calls per kernel-table entry")
     ap.add_argument("--design-sweep", action="store_true",
                     help="run Algorithm 2 over ESS thresholds and RNE targets and print one line each")
     ap.add_argument("--sweep-kind", default="rw", choices=["rw", "mala"])
@@ -598,7 +601,8 @@ def main():
         copy_calibration()
         return
     if args.kernel_table:
-        kernel_table(args.kernel_table.split(","))
+        kernel_table(args.kernel_table.split(","), reps=args.table_reps,
+                     precisions=tuple(args.table_precisions.split(",")))
         return
     if args.reliability or args.g_sweep:
         from paper_1304_4333_amd import synth
