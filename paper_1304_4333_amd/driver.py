@@ -71,9 +71,10 @@ def run_sps(ctx: sps.Context, cfg: SpsConfig, log=None, record: bool = False,
             fused: bool = True) -> dict:
     """One pass of the adaptive SPS (Algorithm 2) on the data and prior set in
     ctx.  record=True also returns the Design of Algorithm 3's first pass.
-    fused=True runs each cycle's M phase in one library call (sps_mphase, one
-    read-back per step); False takes it step by step from here (same
-    arithmetic, more host round trips)."""
+    fused=True runs each cycle's M phase in one library call (sps_mphase: the
+    step-size and stopping rules on the device, a small state record read per
+    step); False takes it step by step from here (same arithmetic, more host
+    round trips)."""
     J, N = cfg.J, cfg.N
     P, d, C, T = J * N, ctx.d, ctx.C, ctx.T
     m = d + C - 1
