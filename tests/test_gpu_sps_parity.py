@@ -9,8 +9,9 @@ structure of Section 2.1), per monitored moment:
 where each side's mean and NSE pool its R independent runs
 (NSE^2 = mean of the runs' NSE^2 / R).
 - Multiplicity: with m moments and df = R (J - 1) on each side, P(|z| > 3)
-  is about 0.003-0.004 per moment, so at most one exceedance is allowed
-  (two or more at no fault has probability below 1% for m <= 31).
+  = p3 is about 0.003-0.004 per moment; the number of exceedances allowed is
+  the 99% point of Binomial(m, p3), at least one (one for m <= 31, two for
+  the 63 moments of multi4).
 - Calibration: all z together must pass a KS test against t(df) at
   p > 0.001 (eq. (gbar_tstat)).
 - logML: the delta-method NSE of one run understates the spread over seeds,
@@ -120,6 +121,9 @@ def test_sps_vs_oracle_at_benchmark_shape(name):
     assert sched("cycles", 0.05, 1.0)
     assert sched("m_iters", 0.10, 1.0)
     assert sched("hit_R_max", 0.25, 1.0)
-    assert int((np.abs(z) > 3).sum()) <= 1, np.round(z, 2)
+    p3 = 2 * stats.t.sf(3.0, df)
+    allowed = max(1, int(stats.binom.ppf(0.99, len(z), p3)))
+    print(f"  exceedances allowed: {allowed} (m = {len(z)}, P(|t_{df}| > 3) = {p3:.4f})")
+    assert int((np.abs(z) > 3).sum()) <= allowed, np.round(z, 2)
     assert ks.pvalue > 1e-3
     assert abs(zl) <= 3.0
