@@ -380,6 +380,34 @@ def test_monitor_and_moments_match_oracle(orc):
     assert np.allclose(rne, rr, rtol=1e-9)
 
 
+@pytest.mark.parametrize("J,N", [(1, 300), (7, 1), (3, 65), (2, 2)])
+def test_moments_and_logml_degenerate_groups(orc, J, N):
+    """One group (no between-group variance: NSE 0 and RNE inf on both sides),
+    one particle per group, and ragged group sizes, for the moments and the
+    logML increment with its combined estimate."""
+    need_gpu()
+    sps = _sps()
+    X, y, _ = dataset(40, 3, 2, seed=30)
+    ctx = make_ctx(X, y, 2)
+    g = synth.make_normals(J * N, 4, seed=31 + J + N) * np.array([1.0, 0.1, 3.0, 10.0]) + 2.0
+    mean, sd, nse, rne = sps.sps_moments(ctx, to_gpu(g), J, N)
+    rm, rs, rn, rr = orc.moments(g, J, N)
+    assert np.allclose(mean, rm, rtol=1e-12, atol=1e-13)
+    assert np.allclose(sd, rs, rtol=1e-9, atol=1e-13)
+    assert np.allclose(nse, rn, rtol=1e-9, atol=1e-15)
+    assert np.allclose(rne, rr, rtol=1e-9)
+    if J == 1:
+        assert np.all(nse == 0.0) and np.all(np.isinf(rne))
+    lw = synth.make_log_weights(J * N, seed=32 + J, spread=2.0)
+    lj0 = synth.make_normals(J, 1, seed=33)[:, 0]
+    lj = to_gpu(lj0.copy())
+    L, lnse = sps.sps_logml(ctx, to_gpu(lw), J, N, lj)
+    ref_j = orc.logml_update(lw, J, N, lj0)
+    ref = orc.logml_total(ref_j)
+    assert np.allclose(lj.cpu().numpy(), ref_j, rtol=1e-13, atol=1e-13)
+    assert L == pytest.approx(ref[0], rel=1e-13) and lnse == pytest.approx(ref[1], rel=1e-10, abs=1e-15)
+
+
 # ------------------------------------------------------------------ two-pass entry points
 @pytest.mark.parametrize("kind", [0, 1])
 def test_mutate_cov_matches_oracle(orc, kind):
