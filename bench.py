@@ -160,6 +160,36 @@ def sps_fixed_nse(w, seeds, rw_hmin=0.1):
             "mixing_gain_per_call": round(steps_ratio / (t_gr / t_ll), 3)}
 
 
+def sps_run_counts(w, seed=1):
+    """One whole adaptive SPS run (Algorithm 2) on the workload with its own
+    precision and M-phase kernel: GPU wall time, cycles, M steps, and the
+    particle x observation likelihood evaluations the run made (C phases:
+    P (t_l - t_{l-1}); M steps: P t_l each, as gradient evaluations with
+    MALA, which also refreshes the gradient once per cycle).  With a CPU rate
+    in evals/s for the same mix, evals / rate estimates the oracle's wall
+    time for the same run."""
+    import torch
+    from paper_1304_4333_amd import driver
+    X, y, _ = synth_data(w)
+    ctx = driver.setup(X, y, w.C, 0.0, w.prior_sd)
+    base = dict(J=w.J, N=w.N, precision=w.precision, seed=seed)
+    cfg = driver.SpsConfig.mala_defaults(**base) if w.kernel == "mala" else driver.SpsConfig(**base)
+    r = driver.run_sps(ctx, cfg, log=_progress(f"{w.name} seed {seed}"))
+    torch.cuda.synchronize()
+    P = w.P
+    c_evals = sum(P * (rec["t"] - rec["t_prev"]) for rec in r["records"])
+    m_evals = sum(P * rec["t"] * rec["R"] for rec in r["records"])
+    refresh = sum(P * rec["t"] for rec in r["records"]) if w.kernel == "mala" else 0
+    row = dict(study="sps_run", workload=w.name, precision=w.precision, kernel=w.kernel, seed=seed,
+               wall_s=round(r["wall"], 3), cycles=r["cycles"], m_steps=r["m_iters"],
+               hit_R_max=r["hit_R_max"], logml=round(float(r["logml"]), 4),
+               c_phase_evals=c_evals, m_step_evals=m_evals, gradient_refresh_evals=refresh,
+               m_steps_are_gradient_evals=w.kernel == "mala")
+    print(json.dumps(row), flush=True)
+    del ctx
+    return row
+
+
 def design_sweep(w, seeds, ess_fracs=(0.3, 0.5, 0.7), k_mids=(0.35, 0.9), kind="rw"):
     """Algorithm 2 with other design constants (Section 2.3 discusses them):
     the ESS threshold of the C phase and the RNE target K of the cycles before
@@ -590,6 +620,8 @@ def main():
     ap.add_argument("--sweep-kind", default="rw", choices=["rw", "mala"])
     ap.add_argument("--reliability", action="store_true",
                     help="one- and two-pass reliability study (Table 2 design) on the cars3 workload")
+    ap.add_argument("--sps-run", default=None,
+                    help="comma-separated workloads: one whole adaptive SPS run each, with its evaluation counts")
     ap.add_argument("--g-sweep", action="store_true",
                     help="prior-tightness study (Table 3 design) over g = 1/64 .. 4 on the cars3 workload")
     ap.add_argument("--sps-only", action="store_true",
@@ -603,6 +635,11 @@ def main():
     if args.kernel_table:
         kernel_table(args.kernel_table.split(","), reps=args.table_reps,
                      precisions=tuple(args.table_precisions.split(",")))
+        return
+    if args.sps_run:
+        from paper_1304_4333_amd import synth
+        for name in args.sps_run.split(","):
+            sps_run_counts(synth.workload(name))
         return
     if args.reliability or args.g_sweep:
         from paper_1304_4333_amd import synth
