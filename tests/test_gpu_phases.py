@@ -344,13 +344,17 @@ def test_mutate_drawn_variates_match_explicit(orc, kind, C, k):
         assert np.array_equal(g1.cpu().numpy(), g2.cpu().numpy())
 
 
-def test_mutate_not_pd_leaves_state():
+@pytest.mark.parametrize("k", [5, 80])
+def test_mutate_not_pd_leaves_state(k):
+    """Three distinct particles repeated: the pooled covariance has rank 2, so
+    the Cholesky (in LDS for d <= 64, blocked for d > 64) reports it and the
+    step changes nothing."""
     need_gpu()
     import torch
     sps = _sps()
-    X, y, _ = dataset(100, 5, 2, seed=24)
+    X, y, _ = dataset(100, k, 2, seed=24)
     ctx = make_ctx(X, y, 2)
-    base = synth.make_particles(3, 5, seed=25)
+    base = synth.make_particles(3, k, seed=25)
     th = to_gpu(np.repeat(base, 32, axis=0))
     ll = torch.zeros(96, dtype=torch.float64, device="cuda")
     before = th.clone()
