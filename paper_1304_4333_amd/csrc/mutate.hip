@@ -28,60 +28,69 @@ static_assert(kStatusBytes <= 4096, "the status block fits the small buffer and 
 
 // Sample variance in one pass, shifted by the first particle c = theta[0]
 // for stability: over each chunk of particles
-//   part[chunk][a][b] = sum_p (theta_pa - c_a)(theta_pb - c_b),
+//   part[chunk][a][b] = sum_p (theta_pa - c_a)(theta_pb - c_b),  a <= b,
 //   psum[chunk][a]    = sum_p (theta_pa - c_a).
-// 64 x 64 tile per block, 4 x 4 per thread, particles in steps of 16.  The
-// (a, b) and (b, a) tiles run the same arithmetic in the same order, so V
-// comes out exactly symmetric.
+// 64 x 64 (a, b) tile per block on the FP64 matrix cores (16 x 16 x 4 over
+// particles), particles staged in LDS 32 at a time, transposed (rows a, b;
+// padded to 33 doubles).  Only tiles that reach the upper triangle run; the
+// final kernel reads entry (min(a, b), max(a, b)), so V is exactly symmetric.
+// psum comes from the diagonal tiles, summed in particle order.
+constexpr int kCovK = 32;
+typedef double f64x4 __attribute__((ext_vector_type(4)));
 __global__ __launch_bounds__(256) void cov_partial_kernel(const double* __restrict__ theta, int64_t P,
                                                           int32_t d, int64_t chunk,
                                                           double* __restrict__ part,
                                                           double* __restrict__ psum) {
-    __shared__ double As[16][65];
-    __shared__ double Bs[16][65];
-    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    __shared__ double As[64][kCovK + 1];
+    __shared__ double Bs[64][kCovK + 1];
+    if (blockIdx.y < blockIdx.x) return;  // the tile lies below the diagonal
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int m = lane & 15, kg = lane >> 4;
     const int a0 = blockIdx.x * 64, b0 = blockIdx.y * 64;
+    const bool diag = blockIdx.x == blockIdx.y;
     const int64_t pbeg = (int64_t)blockIdx.z * chunk;
     const int64_t pend = std::min<int64_t>(P, pbeg + chunk);
-    double acc[4][4] = {};
-    double cs[4] = {0, 0, 0, 0};
-    for (int64_t p0 = pbeg; p0 < pend; p0 += 16) {
-        for (int e = threadIdx.x; e < 16 * 64; e += 256) {
-            const int r = e >> 6, cc = e & 63;
+    f64x4 acc[4];
+#pragma unroll
+    for (int n = 0; n < 4; ++n) acc[n] = f64x4{0, 0, 0, 0};
+    double cs = 0.0;
+    for (int64_t p0 = pbeg; p0 < pend; p0 += kCovK) {
+#pragma unroll
+        for (int l = 0; l < 64 * kCovK / 256; ++l) {
+            const int e = t + 256 * l;
+            const int r = e >> 6, cc = e & 63;  // particle p0 + r, column cc of the tile
             const int64_t p = p0 + r;
             const int a = a0 + cc, b = b0 + cc;
-            As[r][cc] = (p < pend && a < d) ? theta[p * d + a] - theta[a] : 0.0;
-            Bs[r][cc] = (p < pend && b < d) ? theta[p * d + b] - theta[b] : 0.0;
+            As[cc][r] = (p < pend && a < d) ? theta[p * d + a] - theta[a] : 0.0;
+            Bs[cc][r] = (p < pend && b < d) ? theta[p * d + b] - theta[b] : 0.0;
         }
         __syncthreads();
+        if (diag && t < 64) {
+#pragma unroll 8
+            for (int r = 0; r < kCovK; ++r) cs += As[t][r];
+        }
 #pragma unroll
-        for (int kk = 0; kk < 16; ++kk) {
-            double av[4], bv[4];
+        for (int s = 0; s < kCovK / 4; ++s) {
+            const double av = As[16 * w + m][4 * s + kg];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) av[i] = As[kk][ty * 4 + i];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) bv[j] = Bs[kk][tx * 4 + j];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                cs[i] += av[i];
-#pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] += av[i] * bv[j];
-            }
+            for (int n = 0; n < 4; ++n)
+                acc[n] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, Bs[16 * n + m][4 * s + kg], acc[n], 0, 0, 0);
         }
         __syncthreads();
     }
+    // element i of tile n: a = a0 + 16 w + kg + 4 i, b = b0 + 16 n + m
     double* out = part + (int64_t)blockIdx.z * d * d;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int a = a0 + ty * 4 + i;
-        if (a >= d) continue;
+    for (int n = 0; n < 4; ++n) {
+        const int b = b0 + 16 * n + m;
+        if (b >= d) continue;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int b = b0 + tx * 4 + j;
-            if (b < d) out[(int64_t)a * d + b] = acc[i][j];
+        for (int i = 0; i < 4; ++i) {
+            const int a = a0 + 16 * w + kg + 4 * i;
+            if (a < d && a <= b) out[(int64_t)a * d + b] = acc[n][i];
         }
-        if (blockIdx.y == 0 && tx == 0) psum[(int64_t)blockIdx.z * d + a] = cs[i];
     }
+    if (diag && t < 64 && a0 + t < d) psum[(int64_t)blockIdx.z * d + a0 + t] = cs;
 }
 
 // Sigma = h V, V = (S - P m m') / (P - 1) with S, m the shifted sums over all
@@ -99,9 +108,10 @@ __global__ __launch_bounds__(256) void cov_final_kernel(const double* __restrict
     const int64_t e = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (e >= (int64_t)d * d) return;
     const int32_t a = (int32_t)(e / d), b = (int32_t)(e % d);
+    const int64_t eu = a <= b ? e : (int64_t)b * d + a;  // the partials hold the upper triangle
     double s = 0.0, sa = 0.0, sb = 0.0;
     for (int32_t q = lane; q < nchunk; q += 64) {
-        s += part[(int64_t)q * d * d + e];
+        s += part[(int64_t)q * d * d + eu];
         sa += psum[(int64_t)q * d + a];
         sb += psum[(int64_t)q * d + b];
     }
@@ -203,51 +213,70 @@ __global__ __launch_bounds__(1024) void trinv_kernel(const double* __restrict__ 
 }
 
 // Out[p][a] = Base[p][a] + alpha * sum_q A[p][q] B[a][q]  (A: P x d, B: d x d).
-// Base may be null (treated as 0).  64 x 64 output tile per block.
+// Base may be null (treated as 0).  64 x 64 output tile per block on the FP64
+// matrix cores (16 x 16 x 4): wave w takes particles 16 w .. 16 w + 15 and
+// the four 16-wide output tiles; A and B are staged in LDS 32 columns at a
+// time, rows padded to 33 doubles.  A lane supplies A[16 w + m][4 s + kg] and
+// B[16 n + m][4 s + kg]; element i of tile n is row 16 w + kg + 4 i, column
+// 16 n + m (the FP64 MFMA layout).
+constexpr int kGemmK = 32;
 __global__ __launch_bounds__(256) void gemm_abt_kernel(const double* __restrict__ A,
                                                        const double* __restrict__ B,
                                                        const double* Base,  // may alias Out
                                                        double* Out, int64_t P,
                                                        int32_t d, double alpha) {
-    __shared__ double As[16][65];
-    __shared__ double Bs[16][65];
-    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    __shared__ double As[64][kGemmK + 1];
+    __shared__ double Bs[64][kGemmK + 1];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int m = lane & 15, kg = lane >> 4;
     const int64_t p0 = (int64_t)blockIdx.x * 64;
     const int a0 = blockIdx.y * 64;
-    double acc[4][4] = {};
-    for (int q0 = 0; q0 < d; q0 += 16) {
-        for (int e = threadIdx.x; e < 16 * 64; e += 256) {
-            const int r = e >> 4, cc = e & 15;
+    f64x4 acc[4];
+#pragma unroll
+    for (int n = 0; n < 4; ++n) acc[n] = f64x4{0, 0, 0, 0};
+    // the next chunk's operands are loaded into registers while this chunk's
+    // MFMAs run
+    double va[64 * kGemmK / 256], vb[64 * kGemmK / 256];
+    auto load = [&](int q0) __attribute__((always_inline)) {
+#pragma unroll
+        for (int l = 0; l < 64 * kGemmK / 256; ++l) {
+            const int e = t + 256 * l;
+            const int r = e / kGemmK, cc = e % kGemmK;
             const int64_t p = p0 + r;
             const int q = q0 + cc;
-            As[cc][r] = (p < P && q < d) ? A[p * d + q] : 0.0;
-            Bs[cc][r] = (a0 + r < d && q < d) ? B[(int64_t)(a0 + r) * d + q] : 0.0;
+            va[l] = (p < P && q < d) ? A[p * d + q] : 0.0;
+            vb[l] = (a0 + r < d && q < d) ? B[(int64_t)(a0 + r) * d + q] : 0.0;
+        }
+    };
+    load(0);
+    for (int q0 = 0; q0 < d; q0 += kGemmK) {
+#pragma unroll
+        for (int l = 0; l < 64 * kGemmK / 256; ++l) {
+            const int e = t + 256 * l;
+            As[e / kGemmK][e % kGemmK] = va[l];
+            Bs[e / kGemmK][e % kGemmK] = vb[l];
         }
         __syncthreads();
+        if (q0 + kGemmK < d) load(q0 + kGemmK);
 #pragma unroll
-        for (int kk = 0; kk < 16; ++kk) {
-            double av[4], bv[4];
+        for (int s = 0; s < kGemmK / 4; ++s) {
+            const double av = As[16 * w + m][4 * s + kg];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) av[i] = As[kk][ty * 4 + i];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) bv[j] = Bs[kk][tx * 4 + j];
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] += av[i] * bv[j];
+            for (int n = 0; n < 4; ++n)
+                acc[n] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, Bs[16 * n + m][4 * s + kg], acc[n], 0, 0, 0);
         }
         __syncthreads();
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int64_t p = p0 + ty * 4 + i;
-        if (p >= P) continue;
+    for (int n = 0; n < 4; ++n) {
+        const int a = a0 + 16 * n + m;
+        if (a >= d) continue;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int a = a0 + tx * 4 + j;
-            if (a >= d) continue;
+        for (int i = 0; i < 4; ++i) {
+            const int64_t p = p0 + 16 * w + kg + 4 * i;
+            if (p >= P) continue;
             const double b = Base ? Base[p * d + a] : 0.0;
-            Out[p * d + a] = b + alpha * acc[i][j];
+            Out[p * d + a] = b + alpha * acc[n][i];
         }
     }
 }
@@ -396,8 +425,6 @@ __global__ __launch_bounds__(64) void trinv_small_kernel(const double* __restric
     for (int r = 0; r < d; ++r)
         if (t < d) W[r * d + t] = Ws[r][t];
 }
-typedef double f64x4 __attribute__((ext_vector_type(4)));
-
 // d <= 64: small contractions on the FP64 matrix cores (16 x 16 x 4).  A
 // workgroup takes 64 consecutive particles (a contiguous block in memory),
 // wave w the tile of particles 16 w .. 16 w + 15 and every 16-wide tile of
