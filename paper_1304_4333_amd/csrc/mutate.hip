@@ -130,6 +130,8 @@ __global__ __launch_bounds__(256) void cov_final_kernel(const double* __restrict
 // column, written back, and the trailing lower triangle is updated with the
 // panel's rank-NB product (every entry a dot product of two LDS rows).  LT
 // receives L^T.  A non-positive or non-finite pivot sets kFlagNotPD and stops.
+// Loops run over (row, column) thread grids (NB or 32 columns wide), so no
+// index is formed by a division.
 template <int NB, int ROWS>
 __global__ __launch_bounds__(1024) void cholesky_blocked_kernel(const double* __restrict__ V, int32_t d,
                                                                 double* __restrict__ L, double* __restrict__ LT,
@@ -137,19 +139,18 @@ __global__ __launch_bounds__(1024) void cholesky_blocked_kernel(const double* __
     __shared__ double Pn[ROWS][NB + 1];
     __shared__ int fail_s;
     const int t = threadIdx.x;
+    const int ty32 = t >> 5, tx32 = t & 31;        // 32 x 32 grid
+    const int tyn = t / NB, txn = t % NB;          // (1024 / NB) x NB grid
+    constexpr int kRowsN = 1024 / NB;
     if (t == 0) fail_s = 0;
-    for (int e = t; e < d * d; e += 1024) {
-        const int r = e / d, q = e % d;
-        L[e] = q <= r ? V[e] : 0.0;
-    }
+    for (int r = ty32; r < d; r += 32)
+        for (int q = tx32; q < d; q += 32) L[(int64_t)r * d + q] = q <= r ? V[(int64_t)r * d + q] : 0.0;
     __syncthreads();
     for (int k = 0; k < d; k += NB) {
         const int kw = min(NB, d - k);  // panel width
         const int m = d - k;            // panel rows k .. d-1
-        for (int e = t; e < m * kw; e += 1024) {
-            const int i = e / kw, jj = e % kw;
-            Pn[i][jj] = L[(int64_t)(k + i) * d + k + jj];
-        }
+        if (txn < kw)
+            for (int i = tyn; i < m; i += kRowsN) Pn[i][txn] = L[(int64_t)(k + i) * d + k + txn];
         __syncthreads();
         for (int jj = 0; jj < kw; ++jj) {
             const double piv = Pn[jj][jj];
@@ -162,35 +163,26 @@ __global__ __launch_bounds__(1024) void cholesky_blocked_kernel(const double* __
             __syncthreads();  // every thread has read the pivot
             for (int i = jj + t; i < m; i += 1024) Pn[i][jj] = (i == jj) ? ljj : Pn[i][jj] * inv;
             __syncthreads();
-            const int nc = kw - jj - 1;  // panel columns right of jj
-            if (nc > 0) {
-                for (int e = t; e < (m - jj - 1) * nc; e += 1024) {
-                    const int i = jj + 1 + e / nc, c = jj + 1 + e % nc;
-                    if (c <= i) Pn[i][c] -= Pn[i][jj] * Pn[c][jj];
-                }
-            }
+            // panel columns right of jj: thread column txn, rows from jj + 1
+            if (txn > jj && txn < kw)
+                for (int i = jj + 1 + tyn; i < m; i += kRowsN)
+                    if (txn <= i) Pn[i][txn] -= Pn[i][jj] * Pn[txn][jj];
             __syncthreads();
         }
-        for (int e = t; e < m * kw; e += 1024) {
-            const int i = e / kw, jj = e % kw;
-            L[(int64_t)(k + i) * d + k + jj] = i >= jj ? Pn[i][jj] : 0.0;
-        }
-        const int n = m - kw;  // trailing rows and columns k + kw .. d-1
-        for (int e = t; e < n * n; e += 1024) {
-            const int i = kw + e / n, c = kw + e % n;  // panel rows of the entry (r, q) = (k + i, k + c)
-            if (c <= i) {
+        if (txn < kw)
+            for (int i = tyn; i < m; i += kRowsN) L[(int64_t)(k + i) * d + k + txn] = i >= txn ? Pn[i][txn] : 0.0;
+        // trailing lower triangle: entry (r, q) = (k + i, k + c), kw <= c <= i < m
+        for (int i = kw + ty32; i < m; i += 32)
+            for (int c = kw + tx32; c <= i; c += 32) {
                 double s = 0.0;
 #pragma unroll 8
                 for (int jj = 0; jj < kw; ++jj) s += Pn[i][jj] * Pn[c][jj];
                 L[(int64_t)(k + i) * d + k + c] -= s;
             }
-        }
         __syncthreads();
     }
-    for (int e = t; e < d * d; e += 1024) {
-        const int r = e / d, q = e % d;
-        LT[(int64_t)q * d + r] = L[e];
-    }
+    for (int r = ty32; r < d; r += 32)
+        for (int q = tx32; q < d; q += 32) LT[(int64_t)q * d + r] = L[(int64_t)r * d + q];
 }
 
 // W = L^-1 (lower triangular), row by row in one workgroup.
