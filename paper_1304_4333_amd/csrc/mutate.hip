@@ -124,19 +124,34 @@ __global__ __launch_bounds__(256) void cov_final_kernel(const double* __restrict
     if (lane == 0) V[e] = h * ((s - sa * sb / (double)P) / (double)(P - 1));
 }
 
-// d > 64: blocked right-looking Cholesky in one workgroup of 1024 threads,
-// in place in L (which starts as the lower triangle of V).  Per panel of NB
-// columns: the panel's rows are staged in LDS, factored there column by
-// column, written back, and the trailing lower triangle is updated with the
-// panel's rank-NB product (every entry a dot product of two LDS rows).  LT
-// receives L^T.  A non-positive or non-finite pivot sets kFlagNotPD and stops.
-// Loops run over (row, column) thread grids (NB or 32 columns wide), so no
-// index is formed by a division.
+// Lane l's value of v, read by every lane of the wave (two 32-bit readlanes).
+__device__ inline double readlane_f64(double v, int l) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, l), hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// d > 64: blocked Cholesky in one workgroup of 1024 threads, in place in L
+// (which starts as the lower triangle of V).  Per panel of NB columns, staged
+// in LDS:
+//   1. one wave factors the NB x NB diagonal block with row i in lane i's
+//      registers, column by column (entry (i, c) is its value minus the
+//      products L_iq L_cq for q = 0 .. c-1 in that order, times 1 / L_cc, and
+//      L_cc = sqrt of the pivot so reduced), other rows' L_cq read by lane;
+//   2. every row below the block is solved against it by one thread, with the
+//      same products in the same order, so each entry gets exactly the
+//      arithmetic of the right-looking column sweep;
+//   3. the panel is written back, rows k .. k+NB-1 of LT = L^T are written
+//      from it, and the trailing lower triangle is updated with the panel's
+//      rank-NB product, each thread on a 2 x 2 set of entries 32 apart.
+// A non-positive or non-finite pivot sets kFlagNotPD and stops.  Loops run
+// over (row, column) thread grids, so no index is formed by a division.
 template <int NB, int ROWS>
 __global__ __launch_bounds__(1024) void cholesky_blocked_kernel(const double* __restrict__ V, int32_t d,
                                                                 double* __restrict__ L, double* __restrict__ LT,
                                                                 unsigned* flags) {
     __shared__ double Pn[ROWS][NB + 1];
+    __shared__ double inv_s[NB];
     __shared__ int fail_s;
     const int t = threadIdx.x;
     const int ty32 = t >> 5, tx32 = t & 31;        // 32 x 32 grid
@@ -152,37 +167,93 @@ __global__ __launch_bounds__(1024) void cholesky_blocked_kernel(const double* __
         if (txn < kw)
             for (int i = tyn; i < m; i += kRowsN) Pn[i][txn] = L[(int64_t)(k + i) * d + k + txn];
         __syncthreads();
-        for (int jj = 0; jj < kw; ++jj) {
-            const double piv = Pn[jj][jj];
-            if (!(piv > 0.0) || !isfinite(piv)) {  // the same value in every thread
-                if (t == 0) atomicOr(flags, kFlagNotPD);
-                return;
+        if (t < 64) {  // 1. the diagonal block, row t in registers
+            double r[NB];
+#pragma unroll
+            for (int q = 0; q < NB; ++q) r[q] = (t < kw && q < kw) ? Pn[t][q] : 0.0;
+            bool fail = false;  // the same in every lane
+#pragma unroll
+            for (int c = 0; c < NB; ++c) {
+                if (c < kw && !fail) {
+                    double x = r[c];
+#pragma unroll
+                    for (int q = 0; q < c; ++q) x -= r[q] * readlane_f64(r[q], c);
+                    const double piv = readlane_f64(x, c);
+                    if (!(piv > 0.0) || !isfinite(piv)) {
+                        fail = true;
+                    } else {
+                        const double ljj = sqrt(piv);
+                        const double inv = 1.0 / ljj;
+                        r[c] = (t == c) ? ljj : x * inv;
+                        if (t == 0) inv_s[c] = inv;
+                    }
+                }
             }
-            const double ljj = sqrt(piv);
-            const double inv = 1.0 / ljj;
-            __syncthreads();  // every thread has read the pivot
-            for (int i = jj + t; i < m; i += 1024) Pn[i][jj] = (i == jj) ? ljj : Pn[i][jj] * inv;
-            __syncthreads();
-            // panel columns right of jj: thread column txn, rows from jj + 1
-            if (txn > jj && txn < kw)
-                for (int i = jj + 1 + tyn; i < m; i += kRowsN)
-                    if (txn <= i) Pn[i][txn] -= Pn[i][jj] * Pn[txn][jj];
-            __syncthreads();
+            if (fail) {
+                if (t == 0) fail_s = 1;
+            } else if (t < kw) {
+#pragma unroll
+                for (int q = 0; q < NB; ++q)
+                    if (q <= t) Pn[t][q] = r[q];
+            }
         }
+        __syncthreads();
+        if (fail_s) {
+            if (t == 0) atomicOr(flags, kFlagNotPD);
+            return;
+        }
+        for (int i = kw + t; i < m; i += 1024) {  // 2. rows below the block
+            double r[NB];
+#pragma unroll
+            for (int q = 0; q < NB; ++q) r[q] = q < kw ? Pn[i][q] : 0.0;
+#pragma unroll
+            for (int c = 0; c < NB; ++c) {
+                if (c < kw) {
+                    double x = r[c];
+#pragma unroll
+                    for (int q = 0; q < c; ++q) x -= r[q] * Pn[c][q];
+                    r[c] = x * inv_s[c];
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < NB; ++q)
+                if (q < kw) Pn[i][q] = r[q];
+        }
+        __syncthreads();
+        // 3. write-back, rows of L^T, trailing update
         if (txn < kw)
             for (int i = tyn; i < m; i += kRowsN) L[(int64_t)(k + i) * d + k + txn] = i >= txn ? Pn[i][txn] : 0.0;
-        // trailing lower triangle: entry (r, q) = (k + i, k + c), kw <= c <= i < m
-        for (int i = kw + ty32; i < m; i += 32)
-            for (int c = kw + tx32; c <= i; c += 32) {
-                double s = 0.0;
+        for (int jj = ty32; jj < kw; jj += 32)
+            for (int q = tx32; q < d; q += 32) {
+                const int i = q - k;  // panel row of L entry (q, k + jj)
+                LT[(int64_t)(k + jj) * d + q] = i >= jj ? Pn[i][jj] : 0.0;
+            }
+        // entries (k + i, k + c), kw <= c <= i < m, as (ib, cb), (ib, cb + 32),
+        // (ib + 32, cb), (ib + 32, cb + 32); rows past the panel are clamped for
+        // the reads and not written
+        for (int ib = kw + ty32; ib < m; ib += 64)
+            for (int cb = kw + tx32; cb <= ib + 32 && cb < m; cb += 64) {
+                const int i1 = min(ib + 32, m - 1), c1 = min(cb + 32, m - 1);
+                double s00 = 0.0, s01 = 0.0, s10 = 0.0, s11 = 0.0;
 #pragma unroll 8
-                for (int jj = 0; jj < kw; ++jj) s += Pn[i][jj] * Pn[c][jj];
-                L[(int64_t)(k + i) * d + k + c] -= s;
+                for (int jj = 0; jj < kw; ++jj) {
+                    const double a0 = Pn[ib][jj], a1 = Pn[i1][jj], b0 = Pn[cb][jj], b1 = Pn[c1][jj];
+                    s00 += a0 * b0;
+                    s01 += a0 * b1;
+                    s10 += a1 * b0;
+                    s11 += a1 * b1;
+                }
+                double* L0 = L + (int64_t)(k + ib) * d + k;
+                if (cb <= ib) L0[cb] -= s00;
+                if (cb + 32 <= ib) L0[cb + 32] -= s01;
+                if (ib + 32 < m) {
+                    double* L1 = L0 + (int64_t)32 * d;
+                    L1[cb] -= s10;
+                    if (cb <= ib) L1[cb + 32] -= s11;
+                }
             }
         __syncthreads();
     }
-    for (int r = ty32; r < d; r += 32)
-        for (int q = tx32; q < d; q += 32) LT[(int64_t)q * d + r] = L[(int64_t)r * d + q];
 }
 
 // W = L^-1 (lower triangular), row by row in one workgroup.
