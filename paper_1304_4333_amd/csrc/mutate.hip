@@ -31,55 +31,90 @@ static_assert(kStatusBytes <= 4096, "the status block fits the small buffer and 
 //   part[chunk][a][b] = sum_p (theta_pa - c_a)(theta_pb - c_b),  a <= b,
 //   psum[chunk][a]    = sum_p (theta_pa - c_a).
 // 64 x 64 (a, b) tile per block on the FP64 matrix cores (16 x 16 x 4 over
-// particles), particles staged in LDS 32 at a time, transposed (rows a, b;
-// padded to 33 doubles).  Only tiles that reach the upper triangle run; the
+// particles), particles staged in LDS 32 at a time in groups of four, laid
+// out so that both the staging stores and the MFMA operand reads are free of
+// bank conflicts.  Only tiles that reach the upper triangle run; the
 // final kernel reads entry (min(a, b), max(a, b)), so V is exactly symmetric.
 // psum comes from the diagonal tiles, summed in particle order.
 constexpr int kCovK = 32;
 typedef double f64x4 __attribute__((ext_vector_type(4)));
-__global__ __launch_bounds__(256) void cov_partial_kernel(const double* __restrict__ theta, int64_t P,
-                                                          int32_t d, int64_t chunk,
+// Grid: one workgroup per (chunk, upper tile), nblk in all, padded to a
+// multiple of 8.  Workgroups are dealt to the 8 XCDs in turn, so workgroup g
+// takes item (g % 8) * (grid / 8) + g / 8: the tiles of one chunk run on one
+// XCD and share its L2, and every XCD gets the same number of items.
+__global__ __launch_bounds__(256, 4) void cov_partial_kernel(const double* __restrict__ theta, int64_t P,
+                                                          int32_t d, int64_t chunk, int64_t nblk,
                                                           double* __restrict__ part,
                                                           double* __restrict__ psum) {
-    __shared__ double As[64][kCovK + 1];
-    __shared__ double Bs[64][kCovK + 1];
-    if (blockIdx.y < blockIdx.x) return;  // the tile lies below the diagonal
+    // [particle group of 4][pair in group][tile column][particle in pair]: a
+    // wave's 16-byte stores are contiguous, and the 16 x 4 operand of one MFMA
+    // is two runs of 32 consecutive doubles
+    __shared__ double As[kCovK / 4][2][64][2];
+    __shared__ double Bs[kCovK / 4][2][64][2];
+    const int64_t item = (int64_t)(blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);
+    if (item >= nblk) return;
+    const int nt = (d + 63) / 64, ntiles = nt * (nt + 1) / 2;
+    const int64_t z = item / ntiles;  // chunk
+    int tx = (int)(item % ntiles), ty = 0;  // tile (tx, ty), tx <= ty, numbered ty (ty + 1) / 2 + tx
+    while (tx > ty) {
+        tx -= ty + 1;
+        ++ty;
+    }
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int m = lane & 15, kg = lane >> 4;
-    const int a0 = blockIdx.x * 64, b0 = blockIdx.y * 64;
-    const bool diag = blockIdx.x == blockIdx.y;
-    const int64_t pbeg = (int64_t)blockIdx.z * chunk;
+    const int a0 = tx * 64, b0 = ty * 64;
+    const bool diag = tx == ty;
+    const int64_t pbeg = z * chunk;
     const int64_t pend = std::min<int64_t>(P, pbeg + chunk);
     f64x4 acc[4];
 #pragma unroll
     for (int n = 0; n < 4; ++n) acc[n] = f64x4{0, 0, 0, 0};
     double cs = 0.0;
+    // thread t stages column t & 63 of the tile for particle groups j0 and
+    // j0 + 4 (j0 = t >> 6); the next chunk is loaded into registers while this
+    // chunk's MFMAs run
+    constexpr int kGroups = kCovK / 4 / 4;  // groups of 4 particles per thread
+    const int cc = t & 63, j0 = t >> 6;
+    const int a = a0 + cc, b = b0 + cc;
+    const double ca = a < d ? theta[a] : 0.0, cb = b < d ? theta[b] : 0.0;
+    double va[4 * kGroups], vb[4 * kGroups];
+    auto load = [&](int64_t p0) __attribute__((always_inline)) {
+#pragma unroll
+        for (int h = 0; h < kGroups; ++h)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int64_t p = p0 + 4 * (j0 + 4 * h) + i;
+                va[4 * h + i] = (p < pend && a < d) ? theta[p * d + a] - ca : 0.0;
+                vb[4 * h + i] = (p < pend && b < d) ? theta[p * d + b] - cb : 0.0;
+            }
+    };
+    load(pbeg);
     for (int64_t p0 = pbeg; p0 < pend; p0 += kCovK) {
 #pragma unroll
-        for (int l = 0; l < 64 * kCovK / 256; ++l) {
-            const int e = t + 256 * l;
-            const int r = e >> 6, cc = e & 63;  // particle p0 + r, column cc of the tile
-            const int64_t p = p0 + r;
-            const int a = a0 + cc, b = b0 + cc;
-            As[cc][r] = (p < pend && a < d) ? theta[p * d + a] - theta[a] : 0.0;
-            Bs[cc][r] = (p < pend && b < d) ? theta[p * d + b] - theta[b] : 0.0;
+        for (int h = 0; h < kGroups; ++h) {
+            const int j = j0 + 4 * h;
+            *reinterpret_cast<double2*>(&As[j][0][cc][0]) = double2{va[4 * h], va[4 * h + 1]};
+            *reinterpret_cast<double2*>(&As[j][1][cc][0]) = double2{va[4 * h + 2], va[4 * h + 3]};
+            *reinterpret_cast<double2*>(&Bs[j][0][cc][0]) = double2{vb[4 * h], vb[4 * h + 1]};
+            *reinterpret_cast<double2*>(&Bs[j][1][cc][0]) = double2{vb[4 * h + 2], vb[4 * h + 3]};
         }
         __syncthreads();
+        if (p0 + kCovK < pend) load(p0 + kCovK);
         if (diag && t < 64) {
 #pragma unroll 8
-            for (int r = 0; r < kCovK; ++r) cs += As[t][r];
+            for (int r = 0; r < kCovK; ++r) cs += As[r >> 2][(r >> 1) & 1][t][r & 1];
         }
 #pragma unroll
         for (int s = 0; s < kCovK / 4; ++s) {
-            const double av = As[16 * w + m][4 * s + kg];
+            const double av = As[s][kg >> 1][16 * w + m][kg & 1];
 #pragma unroll
             for (int n = 0; n < 4; ++n)
-                acc[n] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, Bs[16 * n + m][4 * s + kg], acc[n], 0, 0, 0);
+                acc[n] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, Bs[s][kg >> 1][16 * n + m][kg & 1], acc[n], 0, 0, 0);
         }
         __syncthreads();
     }
     // element i of tile n: a = a0 + 16 w + kg + 4 i, b = b0 + 16 n + m
-    double* out = part + (int64_t)blockIdx.z * d * d;
+    double* out = part + z * d * d;
 #pragma unroll
     for (int n = 0; n < 4; ++n) {
         const int b = b0 + 16 * n + m;
@@ -90,7 +125,7 @@ __global__ __launch_bounds__(256) void cov_partial_kernel(const double* __restri
             if (a < d && a <= b) out[(int64_t)a * d + b] = acc[n][i];
         }
     }
-    if (diag && t < 64 && a0 + t < d) psum[(int64_t)blockIdx.z * d + a0 + t] = cs;
+    if (diag && t < 64 && a0 + t < d) psum[z * d + a0 + t] = cs;
 }
 
 // Sigma = h V, V = (S - P m m') / (P - 1) with S, m the shifted sums over all
@@ -898,14 +933,16 @@ static int mutate_launch(sps_ctx* c, const char* who, double* theta, double* ll,
     const int64_t Pd = P * d;
     const bool small = d <= kSmallD;
     // covariance chunks: d <= 64: at most 64 (one workgroup sums them before
-    // the Cholesky); otherwise about 2048 blocks in flight, at least 64
+    // the Cholesky); otherwise one round of resident blocks, at least 64
     // particles each
     int64_t chunk;
     if (small) {
         chunk = 64;  // one load round per workgroup; the partials are summed by cov_final_kernel
     } else {
-        const int64_t tiles = (int64_t)((d + 63) / 64) * ((d + 63) / 64);
-        const int64_t nch0 = std::max<int64_t>(1, std::min<int64_t>((2048 + tiles - 1) / tiles, (P + 63) / 64));
+        // the upper-triangle tiles times the chunks fill the chip's 1024
+        // resident workgroups (4 per CU at 33 KB of LDS each) in one round
+        const int64_t nt = (d + 63) / 64, tiles = nt * (nt + 1) / 2;
+        const int64_t nch0 = std::max<int64_t>(1, std::min<int64_t>(1024 / tiles, (P + 63) / 64));
         chunk = (((P + nch0 - 1) / nch0) + 15) / 16 * 16;
     }
     const int32_t nchunk = (int32_t)((P + chunk - 1) / chunk);
@@ -973,8 +1010,9 @@ static int mutate_launch(sps_ctx* c, const char* who, double* theta, double* ll,
         if (Sigma_in) {
             SPS_HIP(c, hipMemcpyAsync(Sg, Sigma_in, sizeof(double) * d * d, hipMemcpyDeviceToDevice, c->stream));
         } else {
-            cov_partial_kernel<<<dim3((d + 63) / 64, (d + 63) / 64, nchunk), 256, 0, c->stream>>>(
-                theta, P, d, chunk, part, psum);
+            const int64_t nt = (d + 63) / 64, nblk = nt * (nt + 1) / 2 * nchunk;
+            cov_partial_kernel<<<(unsigned)((nblk + 7) / 8 * 8), 256, 0, c->stream>>>(theta, P, d, chunk, nblk,
+                                                                                   part, psum);
             SPS_CHECK(launched(c, "cov_partial_kernel"));
             cov_final_kernel<<<(unsigned)(((int64_t)d * d + 3) / 4), 256, 0, c->stream>>>(part, psum, nchunk, d,
                                                                                           P, h, Sg, h_dev, stop);
