@@ -316,19 +316,25 @@ __global__ __launch_bounds__(1024) void trinv_kernel(const double* __restrict__ 
 // the four 16-wide output tiles; A and B are staged in LDS 32 columns at a
 // time, rows padded to 33 doubles.  A lane supplies A[16 w + m][4 s + kg] and
 // B[16 n + m][4 s + kg]; element i of tile n is row 16 w + kg + 4 i, column
-// 16 n + m (the FP64 MFMA layout).
+// 16 n + m (the FP64 MFMA layout).  Grid: nblk = (particle tiles) x (output
+// tiles) items, padded to a multiple of 8; workgroup g takes item
+// (g % 8) * (grid / 8) + g / 8, so the output tiles of one particle tile,
+// which read the same rows of A, run together on one XCD.
 constexpr int kGemmK = 32;
 __global__ __launch_bounds__(256) void gemm_abt_kernel(const double* __restrict__ A,
                                                        const double* __restrict__ B,
                                                        const double* Base,  // may alias Out
                                                        double* Out, int64_t P,
-                                                       int32_t d, double alpha) {
+                                                       int32_t d, double alpha, int64_t nblk) {
     __shared__ double As[64][kGemmK + 1];
     __shared__ double Bs[64][kGemmK + 1];
+    const int64_t item = (int64_t)(blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);
+    if (item >= nblk) return;
+    const int na = (d + 63) / 64;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int m = lane & 15, kg = lane >> 4;
-    const int64_t p0 = (int64_t)blockIdx.x * 64;
-    const int a0 = blockIdx.y * 64;
+    const int64_t p0 = item / na * 64;
+    const int a0 = (int)(item % na) * 64;
     f64x4 acc[4];
 #pragma unroll
     for (int n = 0; n < 4; ++n) acc[n] = f64x4{0, 0, 0, 0};
@@ -766,8 +772,8 @@ int gemm_abt(sps_ctx* c, const double* A, const double* B, const double* Base, d
         g.alpha = alpha;
         return gemm_small<GM_PLAIN>(c, g);
     }
-    const dim3 gg((unsigned)((P + 63) / 64), (unsigned)((d + 63) / 64));
-    gemm_abt_kernel<<<gg, 256, 0, c->stream>>>(A, B, Base, Out, P, d, alpha);
+    const int64_t nblk = (P + 63) / 64 * ((d + 63) / 64);
+    gemm_abt_kernel<<<(unsigned)((nblk + 7) / 8 * 8), 256, 0, c->stream>>>(A, B, Base, Out, P, d, alpha, nblk);
     return launched(c, "gemm_abt_kernel");
 }
 
