@@ -321,7 +321,7 @@ __global__ __launch_bounds__(1024) void trinv_kernel(const double* __restrict__ 
 // (g % 8) * (grid / 8) + g / 8, so the output tiles of one particle tile,
 // which read the same rows of A, run together on one XCD.
 constexpr int kGemmK = 32;
-__global__ __launch_bounds__(256) void gemm_abt_kernel(const double* __restrict__ A,
+__global__ __launch_bounds__(256, 4) void gemm_abt_kernel(const double* __restrict__ A,
                                                        const double* __restrict__ B,
                                                        const double* Base,  // may alias Out
                                                        double* Out, int64_t P,
@@ -340,25 +340,30 @@ __global__ __launch_bounds__(256) void gemm_abt_kernel(const double* __restrict_
     for (int n = 0; n < 4; ++n) acc[n] = f64x4{0, 0, 0, 0};
     // the next chunk's operands are loaded into registers while this chunk's
     // MFMAs run
+    // Thread t reads rows t / 32 + 8 l of the chunk at column t % 32; reads
+    // past the last row or column go to the last one (in bounds) and are
+    // replaced by zero, so the loads need no branches.
     double va[64 * kGemmK / 256], vb[64 * kGemmK / 256];
+    const int tr = t / kGemmK, tc = t % kGemmK;
     auto load = [&](int q0) __attribute__((always_inline)) {
+        const int q = q0 + tc;
+        const int qc = min(q, d - 1);
 #pragma unroll
         for (int l = 0; l < 64 * kGemmK / 256; ++l) {
-            const int e = t + 256 * l;
-            const int r = e / kGemmK, cc = e % kGemmK;
-            const int64_t p = p0 + r;
-            const int q = q0 + cc;
-            va[l] = (p < P && q < d) ? A[p * d + q] : 0.0;
-            vb[l] = (a0 + r < d && q < d) ? B[(int64_t)(a0 + r) * d + q] : 0.0;
+            const int64_t p = p0 + tr + 8 * l;
+            const int a = a0 + tr + 8 * l;
+            const double xa = A[std::min<int64_t>(p, P - 1) * d + qc];
+            const double xb = B[(int64_t)min(a, d - 1) * d + qc];
+            va[l] = (p < P && q < d) ? xa : 0.0;
+            vb[l] = (a < d && q < d) ? xb : 0.0;
         }
     };
     load(0);
     for (int q0 = 0; q0 < d; q0 += kGemmK) {
 #pragma unroll
         for (int l = 0; l < 64 * kGemmK / 256; ++l) {
-            const int e = t + 256 * l;
-            As[e / kGemmK][e % kGemmK] = va[l];
-            Bs[e / kGemmK][e % kGemmK] = vb[l];
+            As[tr + 8 * l][tc] = va[l];
+            Bs[tr + 8 * l][tc] = vb[l];
         }
         __syncthreads();
         if (q0 + kGemmK < d) load(q0 + kGemmK);
