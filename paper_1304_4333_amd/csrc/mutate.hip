@@ -78,14 +78,19 @@ __global__ __launch_bounds__(256, 4) void cov_partial_kernel(const double* __res
     const int a = a0 + cc, b = b0 + cc;
     const double ca = a < d ? theta[a] : 0.0, cb = b < d ? theta[b] : 0.0;
     double va[4 * kGroups], vb[4 * kGroups];
+    // reads past the chunk's last particle or the last column go to those
+    // (in bounds) and are replaced by zero, so the loads need no branches
+    const int ac = min(a, d - 1), bc = min(b, d - 1);
     auto load = [&](int64_t p0) __attribute__((always_inline)) {
 #pragma unroll
         for (int h = 0; h < kGroups; ++h)
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int64_t p = p0 + 4 * (j0 + 4 * h) + i;
-                va[4 * h + i] = (p < pend && a < d) ? theta[p * d + a] - ca : 0.0;
-                vb[4 * h + i] = (p < pend && b < d) ? theta[p * d + b] - cb : 0.0;
+                const double* row = theta + std::min<int64_t>(p, pend - 1) * d;
+                const double xa = row[ac], xb = row[bc];
+                va[4 * h + i] = (p < pend && a < d) ? xa - ca : 0.0;
+                vb[4 * h + i] = (p < pend && b < d) ? xb - cb : 0.0;
             }
     };
     load(pbeg);
