@@ -183,7 +183,8 @@ __device__ inline double readlane_f64(double v, int l) {
 //      arithmetic of the right-looking column sweep;
 //   3. the panel is written back, rows k .. k+NB-1 of LT = L^T are written
 //      from it, and the trailing lower triangle is updated with the panel's
-//      rank-NB product, each thread on a 2 x 2 set of entries 32 apart.
+//      rank-NB product on the FP64 matrix cores, one 16 x 16 tile per wave
+//      at a time (tiles on or below the diagonal).
 // A non-positive or non-finite pivot sets kFlagNotPD and stops.  Loops run
 // over (row, column) thread grids, so no index is formed by a division.
 template <int NB, int ROWS>
@@ -268,30 +269,33 @@ __global__ __launch_bounds__(1024) void cholesky_blocked_kernel(const double* __
                 const int i = q - k;  // panel row of L entry (q, k + jj)
                 LT[(int64_t)(k + jj) * d + q] = i >= jj ? Pn[i][jj] : 0.0;
             }
-        // entries (k + i, k + c), kw <= c <= i < m, as (ib, cb), (ib, cb + 32),
-        // (ib + 32, cb), (ib + 32, cb + 32); rows past the panel are clamped for
-        // the reads and not written
-        for (int ib = kw + ty32; ib < m; ib += 64)
-            for (int cb = kw + tx32; cb <= ib + 32 && cb < m; cb += 64) {
-                const int i1 = min(ib + 32, m - 1), c1 = min(cb + 32, m - 1);
-                double s00 = 0.0, s01 = 0.0, s10 = 0.0, s11 = 0.0;
-#pragma unroll 8
-                for (int jj = 0; jj < kw; ++jj) {
-                    const double a0 = Pn[ib][jj], a1 = Pn[i1][jj], b0 = Pn[cb][jj], b1 = Pn[c1][jj];
-                    s00 += a0 * b0;
-                    s01 += a0 * b1;
-                    s10 += a1 * b0;
-                    s11 += a1 * b1;
+        // trailing tiles (bi, bc), bc <= bi, numbered bi (bi + 1) / 2 + bc; rows
+        // past the panel are clamped for the reads and not written.  Lane
+        // (lm, kg) supplies rows i0 + lm and c0 + lm at columns 4 s + kg;
+        // element r of the result is entry (i0 + kg + 4 r, c0 + lm).
+        {
+            const int nb = (m - kw + 15) / 16, ntile = nb * (nb + 1) / 2;
+            const int wave = t >> 6, lane = t & 63, lm = lane & 15, kg = lane >> 4;
+            for (int tile = wave; tile < ntile; tile += 16) {
+                int bc = tile, bi = 0;
+                while (bc > bi) {
+                    bc -= bi + 1;
+                    ++bi;
                 }
-                double* L0 = L + (int64_t)(k + ib) * d + k;
-                if (cb <= ib) L0[cb] -= s00;
-                if (cb + 32 <= ib) L0[cb + 32] -= s01;
-                if (ib + 32 < m) {
-                    double* L1 = L0 + (int64_t)32 * d;
-                    L1[cb] -= s10;
-                    if (cb <= ib) L1[cb + 32] -= s11;
+                const int i0 = kw + 16 * bi, c0 = kw + 16 * bc;
+                const int ra = min(i0 + lm, m - 1), rb = min(c0 + lm, m - 1);
+                f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int s = 0; s < NB / 4; ++s)
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Pn[ra][4 * s + kg], Pn[rb][4 * s + kg], acc, 0, 0, 0);
+                const int c = c0 + lm;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int i = i0 + kg + 4 * r;
+                    if (i < m && c <= i) L[(int64_t)(k + i) * d + k + c] -= acc[r];
                 }
             }
+        }
         __syncthreads();
     }
 }
