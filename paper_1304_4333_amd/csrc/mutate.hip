@@ -178,9 +178,11 @@ __device__ inline double readlane_f64(double v, int l) {
 //      registers, column by column (entry (i, c) is its value minus the
 //      products L_iq L_cq for q = 0 .. c-1 in that order, times 1 / L_cc, and
 //      L_cc = sqrt of the pivot so reduced), other rows' L_cq read by lane;
-//   2. every row below the block is solved against it by one thread, with the
-//      same products in the same order, so each entry gets exactly the
-//      arithmetic of the right-looking column sweep;
+//   2. every row below the block is solved against it, 8 columns at a time
+//      (the earlier columns' products for all entries of the group in
+//      parallel, then the group's own columns row by row), with the same
+//      products in the same order, so each entry gets exactly the arithmetic
+//      of the right-looking column sweep;
 //   3. the panel is written back, rows k .. k+NB-1 of LT = L^T are written
 //      from it, and the trailing lower triangle is updated with the panel's
 //      rank-NB product on the FP64 matrix cores, one 16 x 16 tile per wave
@@ -243,24 +245,35 @@ __global__ __launch_bounds__(1024) void cholesky_blocked_kernel(const double* __
             if (t == 0) atomicOr(flags, kFlagNotPD);
             return;
         }
-        for (int i = kw + t; i < m; i += 1024) {  // 2. rows below the block
-            double r[NB];
+        // 2. rows below the block, 8 columns at a time: first every (row,
+        //    column) entry of the group takes the products of the earlier
+        //    groups' columns (one thread per entry), then each row finishes the
+        //    group's columns in order (one thread per row)
+        for (int cb = 0; cb < kw; cb += 8) {
+            if (cb > 0) {
+                for (int e = t; e < (m - kw) * 8; e += 1024) {
+                    const int i = kw + (e >> 3), c = cb + (e & 7);
+                    if (c < kw) {
+                        double x = Pn[i][c];
+                        for (int q = 0; q < cb; ++q) x -= Pn[i][q] * Pn[c][q];
+                        Pn[i][c] = x;
+                    }
+                }
+                __syncthreads();
+            }
+            for (int i = kw + t; i < m; i += 1024) {
 #pragma unroll
-            for (int q = 0; q < NB; ++q) r[q] = q < kw ? Pn[i][q] : 0.0;
-#pragma unroll
-            for (int c = 0; c < NB; ++c) {
-                if (c < kw) {
-                    double x = r[c];
-#pragma unroll
-                    for (int q = 0; q < c; ++q) x -= r[q] * Pn[c][q];
-                    r[c] = x * inv_s[c];
+                for (int cc = 0; cc < 8; ++cc) {
+                    const int c = cb + cc;
+                    if (c < kw) {
+                        double x = Pn[i][c];
+                        for (int q = cb; q < c; ++q) x -= Pn[i][q] * Pn[c][q];
+                        Pn[i][c] = x * inv_s[c];
+                    }
                 }
             }
-#pragma unroll
-            for (int q = 0; q < NB; ++q)
-                if (q < kw) Pn[i][q] = r[q];
+            __syncthreads();
         }
-        __syncthreads();
         // 3. write-back, rows of L^T, trailing update
         if (txn < kw)
             for (int i = tyn; i < m; i += kRowsN) L[(int64_t)(k + i) * d + k + txn] = i >= txn ? Pn[i][txn] : 0.0;
