@@ -341,13 +341,15 @@ __global__ __launch_bounds__(1024) void trinv_kernel(const double* __restrict__ 
 // 16 n + m (the FP64 MFMA layout).  Grid: nblk = (particle tiles) x (output
 // tiles) items, padded to a multiple of 8; workgroup g takes item
 // (g % 8) * (grid / 8) + g / 8, so the output tiles of one particle tile,
-// which read the same rows of A, run together on one XCD.
+// which read the same rows of A, run together on one XCD.  sq: the per-tile
+// sums of squares (GemmSq), each row's over its 64 columns in tile order,
+// then a butterfly over the 16 lanes that hold the columns.
 constexpr int kGemmK = 32;
 __global__ __launch_bounds__(256, 4) void gemm_abt_kernel(const double* __restrict__ A,
                                                        const double* __restrict__ B,
                                                        const double* Base,  // may alias Out
                                                        double* Out, int64_t P,
-                                                       int32_t d, double alpha, int64_t nblk) {
+                                                       int32_t d, double alpha, int64_t nblk, GemmSq sq) {
     __shared__ double As[64][kGemmK + 1];
     __shared__ double Bs[64][kGemmK + 1];
     const int64_t item = (int64_t)(blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);
@@ -398,16 +400,46 @@ __global__ __launch_bounds__(256, 4) void gemm_abt_kernel(const double* __restri
         }
         __syncthreads();
     }
+    const bool sums = sq.sqb || sq.sqo;  // the same for the whole grid
+    double sb[4] = {0.0, 0.0, 0.0, 0.0}, so[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int n = 0; n < 4; ++n) {
         const int a = a0 + 16 * n + m;
         if (a >= d) continue;
+        const double mua = sq.mu ? sq.mu[a] : 0.0, isa = sq.mu ? sq.isd[a] : 1.0;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int64_t p = p0 + 16 * w + kg + 4 * i;
             if (p >= P) continue;
             const double b = Base ? Base[p * d + a] : 0.0;
-            Out[p * d + a] = b + alpha * acc[n][i];
+            const double o = b + alpha * acc[n][i];
+            if (sq.store) Out[p * d + a] = o;
+            if (sums) {
+                const double fb = sq.mu ? (b - mua) * isa : b;
+                const double fo = sq.mu ? (o - mua) * isa : o;
+                sb[i] += fb * fb;
+                so[i] += fo * fo;
+            }
+        }
+    }
+    if (sums) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+#pragma unroll
+            for (int x = 1; x < 16; x <<= 1) {
+                sb[i] += __shfl_xor(sb[i], x, 64);
+                so[i] += __shfl_xor(so[i], x, 64);
+            }
+        }
+        if (m == 0) {
+            const int64_t j = a0 / 64;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int64_t p = p0 + 16 * w + kg + 4 * i;
+                if (p >= P) continue;
+                if (sq.sqb) sq.sqb[j * P + p] = sb[i];
+                if (sq.sqo) sq.sqo[j * P + p] = so[i];
+            }
         }
     }
 }
@@ -786,9 +818,10 @@ static int gemm_small(sps_ctx* c, const SmallGemm& g) {
 }
 
 int gemm_abt(sps_ctx* c, const double* A, const double* B, const double* Base, double* Out,
-             int64_t P, int32_t d, double alpha) {
+             int64_t P, int32_t d, double alpha, const GemmSq* sq) {
     if (P <= 0 || d <= 0) return SPS_OK;
     if (d <= kSmallD) {
+        if (sq) return fail(c, SPS_ERR_ARG, "gemm_abt: column sums need d > %d", kSmallD);
         SmallGemm g{};
         g.A = A;
         g.B = B;
@@ -800,7 +833,8 @@ int gemm_abt(sps_ctx* c, const double* A, const double* B, const double* Base, d
         return gemm_small<GM_PLAIN>(c, g);
     }
     const int64_t nblk = (P + 63) / 64 * ((d + 63) / 64);
-    gemm_abt_kernel<<<(unsigned)((nblk + 7) / 8 * 8), 256, 0, c->stream>>>(A, B, Base, Out, P, d, alpha, nblk);
+    gemm_abt_kernel<<<(unsigned)((nblk + 7) / 8 * 8), 256, 0, c->stream>>>(A, B, Base, Out, P, d, alpha, nblk,
+                                                                           sq ? *sq : GemmSq{});
     return launched(c, "gemm_abt_kernel");
 }
 
@@ -849,6 +883,17 @@ __global__ void sub_kernel(const double* __restrict__ a, const double* __restric
 // summed here in slice order.
 // z / u null: the normals (MALA) and uniforms are drawn here from Philox
 // streams zstream / zstream + 1 (the values sps_random gives).
+// sq (d > 64, independent prior): the sums of squares for |(theta - mu) / sd|^2,
+// the same at theta', |v|^2 and |z|^2 come as n per-tile partials
+// [j * P + p] from the contractions' epilogues (summed here in tile order)
+// instead of from the rows; a null member keeps the row sum.
+struct AccSq {
+    const double* q0 = nullptr;
+    const double* q1 = nullptr;
+    const double* vv = nullptr;
+    const double* zz = nullptr;
+    int n = 0;
+};
 constexpr int kAccLanes = 16;
 constexpr int kAccPerBlock = 256 / kAccLanes;
 __device__ __forceinline__ double sum16(double v) {
@@ -863,7 +908,7 @@ __global__ __launch_bounds__(256) void accept_kernel(
     const double* __restrict__ u, const double* __restrict__ mu, const double* __restrict__ isd,
     const double* __restrict__ w0, const double* __restrict__ w1,
     int64_t P, int32_t d, int mala, const unsigned* flags, unsigned long long* count,
-    uint64_t seed, uint64_t zstream, int32_t ll2n, const unsigned* stop) {
+    uint64_t seed, uint64_t zstream, int32_t ll2n, const unsigned* stop, AccSq sq) {
     __shared__ unsigned nacc[256 / kAccLanes];
     if (stop && *stop) return;  // the same value for the whole grid: theta, ll, grad stay
     const int sub = threadIdx.x & (kAccLanes - 1);
@@ -888,15 +933,28 @@ __global__ __launch_bounds__(256) void accept_kernel(
             up = u53_to_uniform(ua);
         }
         double q0 = 0.0, q1 = 0.0, vv = 0.0, zz = 0.0;
+        if (sq.q0) {  // lane 0 of the group sums the partials; the others add zeros
+            if (sub == 0) {
+                for (int j = 0; j < sq.n; ++j) {
+                    q0 += sq.q0[(int64_t)j * P + p];
+                    q1 += sq.q1[(int64_t)j * P + p];
+                    if (mala) {
+                        vv += sq.vv[(int64_t)j * P + p];
+                        zz += sq.zz[(int64_t)j * P + p];
+                    }
+                }
+            }
+        } else {
 #pragma unroll 4
-        for (int32_t i = sub; i < d; i += kAccLanes) {
-            const double za = w0 ? w0[p * d + i] : (a[i] - mu[i]) * isd[i];
-            const double zb = w0 ? w1[p * d + i] : (b[i] - mu[i]) * isd[i];
-            q0 += za * za;
-            q1 += zb * zb;
-            if (mala) vv += v[p * d + i] * v[p * d + i];
+            for (int32_t i = sub; i < d; i += kAccLanes) {
+                const double za = w0 ? w0[p * d + i] : (a[i] - mu[i]) * isd[i];
+                const double zb = w0 ? w1[p * d + i] : (b[i] - mu[i]) * isd[i];
+                q0 += za * za;
+                q1 += zb * zb;
+                if (mala) vv += v[p * d + i] * v[p * d + i];
+            }
         }
-        if (mala) {  // |z|^2 by Box-Muller pairs (elements 2 j, 2 j + 1), read or drawn alike
+        if (mala && !sq.zz) {  // |z|^2 by Box-Muller pairs (elements 2 j, 2 j + 1), read or drawn alike
             for (int32_t j = sub; 2 * j < d; j += kAccLanes) {
                 double z0, z1;
                 if (z) {
@@ -982,10 +1040,18 @@ static int mutate_launch(sps_ctx* c, const char* who, double* theta, double* ll,
 
     SPS_CHECK(ensure(c, c->theta2, sizeof(double) * Pd, "proposals"));
     SPS_CHECK(ensure(c, c->ll2, sizeof(double) * P, "proposal log-likelihoods"));
+    // d > 64 with the independent prior: the MH test's sums of squares come
+    // from the contractions' epilogues as na per-tile partials per particle
+    // (in the first P d doubles of pstat, which MALA's v no longer needs)
+    const bool fold = !small && !c->prior_full;
+    const int na = (d + 63) / 64;
     if (mala) {
         SPS_CHECK(ensure(c, c->grad2, sizeof(double) * Pd, "proposal gradients"));
         SPS_CHECK(ensure(c, c->pstat, sizeof(double) * 3 * Pd, "MALA work"));
+    } else if (fold) {
+        SPS_CHECK(ensure(c, c->pstat, sizeof(double) * 2 * na * P, "MH-test partial sums"));
     }
+    AccSq asq{};
     SPS_CHECK(ensure(c, c->chol, sizeof(double) * 4 * (size_t)d * d, "proposal covariance"));
     if (!Sigma_in) {
         SPS_CHECK(ensure(c, c->cov, sizeof(double) * (size_t)nchunk * d * d, "covariance partials"));
@@ -1095,6 +1161,16 @@ static int mutate_launch(sps_ctx* c, const char* who, double* theta, double* ll,
             g.seed = seed;
             g.zstream = stream;
             SPS_CHECK(gemm_small<GM_PLAIN>(c, g));
+        } else if (fold) {
+            GemmSq g{};
+            g.sqb = (double*)c->pstat.p;
+            g.sqo = g.sqb + (size_t)na * P;
+            g.mu = c->prior_mean;
+            g.isd = c->prior_isd;
+            SPS_CHECK(gemm_abt(c, z, L, theta, th2, P, d, 1.0, &g));
+            asq.q0 = g.sqb;
+            asq.q1 = g.sqo;
+            asq.n = na;
         } else {
             SPS_CHECK(gemm_abt(c, z, L, theta, th2, P, d, 1.0));
         }
@@ -1147,12 +1223,28 @@ static int mutate_launch(sps_ctx* c, const char* who, double* theta, double* ll,
         double* uu = v + Pd;
         double* gpi = uu + Pd;
         double* g2 = (double*)c->grad2.p;
+        // partial sums in v's space: |z|^2, |(theta - mu) / sd|^2, the same at
+        // theta', |v|^2 (v itself is not written)
+        const size_t np = (size_t)na * P;
+        GemmSq s0{}, s1{}, s2{};
+        s0.sqb = v;
+        s1.sqb = v + np;
+        s1.sqo = v + 2 * np;
+        s1.mu = c->prior_mean;
+        s1.isd = c->prior_isd;
+        s2.sqo = v + 3 * np;
+        s2.store = 0;
         SPS_CHECK(grad_logpost(grad, theta, R0, gpi));
-        SPS_CHECK(gemm_abt(c, gpi, LT, z, uu, P, d, 0.5));
-        SPS_CHECK(gemm_abt(c, uu, L, theta, th2, P, d, 1.0));
+        SPS_CHECK(gemm_abt(c, gpi, LT, z, uu, P, d, 0.5, &s0));
+        SPS_CHECK(gemm_abt(c, uu, L, theta, th2, P, d, 1.0, &s1));
         SPS_CHECK(loglik_launch(c, th2, P, 0, t, prec, ll2, g2, stop));
         SPS_CHECK(grad_logpost(g2, th2, R1, gpi));
-        SPS_CHECK(gemm_abt(c, gpi, LT, uu, v, P, d, 0.5));
+        SPS_CHECK(gemm_abt(c, gpi, LT, uu, v, P, d, 0.5, &s2));
+        asq.q0 = s1.sqb;
+        asq.q1 = s1.sqo;
+        asq.vv = s2.sqo;
+        asq.zz = s0.sqb;
+        asq.n = na;
     } else {
         double* gpi = (double*)c->pstat.p;
         double* work = gpi + Pd;
@@ -1173,7 +1265,7 @@ static int mutate_launch(sps_ctx* c, const char* who, double* theta, double* ll,
     accept_kernel<<<(unsigned)((P + kAccPerBlock - 1) / kAccPerBlock), 256, 0, c->stream>>>(
         theta, ll, grad, th2, ll2s, mala ? (const double*)c->grad2.p : nullptr, z,
         mala ? (const double*)c->pstat.p : nullptr, u, c->prior_mean, c->prior_isd, R0, R1, P, d,
-        mala ? 1 : 0, flags, count, seed, stream, ll2n, stop);
+        mala ? 1 : 0, flags, count, seed, stream, ll2n, stop, asq);
     SPS_CHECK(launched(c, "accept_kernel"));
     c->has_sigma = true;
     return SPS_OK;
