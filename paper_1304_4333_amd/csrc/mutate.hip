@@ -38,6 +38,19 @@ static_assert(kStatusBytes <= 4096, "the status block fits the small buffer and 
 // psum comes from the diagonal tiles, summed in particle order.
 constexpr int kCovK = 32;
 typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+// Optional outputs of the d > 64 contraction (gemm_abt_kernel): per particle
+// p and 64-column output tile j, the sums over the tile's columns a of
+// f(Base[p][a])^2 (sqb) and f(Out[p][a])^2 (sqo), at [j * P + p];
+// f(x) = (x - mu_a) isd_a when mu is given, else x.  store = 0: Out itself
+// is not written.
+struct GemmSq {
+    double* sqb = nullptr;
+    double* sqo = nullptr;
+    const double* mu = nullptr;
+    const double* isd = nullptr;
+    int store = 1;
+};
 // Grid: one workgroup per (chunk, upper tile), nblk in all, padded to a
 // multiple of 8.  Workgroups are dealt to the 8 XCDs in turn, so workgroup g
 // takes item (g % 8) * (grid / 8) + g / 8: the tiles of one chunk run on one
@@ -817,8 +830,9 @@ static int gemm_small(sps_ctx* c, const SmallGemm& g) {
     return launched(c, "gemm_small_kernel");
 }
 
-int gemm_abt(sps_ctx* c, const double* A, const double* B, const double* Base, double* Out,
-             int64_t P, int32_t d, double alpha, const GemmSq* sq) {
+// gemm_abt with the optional sums of squares (d > 64 only).
+static int gemm_abt_sq(sps_ctx* c, const double* A, const double* B, const double* Base, double* Out,
+                       int64_t P, int32_t d, double alpha, const GemmSq* sq) {
     if (P <= 0 || d <= 0) return SPS_OK;
     if (d <= kSmallD) {
         if (sq) return fail(c, SPS_ERR_ARG, "gemm_abt: column sums need d > %d", kSmallD);
@@ -836,6 +850,11 @@ int gemm_abt(sps_ctx* c, const double* A, const double* B, const double* Base, d
     gemm_abt_kernel<<<(unsigned)((nblk + 7) / 8 * 8), 256, 0, c->stream>>>(A, B, Base, Out, P, d, alpha, nblk,
                                                                            sq ? *sq : GemmSq{});
     return launched(c, "gemm_abt_kernel");
+}
+
+int gemm_abt(sps_ctx* c, const double* A, const double* B, const double* Base, double* Out,
+             int64_t P, int32_t d, double alpha) {
+    return gemm_abt_sq(c, A, B, Base, Out, P, d, alpha, nullptr);
 }
 
 // out[p][i] = theta[p][i] - mu[i]
@@ -1167,7 +1186,7 @@ static int mutate_launch(sps_ctx* c, const char* who, double* theta, double* ll,
             g.sqo = g.sqb + (size_t)na * P;
             g.mu = c->prior_mean;
             g.isd = c->prior_isd;
-            SPS_CHECK(gemm_abt(c, z, L, theta, th2, P, d, 1.0, &g));
+            SPS_CHECK(gemm_abt_sq(c, z, L, theta, th2, P, d, 1.0, &g));
             asq.q0 = g.sqb;
             asq.q1 = g.sqo;
             asq.n = na;
@@ -1235,11 +1254,11 @@ static int mutate_launch(sps_ctx* c, const char* who, double* theta, double* ll,
         s2.sqo = v + 3 * np;
         s2.store = 0;
         SPS_CHECK(grad_logpost(grad, theta, R0, gpi));
-        SPS_CHECK(gemm_abt(c, gpi, LT, z, uu, P, d, 0.5, &s0));
-        SPS_CHECK(gemm_abt(c, uu, L, theta, th2, P, d, 1.0, &s1));
+        SPS_CHECK(gemm_abt_sq(c, gpi, LT, z, uu, P, d, 0.5, &s0));
+        SPS_CHECK(gemm_abt_sq(c, uu, L, theta, th2, P, d, 1.0, &s1));
         SPS_CHECK(loglik_launch(c, th2, P, 0, t, prec, ll2, g2, stop));
         SPS_CHECK(grad_logpost(g2, th2, R1, gpi));
-        SPS_CHECK(gemm_abt(c, gpi, LT, uu, v, P, d, 0.5, &s2));
+        SPS_CHECK(gemm_abt_sq(c, gpi, LT, uu, v, P, d, 0.5, &s2));
         asq.q0 = s1.sqb;
         asq.q1 = s1.sqo;
         asq.vv = s2.sqo;

@@ -210,21 +210,10 @@ int fill(sps_ctx* c, double* p, int64_t n, double v);
 // Philox draws into out (kind 0: 53-bit integers, 1: uniforms, 2: normals).
 int random_fill(sps_ctx* c, int kind, uint64_t seed, uint64_t stream, int64_t count, int32_t d,
                 void* out);
-// Optional outputs of gemm_abt for d > 64: per particle p and 64-column
-// output tile j, the sums over the tile's columns a of f(Base[p][a])^2 (sqb)
-// and f(Out[p][a])^2 (sqo), at [j * P + p]; f(x) = (x - mu_a) isd_a when mu
-// is given, else x.  store = 0: Out itself is not written.
-struct GemmSq {
-    double* sqb = nullptr;
-    double* sqo = nullptr;
-    const double* mu = nullptr;
-    const double* isd = nullptr;
-    int store = 1;
-};
 // Out = Base + alpha A B' with A (P x d), B (d x d), all row-major FP64;
-// Base may be null or alias Out.  sq (d > 64 only): the sums above.
+// Base may be null or alias Out.
 int gemm_abt(sps_ctx* c, const double* A, const double* B, const double* Base, double* Out,
-             int64_t P, int32_t d, double alpha, const GemmSq* sq = nullptr);
+             int64_t P, int32_t d, double alpha);
 // Monitored functions (theta and theta_c' xbar) of P particles into g (P x m).
 int monitor_launch(sps_ctx* c, const double* theta, int64_t P, double* g);
 // Moments of g (J groups of N, m functions) on the device; *out points at
