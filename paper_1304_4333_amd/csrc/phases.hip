@@ -609,20 +609,25 @@ __global__ void gather_kernel(const int32_t* __restrict__ anc, int64_t P, int32_
 }
 
 // ------------------------------------------------------------------ moments
-__global__ void monitor_kernel(const double* __restrict__ theta, int64_t P, int32_t k, int32_t C,
-                               const double* __restrict__ xbar, double* __restrict__ g) {
+// The monitored functions of a particle: theta itself, then theta_c' xbar
+// for c = 0 .. C-2 (products in order i = 0 .. k-1).  One wave per particle:
+// the wave copies theta's row, lanes 0 .. C-2 form the inner products (a flat
+// index over P (d + C - 1) elements would need a 64-bit division per element,
+// and waves holding an inner-product lane would wait on its 50-load chain).
+__global__ __launch_bounds__(256) void monitor_kernel(const double* __restrict__ theta, int64_t P, int32_t k,
+                                                      int32_t C, const double* __restrict__ xbar,
+                                                      double* __restrict__ g) {
     const int32_t d = k * (C - 1), m = d + C - 1;
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= P * m) return;
-    const int64_t p = e / m;
-    const int32_t f = (int32_t)(e % m);
-    if (f < d) {
-        g[e] = theta[p * d + f];
-    } else {
-        const int32_t c = f - d;
+    const int lane = threadIdx.x & 63;
+    const int64_t p = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (p >= P) return;
+    const double* th = theta + p * d;
+    double* gp = g + p * m;
+    for (int32_t f = lane; f < d; f += 64) gp[f] = th[f];
+    for (int32_t c = lane; c < C - 1; c += 64) {
         double s = 0.0;
-        for (int32_t i = 0; i < k; ++i) s += theta[p * d + c * k + i] * xbar[i];
-        g[e] = s;
+        for (int32_t i = 0; i < k; ++i) s += th[c * k + i] * xbar[i];
+        gp[d + c] = s;
     }
 }
 
@@ -957,7 +962,7 @@ namespace sps {
 int monitor_launch(sps_ctx* c, const double* theta, int64_t P, double* g) {
     const int64_t n = P * (c->d + c->C - 1);
     if (n == 0) return SPS_OK;
-    monitor_kernel<<<(unsigned)((n + 255) / 256), 256, 0, c->stream>>>(theta, P, c->k, c->C, c->xbar, g);
+    monitor_kernel<<<(unsigned)((P + 3) / 4), 256, 0, c->stream>>>(theta, P, c->k, c->C, c->xbar, g);
     return launched(c, "monitor_kernel");
 }
 
