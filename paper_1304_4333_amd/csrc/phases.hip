@@ -626,7 +626,8 @@ __global__ __launch_bounds__(256) void monitor_kernel(const double* __restrict__
     for (int32_t f = lane; f < d; f += 64) gp[f] = th[f];
     for (int32_t c = lane; c < C - 1; c += 64) {
         double s = 0.0;
-        for (int32_t i = 0; i < k; ++i) s += th[c * k + i] * xbar[i];
+#pragma unroll 16
+        for (int32_t i = 0; i < k; ++i) s += th[c * k + i] * xbar[i];  // loads issued 16 ahead
         gp[d + c] = s;
     }
 }
