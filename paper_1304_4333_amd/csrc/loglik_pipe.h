@@ -401,8 +401,12 @@ __global__ __launch_bounds__(256) void loglik_pipe_kernel(LoglikArgs a) {
     // followed by a few VALU instructions, so that the matrix pipe and the
     // vector ALU work at the same time.  NBLK blocks; TAIL: another block
     // follows the last one (its reads are issued during the last one).
+    // VALU instructions per tile to spread over the MFMAs.  Measured for the
+    // binary adjoint (ar100, one box, kernel table): 8 per element 3.25-3.35
+    // ms, 16 3.18 ms, 24 3.06-3.17 ms, 32 and 48 no better than 24; twice the
+    // forward counts gave nothing (binary) or lost 2% (C = 6).
     constexpr int kMfmaBlk = PW * NC * 3;  // MFMAs per block
-    constexpr int kValuTile = NC == 1 ? PW * 4 * (GRAD ? 8 : 3) : PW * 4 * (2 * NC + 3 + (GRAD ? 4 * NC + 1 : 0));
+    constexpr int kValuTile = NC == 1 ? PW * 4 * (GRAD ? 24 : 3) : PW * 4 * (2 * NC + 3 + (GRAD ? 4 * NC + 1 : 0));
     auto interleave = [&](auto nblk_c, auto tail_c) __attribute__((always_inline)) {
         constexpr int NBLK = decltype(nblk_c)::value;
         constexpr bool TAIL = decltype(tail_c)::value;
